@@ -1,0 +1,231 @@
+"""Plain FP64 periodic kernel-independent FMM (the oracle's second tier).
+
+This follows Algorithm 2 of the paper (Section 2, near/far split with a
+precomputed periodic M2L operator), with its step d folded into the tree's
+downward pass as the paper suggests at the end of that algorithm's
+discussion:
+
+  Stage 1 (operators, unit box, scaled by 2^l at level l since the kernels
+  are homogeneous of degree -1):
+    * upward / downward check-to-equivalent solves from the SVD A = U S V^T,
+      applied as (V S_eps^+)(U^T q) with S_eps^+ dropping singular values
+      below eps * s_max (Appendix B, the backward-stable solver);
+    * M2M, L2L for the eight octants and M2L for the 316 offsets in
+      [-3,3]^3 \\ [-1,1]^3, from the free-space kernel between surfaces;
+    * the periodic root operator M_root = K^{P,F}(x^{B0,d}, y^{B0,u}) over
+      images with |p|_inf >= 2 (Eq. M2Lsolve's right-hand side).
+  Stage 2 (evaluation):
+    a. S2M at leaves, then M2M and upward solves up to the root density
+       phi^{B0,u} (Algorithm 2, steps a and b);
+    b. q^{B0,d} = M_root phi^{B0,u}  (step c, folded: the root's downward
+       check potential rather than a separate far-field loop at targets);
+    c. V-list M2L and X-list S2L into downward check potentials, L2L and the
+       downward solves from the root to the leaves;
+    d. at leaves: L2T from phi^{B,d}, W-list M2T from phi^{A,u} and the
+       U-list direct sums over adjacent leaves and their periodic images.
+
+Every direct sum goes through the oracle's plain C loop; every dense
+operator product is a numpy matmul.  Test infrastructure only.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+from . import tree as otree
+from . import periodic
+from ._native import direct
+from .kernels import (LAPLACE, STOKES, INNER, OUTER, kdim, unit_surface, kernel_matrix)
+
+EPS = np.finfo(np.float64).eps
+
+
+@dataclass
+class Pinv:
+    Ut: np.ndarray      # [r, kn]
+    VS: np.ndarray      # [kn, r]
+
+    def apply(self, q: np.ndarray) -> np.ndarray:
+        """(V S^+)(U^T q) -- the backward-stable order of Appendix B."""
+        return self.VS @ (self.Ut @ q)
+
+
+def pinv_factors(A: np.ndarray, rel_threshold: float = EPS) -> Pinv:
+    U, s, Vt = np.linalg.svd(A)
+    keep = s > rel_threshold * s[0]
+    return Pinv(Ut=U[:, keep].T.copy(), VS=(Vt[keep].T / s[keep][None, :]).copy())
+
+
+def octant_offset(o: int) -> np.ndarray:
+    return np.array([((o >> 2) & 1) - 0.5, ((o >> 1) & 1) - 0.5, (o & 1) - 0.5]) * 0.5
+
+
+M2L_OFFSETS = [d for d in itertools.product(range(-3, 4), repeat=3) if max(abs(c) for c in d) >= 2]
+
+
+class Operators:
+    """Unit-box operators for one (kernel, periodicity, p)."""
+
+    def __init__(self, kernel: int, mask: int, p: int, rel_threshold: float = EPS):
+        self.kernel, self.mask, self.p = kernel, mask, p
+        self.k = kdim(kernel)
+        u = unit_surface(p)
+        self.n = u.shape[0]
+        self.inner = 0.5 * INNER * u      # unit box centred at 0
+        self.outer = 0.5 * OUTER * u
+        K = lambda X, Y: kernel_matrix(kernel, X, Y)
+        self.up = pinv_factors(K(self.outer, self.inner), rel_threshold)
+        self.down = pinv_factors(K(self.inner, self.outer), rel_threshold)
+        self.m2m = [K(self.outer, octant_offset(o) + 0.5 * self.inner) for o in range(8)]
+        self.l2l = [K(octant_offset(o) + 0.5 * self.inner, self.outer) for o in range(8)]
+        self._m2l: Dict[tuple, np.ndarray] = {}
+        self.mroot = periodic.far_kernel_matrix(kernel, mask, self.inner + 0.5, self.inner + 0.5)
+
+    def m2l(self, delta) -> np.ndarray:
+        delta = tuple(int(c) for c in delta)
+        if delta not in self._m2l:
+            self._m2l[delta] = kernel_matrix(self.kernel, self.inner,
+                                             np.array(delta, dtype=np.float64) + self.inner)
+        return self._m2l[delta]
+
+
+_OPS_CACHE: Dict[tuple, Operators] = {}
+
+
+def operators(kernel: int, mask: int, p: int, rel_threshold: float = EPS) -> Operators:
+    key = (kernel, mask, p, rel_threshold)
+    if key not in _OPS_CACHE:
+        _OPS_CACHE[key] = Operators(kernel, mask, p, rel_threshold)
+    return _OPS_CACHE[key]
+
+
+class KIFMM:
+    """One problem: tree, lists and the evaluation pass."""
+
+    def __init__(self, kernel: int, mask: int, p: int, s: int, points: np.ndarray,
+                 rel_threshold: float = EPS, box_length: float = 1.0):
+        if not periodic.supported(kernel, mask):
+            raise NotImplementedError("unsupported kernel/periodicity")
+        self.kernel, self.mask, self.p, self.s = kernel, mask, p, s
+        self.k = kdim(kernel)
+        self.L = float(box_length)
+        pts = np.asarray(points, dtype=np.float64)
+        self.u = otree.wrap(pts / self.L, mask)
+        self.tree = otree.build_tree(self.u, s)
+        self.lists = otree.build_lists(self.tree, mask)
+        self.ops = operators(kernel, mask, p, rel_threshold)
+        self.sorted_pts = self.u[self.tree.perm]
+
+    # -- geometry helpers
+    def _pts(self, b, shift=(0, 0, 0)):
+        t = self.tree
+        return self.sorted_pts[t.begin[b]:t.end[b]] + np.asarray(shift, dtype=np.float64)
+
+    def _surf(self, b, factor, shift=(0, 0, 0)):
+        t = self.tree
+        return t.centre(b) + np.asarray(shift, dtype=np.float64) + 0.5 * factor * t.edge(b) * unit_surface(self.p)
+
+    def upward(self, dens_sorted: np.ndarray) -> np.ndarray:
+        """phi^{B,u} for every box (dens_sorted: [N, k] in Morton order), level by level."""
+        t, ops, k = self.tree, self.ops, self.k
+        kn = k * ops.n
+        phi_u = np.zeros((t.nbox, kn))
+        for lv in range(t.depth(), -1, -1):
+            boxes = [b for b in range(t.nbox) if t.level[b] == lv]
+            h = 0.5 ** lv
+            Q = np.zeros((len(boxes), kn))
+            for i, b in enumerate(boxes):
+                if t.is_leaf(b):
+                    direct(self.kernel, self._surf(b, OUTER), self._pts(b), dens_sorted[t.begin[b]:t.end[b]], Q[i])
+            for o in range(8):
+                rows = [i for i, b in enumerate(boxes) if t.children[b][o] >= 0]
+                if rows:
+                    ch = [t.children[boxes[i]][o] for i in rows]
+                    Q[rows] += (ops.m2m[o] @ phi_u[ch].T).T / h
+            phi_u[boxes] = h * ops.up.apply(Q.T).T
+        return phi_u
+
+    def evaluate(self, density: np.ndarray, target_leaves: Optional[Sequence[int]] = None,
+                 return_sorted: bool = False):
+        """Potentials at all points (input order), or at the points of the given leaves.
+
+        density: [N, k] (or [N] for Laplace) in input order.
+        With target_leaves, returns {leaf: potentials [count, k] in Morton order};
+        only the downward pass along those leaves' ancestors is computed.
+        """
+        t, ops, k, L = self.tree, self.ops, self.k, self.L
+        dens = np.asarray(density, dtype=np.float64).reshape(-1, k)
+        ds = np.ascontiguousarray(dens[t.perm])
+        phi_u = self.upward(ds)
+        kn = k * ops.n
+        leaves = t.leaves() if target_leaves is None else list(target_leaves)
+        need = set()
+        for b in leaves:
+            while b >= 0 and b not in need:
+                need.add(b)
+                b = t.parent[b]
+        # V-list M2L (grouped by offset) and X-list S2L into downward check potentials
+        qd = {b: np.zeros(kn) for b in need}
+        groups: Dict[tuple, list] = {}
+        for b in need:
+            if b == 0:
+                continue
+            cb = np.array(t.coord[b])
+            for (a, p) in self.lists.V[b]:
+                delta = tuple(int(c) for c in np.array(t.coord[a]) + np.array(p) * (1 << t.level[b]) - cb)
+                groups.setdefault(delta, []).append((b, a))
+        for delta, pairs in groups.items():
+            tb = [b for b, _ in pairs]
+            src = [a for _, a in pairs]
+            scale = np.array([1.0 / t.edge(b) for b in tb])
+            contrib = (ops.m2l(delta) @ phi_u[src].T).T * scale[:, None]
+            for i, b in enumerate(tb):
+                qd[b] += contrib[i]
+        for b in need:
+            for (a, p) in self.lists.X[b]:
+                direct(self.kernel, self._surf(b, INNER), self._pts(a, p), ds[t.begin[a]:t.end[a]], qd[b])
+        # root far field (folded step c), L2L and downward solves
+        phi_d = {}
+        for b in sorted(need, key=lambda b: t.level[b]):
+            h = t.edge(b)
+            q = qd[b]
+            if b == 0:
+                q = q + ops.mroot @ phi_u[0]
+            else:
+                par = t.parent[b]
+                o = t.children[par].index(b)
+                q = q + ops.l2l[o] @ phi_d[par] / t.edge(par)
+            phi_d[b] = h * ops.down.apply(q)
+        out = {}
+        for b in leaves:
+            x = self._pts(b)
+            pot = np.zeros((x.shape[0], k))
+            direct(self.kernel, x, self._surf(b, OUTER), phi_d[b], pot)
+            for (a, p) in self.lists.W[b]:
+                direct(self.kernel, x, self._surf(a, INNER, p), phi_u[a], pot)
+            for (a, p) in self.lists.U[b]:
+                direct(self.kernel, x, self._pts(a), ds[t.begin[a]:t.end[a]], pot, shift=p)
+            out[b] = pot / L
+        if target_leaves is not None:
+            return out
+        res = np.zeros((t.end[0], k))
+        for b, pot in out.items():
+            res[t.begin[b]:t.end[b]] = pot
+        if return_sorted:
+            return res
+        full = np.zeros_like(res)
+        full[t.perm] = res
+        return full
+
+
+def evaluate(kernel: int, mask: int, p: int, s: int, points: np.ndarray, density: np.ndarray,
+             rel_threshold: float = EPS) -> np.ndarray:
+    """Convenience wrapper: [R, N, k] densities -> [R, N, k] potentials."""
+    f = KIFMM(kernel, mask, p, s, points, rel_threshold)
+    dens = np.asarray(density, dtype=np.float64)
+    if dens.ndim == 2:
+        dens = dens[None]
+    return np.stack([f.evaluate(d) for d in dens])
