@@ -1,0 +1,166 @@
+"""Throughput of the periodic KIFMM evaluation pass on one MI355X.
+
+Workload: Stokes velocity kernel, triply periodic unit cube, N = 1,000,000
+uniform random points, i.i.d. N(0,1) forces made force-free, p = 8, at most
+2000 points per leaf (seeded, synthetic).  One step = one pass of the whole
+path over the batch: wrap/validate, Morton sort, octree and lists
+(pkifmm_set_points) and the evaluation (pkifmm_evaluate), inputs and outputs
+resident in HBM.  The mixed-precision form is the headline value; the plain
+float64 form is timed beside it.
+
+Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "targets evaluated/sec, Stokes TP N=1M at 1e-6 rel. L2: mixed-prec vs plain FP64"
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+FLOPS_PER_STOKES_PAIR = 28       # 3 sub, r^2 5, r^-3 2, f.r 5, scale 1, 6 FMA (rsqrt not counted)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_form(pk, torch, pb, precision, steps, warmup):
+    plan = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=precision, flags=pk.PHASE_TIMING)
+    xyz = torch.as_tensor(pb.points, device="cuda")
+    dens = torch.as_tensor(pb.density, device="cuda")
+    out = torch.empty_like(dens)
+    for _ in range(warmup):
+        plan.set_points(xyz)
+        plan.evaluate(dens, out=out)
+    torch.cuda.synchronize()
+    plan.stats()                                  # drop the warm-up phase events
+    t_sp = t_ev = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        plan.set_points(xyz)                      # synchronises (tree topology on the host)
+        b = time.perf_counter()
+        plan.evaluate(dens, out=out)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        t_sp += b - a
+        t_ev += c - b
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    st = plan.stats()
+    res = out.cpu().numpy()
+    plan.close()
+    return {"s_total": total, "s_set_points": t_sp / steps, "s_evaluate": t_ev / steps, "stats": st}, res
+
+
+def cpu_baseline(pb, n_leaves_sample=6):
+    """The oracle (plain FP64 CPU KIFMM) on a bounded sample of the same workload."""
+    from oracle import kifmm
+    t0 = time.perf_counter()
+    f = kifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)     # operators + tree + lists
+    t1 = time.perf_counter()
+    f_ops = t1 - t0
+    # second construction: operators cached, so this is the tree and lists alone
+    t1 = time.perf_counter()
+    f = kifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+    t_tree = time.perf_counter() - t1
+    leaves = f.tree.leaves()
+    rng = np.random.default_rng(1)
+    pick = [leaves[i] for i in sorted(rng.choice(len(leaves), n_leaves_sample, replace=False))]
+    dens = pb.density[0]
+    t2 = time.perf_counter()
+    f.upward(np.ascontiguousarray(dens.reshape(-1, 3)[f.tree.perm]))
+    t_up = time.perf_counter() - t2
+    t3 = time.perf_counter()
+    sub = f.evaluate(dens, target_leaves=pick)       # repeats the upward pass, then the sampled leaves
+    t_sample = time.perf_counter() - t3 - t_up
+    n_sample = sum(f.tree.end[b] - f.tree.begin[b] for b in pick)
+    # whole-job estimate: tree + upward once, downward/leaf work scaled by points
+    t_full = t_tree + t_up + max(t_sample, 0.0) * (pb.n / n_sample)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": pb.n / t_full, "unit": "targets/s", "cores": cores, "kind": "oracle",
+            "sample": (f"tree+lists and the full upward pass timed once ({t_tree + t_up:.1f} s); downward pass "
+                       f"and leaf sums timed on {n_sample} targets in {n_sample and len(pick)} random leaves "
+                       f"({t_sample:.1f} s) and scaled to N; operator precompute ({f_ops:.1f} s) excluded"),
+            "seconds_estimated_full": t_full}, (f, sub)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the distributed design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1705_02043_amd as pk
+    import workloads as W
+    pb = W.stokes_tp_uniform()
+    log(f"workload {pb.name}: N={pb.n} p={pb.p} s={pb.s}")
+    r64, out64 = time_form(pk, torch, pb, pk.FP64, args.steps, args.warmup)
+    log(f"fp64: {r64['s_total'] / args.steps * 1e3:.2f} ms/step")
+    rmx, outmx = time_form(pk, torch, pb, pk.MIXED, args.steps, args.warmup)
+    log(f"mixed: {rmx['s_total'] / args.steps * 1e3:.2f} ms/step")
+    ms_step = rmx["s_total"] / args.steps * 1e3
+    st = rmx["stats"]
+    # dominant kernel: the float32 U-list direct sums (phase "near"), timed with HIP events
+    t_near = st["ms_phase"]["near"] * 1e-3
+    achieved = FLOPS_PER_STOKES_PAIR * st["u_pairs"] / t_near / 1e12
+    roofline = {"bound": "alu", "kernel": "k_p2p<3,true> (U-list near field, float32)",
+                "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                "algorithmic": f"{FLOPS_PER_STOKES_PAIR} flop/pair x {st['u_pairs']} pairs per launch",
+                "ms_per_launch": t_near * 1e3}
+    rel_mx_vs_64 = float(np.linalg.norm(outmx - out64) / np.linalg.norm(out64))
+    rec = {
+        "metric": METRIC,
+        "value": pb.n / (ms_step * 1e-3),
+        "unit": "targets/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "stokes_tp_uniform_n1000000_p8_s2000", "kernel": "stokes", "periodic": "xyz",
+                   "n": pb.n, "p": pb.p, "s": pb.s, "n_rhs": 1, "seed": 2, "precision": "mixed"},
+        "step": "set_points + evaluate",
+        "mixed": {"ms_set_points": rmx["s_set_points"] * 1e3, "ms_evaluate": rmx["s_evaluate"] * 1e3,
+                  "eval_only_targets_per_s": pb.n / rmx["s_evaluate"], "ms_phase": st["ms_phase"]},
+        "fp64": {"value": pb.n / (r64["s_total"] / args.steps), "ms_per_step": r64["s_total"] / args.steps * 1e3,
+                 "ms_set_points": r64["s_set_points"] * 1e3, "ms_evaluate": r64["s_evaluate"] * 1e3,
+                 "eval_only_targets_per_s": pb.n / r64["s_evaluate"], "ms_phase": r64["stats"]["ms_phase"]},
+        "speedup_mixed_vs_fp64": r64["s_total"] / rmx["s_total"],
+        "tree": {k: st[k] for k in ("n_boxes", "n_leaves", "depth", "n_u", "n_v", "n_w", "n_x", "u_pairs")},
+        "accuracy": {"rel_l2_mixed_vs_fp64_gpu": rel_mx_vs_64},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cb, (f, sub) = cpu_baseline(pb)
+        rec["cpu_baseline"] = cb
+        num64 = nummx = den = 0.0
+        for b, ref in sub.items():
+            idx = f.tree.perm[f.tree.begin[b]:f.tree.end[b]]
+            num64 += np.sum((out64[0][idx] - ref) ** 2)
+            nummx += np.sum((outmx[0][idx] - ref) ** 2)
+            den += np.sum(ref ** 2)
+        rec["accuracy"]["rel_l2_vs_oracle_sampled"] = {"fp64": float(np.sqrt(num64 / den)),
+                                                       "mixed": float(np.sqrt(nummx / den)),
+                                                       "targets": int(sum(len(v) for v in sub.values()))}
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

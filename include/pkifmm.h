@@ -1,0 +1,203 @@
+/*
+ * pkifmm.h -- C interface of the periodic kernel-independent FMM evaluation
+ * pass for AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the periodic sum of the paper's problem statement
+ * (Yan & Shelley, "Flexibly imposing periodicity in kernel independent FMM:
+ * a multipole-to-local operator approach", Section 2, Eq. pfmmDef):
+ *
+ *     q_t = sum_{p in P} sum_s K(x_t - (y_s + p L)) phi_s ,
+ *
+ * where P is the lattice of periodic shifts (components only along the
+ * periodic axes), L the edge of the cubic box [0, L)^3, and K one of the
+ * paper's example kernels (Section 2, Eq. kexamples):
+ *     PKIFMM_LAPLACE     K(r) = 1 / (4 pi |r|)                          k = 1
+ *     PKIFMM_STOKES      K(r) = (1/(8 pi)) (I/|r| + r r^T / |r|^3)       k = 3
+ * A pair at exactly zero separation contributes nothing.  Sources are also the
+ * targets.  Periodic sums that only converge conditionally are taken in the
+ * following sense: singly periodic (SP) -- the limit of symmetric image
+ * truncations, which requires zero net density (Section 2, Eq.
+ * compatcondition, neutrality); triply periodic (TP) -- the Ewald sum with
+ * the k = 0 Fourier mode removed (zero mean; Section 3, triply periodic
+ * Stokes, which allows a net force).
+ *
+ * The method is Algorithm 2 of the paper with its step d folded into the
+ * tree: an octree covers the original box and its images with |p|_inf <= 1;
+ * the far field (|p|_inf >= 2) is one precomputed periodic operator applied to
+ * the root's upward equivalent density and added to the root's downward check
+ * potential.
+ *
+ * Conventions for every call:
+ *   * return value: 0 (PKIFMM_OK) or a negative status code below;
+ *   * device pointers are HIP device memory owned by the caller, which must
+ *     keep them alive until the stream work completes; the library never
+ *     frees them;
+ *   * `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *   * a plan is used by one host thread and one stream at a time.
+ */
+#ifndef PKIFMM_H
+#define PKIFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pkifmm_plan pkifmm_plan;
+
+/* kernels */
+#define PKIFMM_LAPLACE 1
+#define PKIFMM_STOKES 2
+
+/* periodic axes (bit mask): 0 = free space, X = singly periodic, X|Y|Z = triply periodic */
+#define PKIFMM_PERIODIC_X 1u
+#define PKIFMM_PERIODIC_Y 2u
+#define PKIFMM_PERIODIC_Z 4u
+
+/* arithmetic of the evaluation pass */
+#define PKIFMM_FP64 0        /* every step in double precision */
+#define PKIFMM_MIXED 1       /* U-list near field (leaf-to-leaf direct sums) in float32 with
+                                float64 partial-sum accumulation; every quantity that feeds a
+                                check-to-equivalent solve (S2M, X, M2M, M2L, L2L, the root far
+                                field) and every use of an equivalent density (W, L2T) in float64 */
+
+/* M2L arithmetic in the mixed mode */
+#define PKIFMM_M2L_FP32 0    /* float32 operands, float32 MFMA accumulation */
+#define PKIFMM_M2L_BF16X3 1  /* each float32 operand split into bf16 hi + lo; three bf16 MFMA
+                                products (hi*hi + hi*lo + lo*hi) with float32 accumulation */
+
+/* status codes */
+#define PKIFMM_OK 0
+#define PKIFMM_ERR_INVALID_ARG -1
+#define PKIFMM_ERR_OUT_OF_BOX -2     /* a coordinate on a non-periodic axis outside [0, L], or not finite */
+#define PKIFMM_ERR_INCOMPATIBLE -3   /* SP input with a non-zero net density */
+#define PKIFMM_ERR_UNSUPPORTED -4    /* kernel x periodicity without a far-field operator */
+#define PKIFMM_ERR_OOM -5
+#define PKIFMM_ERR_HIP -6
+#define PKIFMM_ERR_NO_POINTS -7      /* evaluate before set_points */
+#define PKIFMM_ERR_NUMERICS -8       /* operator construction failed its self-check */
+
+typedef struct {
+    int kernel;                  /* PKIFMM_LAPLACE or PKIFMM_STOKES */
+    unsigned periodic_mask;      /* 0, PKIFMM_PERIODIC_X (any single axis) or X|Y|Z */
+    int p;                       /* surface points per cube edge, 4..16 */
+    int max_pts_per_leaf;        /* s: a box holding more points is split */
+    int precision;               /* PKIFMM_FP64 or PKIFMM_MIXED */
+    int m2l_mode;                /* PKIFMM_M2L_FP32 or PKIFMM_M2L_BF16X3 (mixed only) */
+    double box_length;           /* L > 0 */
+    double svd_rel_threshold;    /* singular values <= this * s_max are dropped; 0 selects 2^-52
+                                    (Appendix B: epsilon_SVD = machine epsilon times s_max) */
+    unsigned flags;              /* PKIFMM_SKIP_CHECKS */
+} pkifmm_config;
+
+#define PKIFMM_SKIP_CHECKS 1u    /* skip the SP neutrality check (no device-to-host read) */
+#define PKIFMM_PHASE_TIMING 2u   /* record HIP events around the phases of every evaluate on its
+                                    stream; pkifmm_get_stats waits for them and reports averages */
+
+/* phases of one evaluation, in stream order */
+#define PKIFMM_PHASE_NEAR 0      /* U-list direct sums (leaf points to leaf points) */
+#define PKIFMM_PHASE_UP 1        /* density permutation, S2M, M2M, upward solves */
+#define PKIFMM_PHASE_M2L 2       /* root far field, V-list M2L and its per-target sums */
+#define PKIFMM_PHASE_DOWN 3      /* X list, L2L, downward solves */
+#define PKIFMM_PHASE_LEAF 4      /* W-list M2T, L2T, output permutation */
+#define PKIFMM_NUM_PHASES 5
+
+typedef struct {
+    int64_t n_points;
+    int n_boxes, n_leaves, depth;
+    int64_t n_u, n_v, n_w, n_x;  /* list entries */
+    int64_t u_pairs;             /* point pairs summed directly over the U lists */
+    int svd_rank_up, svd_rank_down;
+    double ms_set_points;        /* host wall time of the last pkifmm_set_points */
+    double ms_evaluate;          /* host wall time of the last pkifmm_evaluate call (enqueue only
+                                    unless a check synchronised) */
+    int n_timed;                 /* evaluations averaged in ms_phase (PKIFMM_PHASE_TIMING) */
+    double ms_phase[PKIFMM_NUM_PHASES];   /* average device time per phase, HIP events */
+} pkifmm_stats;
+
+/* Fill `cfg` with defaults: Laplace, free space, p = 8, s = 64, FP64, L = 1. */
+int pkifmm_config_default(pkifmm_config *cfg);
+
+/*
+ * Build the operators of Algorithm 2, Stage 1 (Section 2 and Section 3.1):
+ * check-to-equivalent solves from the SVD of A (applied as (V S^+)(U^T q),
+ * Appendix B), M2M/L2L for eight octants, M2L for the 316 offsets, and the
+ * periodic root operator K^{P,F} over images |p|_inf >= 2.  Runs on the
+ * current HIP device; blocking.  *out receives a plan owned by the caller
+ * (release with pkifmm_plan_destroy).
+ */
+int pkifmm_plan_create(const pkifmm_config *cfg, pkifmm_plan **out);
+
+/*
+ * Wrap, validate, Morton-sort the points and build the adaptive octree and
+ * the periodic U/V/W/X lists.
+ *   xyz: device, [n][3] float64, row-major, n >= 0 (copied; may be freed
+ *        after the call returns).
+ * Synchronises `stream` (the tree topology is built on the host).
+ * Errors: OUT_OF_BOX (nothing is kept), INVALID_ARG, OOM, HIP.
+ */
+int pkifmm_set_points(pkifmm_plan *plan, int64_t n, const double *xyz, void *stream);
+
+/*
+ * Evaluate the periodic sum for n_rhs densities on the current points.
+ *   density:   device, [n_rhs][n][k] float64 (k = 1 Laplace, 3 Stokes), input order
+ *   potential: device, [n_rhs][n][k] float64, overwritten, input order
+ * Work is enqueued on `stream`; the call returns after enqueueing unless the
+ * SP neutrality check runs (it reads one reduction back).  The output is
+ * float64 in every precision mode.
+ * Errors: NO_POINTS, INVALID_ARG, INCOMPATIBLE, OOM, HIP.
+ */
+int pkifmm_evaluate(pkifmm_plan *plan, int n_rhs, const double *density, double *potential,
+                    void *stream);
+
+/* Tree and list sizes of the current points and the last call timings.  With
+ * PKIFMM_PHASE_TIMING this waits for the recorded events of every evaluation since
+ * the previous call, reports their per-phase averages and starts a new window. */
+int pkifmm_get_stats(pkifmm_plan *plan, pkifmm_stats *out);
+
+/*
+ * Copy the tree to host arrays for inspection (each may be NULL):
+ *   perm   [n]        int64: sorted position -> input index
+ *   boxes  [nbox][8]  int32: level, ix, iy, iz, begin, end, parent, first child or -1
+ * Boxes are numbered level by level, in Morton order within a level.
+ */
+int pkifmm_get_tree(const pkifmm_plan *plan, int64_t *perm, int32_t *boxes);
+
+/*
+ * Copy one interaction list to host arrays.
+ *   which: 'U', 'V', 'W' or 'X'
+ *   offsets [nbox + 1] int64 (CSR over boxes; boxes without such a list are empty)
+ *   entries [offsets[nbox]][4] int32: source box, shift x, shift y, shift z
+ * Call with entries = NULL to obtain offsets (and so the size) first.
+ */
+int pkifmm_get_list(const pkifmm_plan *plan, char which, int64_t *offsets, int32_t *entries);
+
+/*
+ * Host-only inspection of the topology code (no GPU is touched): build the
+ * octree from Morton keys already sorted by (key, input index) and return one
+ * interaction list, exactly as pkifmm_set_points would.
+ *   sorted_keys: host, [n] 63-bit keys (x bit above y bit above z bit per level)
+ *   which:       'U', 'V', 'W' or 'X'
+ *   n_boxes:     out, number of boxes
+ *   boxes:       NULL or host [n_boxes][8] int32 (same rows as pkifmm_get_tree)
+ *   offsets:     NULL or host [n_boxes + 1] int64
+ *   entries:     NULL or host [offsets[n_boxes]][4] int32 (same rows as pkifmm_get_list)
+ * Call first with the arrays NULL to size them.
+ */
+int pkifmm_host_topology(const uint64_t *sorted_keys, int64_t n, int max_pts_per_leaf, unsigned periodic_mask,
+                         char which, int64_t *n_boxes, int32_t *boxes, int64_t *offsets, int32_t *entries);
+
+/* Release the plan and every buffer it owns.  NULL is accepted. */
+int pkifmm_plan_destroy(pkifmm_plan *plan);
+
+/* Static text for a status code. */
+const char *pkifmm_status_string(int status);
+
+/* Text of the last error on this plan (valid until the next call on it). */
+const char *pkifmm_last_error(const pkifmm_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PKIFMM_H */

@@ -1,0 +1,203 @@
+"""Periodic kernel-independent FMM evaluation pass on MI355X (gfx950).
+
+Thin ctypes binding of the C interface in ``include/pkifmm.h``: every
+``pkifmm_*`` function is exposed under the same name, and :class:`Plan` wraps
+them for torch tensors (device memory and the current stream come from
+PyTorch; all arithmetic runs in the library's HIP kernels).  Importing this
+module does not touch the GPU; using it without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpkifmm.so")
+
+LAPLACE, STOKES = 1, 2
+PERIODIC_X, PERIODIC_Y, PERIODIC_Z = 1, 2, 4
+FP64, MIXED = 0, 1
+M2L_FP32, M2L_BF16X3 = 0, 1
+SKIP_CHECKS = 1
+PHASE_TIMING = 2
+
+OK = 0
+ERR_INVALID_ARG, ERR_OUT_OF_BOX, ERR_INCOMPATIBLE, ERR_UNSUPPORTED = -1, -2, -3, -4
+ERR_OOM, ERR_HIP, ERR_NO_POINTS, ERR_NUMERICS = -5, -6, -7, -8
+
+EXPORTED = ["pkifmm_config_default", "pkifmm_plan_create", "pkifmm_set_points", "pkifmm_evaluate",
+            "pkifmm_get_stats", "pkifmm_get_tree", "pkifmm_get_list", "pkifmm_plan_destroy",
+            "pkifmm_status_string", "pkifmm_last_error", "pkifmm_host_topology"]
+
+
+class pkifmm_config(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int), ("periodic_mask", ctypes.c_uint), ("p", ctypes.c_int),
+                ("max_pts_per_leaf", ctypes.c_int), ("precision", ctypes.c_int), ("m2l_mode", ctypes.c_int),
+                ("box_length", ctypes.c_double), ("svd_rel_threshold", ctypes.c_double),
+                ("flags", ctypes.c_uint)]
+
+
+class pkifmm_stats(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("n_boxes", ctypes.c_int), ("n_leaves", ctypes.c_int),
+                ("depth", ctypes.c_int), ("n_u", ctypes.c_int64), ("n_v", ctypes.c_int64),
+                ("n_w", ctypes.c_int64), ("n_x", ctypes.c_int64), ("u_pairs", ctypes.c_int64),
+                ("svd_rank_up", ctypes.c_int), ("svd_rank_down", ctypes.c_int),
+                ("ms_set_points", ctypes.c_double), ("ms_evaluate", ctypes.c_double),
+                ("n_timed", ctypes.c_int), ("ms_phase", ctypes.c_double * 5)]
+
+PHASES = ["near", "up", "m2l", "down", "leaf"]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_1705_02043_amd/build.py (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        sig = {
+            "pkifmm_config_default": (i32, [ctypes.POINTER(pkifmm_config)]),
+            "pkifmm_plan_create": (i32, [ctypes.POINTER(pkifmm_config), ctypes.POINTER(vp)]),
+            "pkifmm_set_points": (i32, [vp, i64, vp, vp]),
+            "pkifmm_evaluate": (i32, [vp, i32, vp, vp, vp]),
+            "pkifmm_get_stats": (i32, [vp, ctypes.POINTER(pkifmm_stats)]),
+            "pkifmm_get_tree": (i32, [vp, vp, vp]),
+            "pkifmm_get_list": (i32, [vp, ctypes.c_char, vp, vp]),
+            "pkifmm_plan_destroy": (i32, [vp]),
+            "pkifmm_status_string": (ctypes.c_char_p, [i32]),
+            "pkifmm_last_error": (ctypes.c_char_p, [vp]),
+            "pkifmm_host_topology": (i32, [vp, i64, i32, ctypes.c_uint, ctypes.c_char, vp, vp, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def __getattr__(name):
+    if name in EXPORTED:
+        return getattr(lib(), name)
+    raise AttributeError(name)
+
+
+class PkifmmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _check(status: int, plan=None):
+    if status != OK:
+        L = lib()
+        msg = L.pkifmm_status_string(status).decode()
+        if plan is not None:
+            extra = L.pkifmm_last_error(plan).decode()
+            if extra:
+                msg += ": " + extra
+        raise PkifmmError(status, msg)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """One (kernel, periodicity, p, s, precision) set of operators, a point set and its tree."""
+
+    def __init__(self, kernel: int, periodic_mask: int, p: int, max_pts_per_leaf: int,
+                 precision: int = FP64, m2l_mode: int = M2L_FP32, box_length: float = 1.0,
+                 svd_rel_threshold: float = 0.0, flags: int = 0):
+        L = lib()
+        cfg = pkifmm_config()
+        _check(L.pkifmm_config_default(ctypes.byref(cfg)))
+        cfg.kernel, cfg.periodic_mask, cfg.p = kernel, periodic_mask, p
+        cfg.max_pts_per_leaf, cfg.precision, cfg.m2l_mode = max_pts_per_leaf, precision, m2l_mode
+        cfg.box_length, cfg.svd_rel_threshold, cfg.flags = box_length, svd_rel_threshold, flags
+        h = ctypes.c_void_p()
+        _check(L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.k = 1 if kernel == LAPLACE else 3
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pkifmm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_points(self, xyz, stream=None):
+        """xyz: torch float64 CUDA tensor [n, 3] (input order)."""
+        import torch
+        assert xyz.is_cuda and xyz.dtype == torch.float64 and xyz.dim() == 2 and xyz.shape[1] == 3
+        xyz = xyz.contiguous()
+        _check(lib().pkifmm_set_points(self._h, xyz.shape[0], ctypes.c_void_p(xyz.data_ptr()),
+                                       _stream_ptr(stream)), self._h)
+        self.n = xyz.shape[0]
+
+    def evaluate(self, density, out=None, stream=None):
+        """density: float64 CUDA [R, n, k] (or [n, k]); returns potentials of the same shape."""
+        import torch
+        squeeze = density.dim() == 2
+        d = density[None] if squeeze else density
+        assert d.is_cuda and d.dtype == torch.float64 and d.shape[1] == self.n and d.shape[2] == self.k
+        d = d.contiguous()
+        if out is None:
+            out = torch.empty_like(d)
+        _check(lib().pkifmm_evaluate(self._h, d.shape[0], ctypes.c_void_p(d.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), self._h)
+        return out[0] if squeeze else out
+
+    def stats(self) -> dict:
+        st = pkifmm_stats()
+        _check(lib().pkifmm_get_stats(self._h, ctypes.byref(st)), self._h)
+        out = {f: getattr(st, f) for f, _ in pkifmm_stats._fields_ if f != "ms_phase"}
+        out["ms_phase"] = {PHASES[i]: st.ms_phase[i] for i in range(len(PHASES))}
+        return out
+
+    def tree(self):
+        """(perm [n] int64, boxes [nbox, 8] int32) as numpy arrays."""
+        import numpy as np
+        st = self.stats()
+        perm = np.zeros(max(self.n, 1), dtype=np.int64)
+        boxes = np.zeros((st["n_boxes"], 8), dtype=np.int32)
+        _check(lib().pkifmm_get_tree(self._h, perm.ctypes.data, boxes.ctypes.data), self._h)
+        return perm[:self.n], boxes
+
+    def lists(self, which: str):
+        """(offsets [nbox+1] int64, entries [m, 4] int32) of the U, V, W or X list."""
+        import numpy as np
+        st = self.stats()
+        off = np.zeros(st["n_boxes"] + 1, dtype=np.int64)
+        _check(lib().pkifmm_get_list(self._h, which.encode(), off.ctypes.data, None), self._h)
+        ent = np.zeros((max(int(off[-1]), 1), 4), dtype=np.int32)
+        _check(lib().pkifmm_get_list(self._h, which.encode(), off.ctypes.data, ent.ctypes.data), self._h)
+        return off, ent[:int(off[-1])]
+
+
+def host_topology(sorted_keys, max_pts_per_leaf: int, periodic_mask: int, which: str):
+    """Host-only tree + one list from sorted Morton keys: (boxes [nbox, 8], offsets, entries [m, 4])."""
+    import numpy as np
+    keys = np.ascontiguousarray(sorted_keys, dtype=np.uint64)
+    L = lib()
+    nb = ctypes.c_int64()
+    args = (keys.ctypes.data, keys.shape[0], max_pts_per_leaf, periodic_mask, which.encode())
+    _check(L.pkifmm_host_topology(*args, ctypes.byref(nb), None, None, None))
+    boxes = np.zeros((nb.value, 8), dtype=np.int32)
+    off = np.zeros(nb.value + 1, dtype=np.int64)
+    _check(L.pkifmm_host_topology(*args, ctypes.byref(nb), boxes.ctypes.data, off.ctypes.data, None))
+    ent = np.zeros((max(int(off[-1]), 1), 4), dtype=np.int32)
+    _check(L.pkifmm_host_topology(*args, ctypes.byref(nb), boxes.ctypes.data, off.ctypes.data, ent.ctypes.data))
+    return boxes, off, ent[:int(off[-1])]

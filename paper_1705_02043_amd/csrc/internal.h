@@ -1,0 +1,101 @@
+// Internal declarations of the periodic KIFMM library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "pkifmm.h"
+
+namespace pk {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define PK_HIP(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::pk::Error(PKIFMM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kMaxLevel = 21;
+constexpr int kNumM2L = 316;   // offsets in [-3,3]^3 with |delta|_inf >= 2
+
+// Device buffer owned by a plan.
+template <class T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void ensure(size_t count) {
+        if (count <= n && p) return;
+        release();
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            p = nullptr;
+            throw Error(PKIFMM_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
+        n = std::max<size_t>(count, 1);
+    }
+    void upload(const std::vector<T>& h, hipStream_t s) {
+        ensure(h.size());
+        if (!h.empty()) PK_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+};
+
+// ---------------------------------------------------------------- tree (host topology)
+
+struct HostTree {
+    std::vector<int> level, ix, iy, iz, begin, end, parent;
+    std::vector<int> child;       // [nbox][8], -1 absent
+    std::vector<int> leaf_id;     // box -> leaf index or -1
+    std::vector<int> leaves;      // leaf index -> box
+    std::vector<int> level_start; // boxes of level l are [level_start[l], level_start[l+1])
+    int depth = 0;
+    int nbox() const { return (int)level.size(); }
+    bool is_leaf(int b) const {
+        for (int o = 0; o < 8; ++o)
+            if (child[8 * b + o] >= 0) return false;
+        return true;
+    }
+};
+
+struct Entry {
+    int src;      // source box
+    int8_t sx, sy, sz;   // image shift, each in {-1, 0, 1}
+    bool operator<(const Entry& o) const {
+        if (src != o.src) return src < o.src;
+        if (sx != o.sx) return sx < o.sx;
+        if (sy != o.sy) return sy < o.sy;
+        return sz < o.sz;
+    }
+    bool operator==(const Entry& o) const { return src == o.src && sx == o.sx && sy == o.sy && sz == o.sz; }
+};
+
+struct HostLists {
+    // CSR over boxes
+    std::vector<int64_t> u_off, v_off, w_off, x_off;
+    std::vector<Entry> u, v, w, x;
+};
+
+void build_tree_host(const uint64_t* sorted_keys, int64_t n, int s, HostTree& t);
+void build_lists_host(const HostTree& t, unsigned periodic_mask, HostLists& l);
+int m2l_offset_index(int dx, int dy, int dz);   // -> 0..315
+void m2l_offset_vector(int idx, int& dx, int& dy, int& dz);
+
+}  // namespace pk

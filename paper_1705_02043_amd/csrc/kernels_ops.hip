@@ -1,0 +1,297 @@
+// Operator construction (Algorithm 2, Stage 1) in float64 on the device:
+// kernel matrices between surface grids, the periodic far-field kernel
+// K^{P,F} over images |p|_inf >= 2, and the split SVD factors of the
+// check-to-equivalent solves.  Raw kernels throughout (1/|r| and
+// I/|r| + r r^T/|r|^3); the 1/(4 pi), 1/(8 pi) factors are applied to the
+// final potentials.
+//
+// Periodic far-field kernels (the paper leaves the periodic sums to the
+// Ewald literature; the conventions used here):
+//   * singly periodic Laplace along axis e: each image term is regularised by
+//     its monopole value, sum_{|k|>=2} 1/|r - k e| - 1/|k|; images up to
+//     |k| = kNear are summed directly and the rest in closed form from the
+//     Legendre expansion, 2 sum_m P_2m(cos t) |r|^2m zeta(2m+1, kNear+1);
+//   * triply periodic Stokes: Hasimoto's split with the k = 0 mode removed;
+//     real-space part S^R over the far images, Fourier part over k != 0, and
+//     the near images |p|_inf <= 1 removed analytically by subtracting the
+//     smooth part S^F = S - S^R (finite at r = 0, where it equals 4 xi/sqrt(pi) I);
+//   * triply periodic Laplace: Ewald with the k = 0 mode removed, near images
+//     removed the same way.
+#include <cmath>
+#include <vector>
+
+#include "launch.h"
+
+namespace pk {
+
+namespace {
+
+constexpr int kNear = 40;       // SP: images |k| <= kNear summed directly
+constexpr int kLegendre = 12;   // SP: tail terms
+constexpr double kXi = 3.5;     // TP Ewald splitting parameter
+
+__global__ void k_kmat(int kernel, const double* __restrict__ X, int m, const double* __restrict__ Y, int n,
+                       double* __restrict__ out, int64_t ld) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;   // target point
+    int j = blockIdx.y;                               // source point
+    if (i >= m) return;
+    double dx = X[3 * i] - Y[3 * j], dy = X[3 * i + 1] - Y[3 * j + 1], dz = X[3 * i + 2] - Y[3 * j + 2];
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double ri = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
+    if (kernel == PKIFMM_LAPLACE) {
+        out[i + (int64_t)j * ld] = ri;
+        return;
+    }
+    double d[3] = {dx, dy, dz};
+    double ri3 = ri * ri * ri;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            out[(3 * i + a) + (int64_t)(3 * j + b) * ld] = (a == b ? ri : 0.0) + d[a] * d[b] * ri3;
+}
+
+// ---- singly periodic Laplace
+__global__ void k_far_sp_laplace(int axis, const double* __restrict__ X, int m, const double* __restrict__ Y, int n,
+                                 double* __restrict__ out, int64_t ld, const double* __restrict__ zeta) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    if (i >= m) return;
+    double r[3] = {X[3 * i] - Y[3 * j], X[3 * i + 1] - Y[3 * j + 1], X[3 * i + 2] - Y[3 * j + 2]};
+    double acc = 0.0;
+    for (int k = kNear; k >= 2; --k) {   // small terms first
+        double rp[3] = {r[0], r[1], r[2]}, rm[3] = {r[0], r[1], r[2]};
+        rp[axis] -= k;
+        rm[axis] += k;
+        double a = 1.0 / sqrt(rp[0] * rp[0] + rp[1] * rp[1] + rp[2] * rp[2]);
+        double b = 1.0 / sqrt(rm[0] * rm[0] + rm[1] * rm[1] + rm[2] * rm[2]);
+        acc += (a - 1.0 / k) + (b - 1.0 / k);
+    }
+    double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double rn = sqrt(rr);
+    double ct = rn > 0.0 ? r[axis] / rn : 0.0;
+    // Legendre recurrence up to order 2*kLegendre
+    double pm1 = 1.0, p0 = ct, tail = 0.0, rpow = 1.0;
+    for (int l = 1; l < 2 * kLegendre; ++l) {
+        double pn = ((2 * l + 1) * ct * p0 - l * pm1) / (l + 1);
+        pm1 = p0;
+        p0 = pn;
+        if ((l + 1) % 2 == 0) {
+            int mm = (l + 1) / 2;
+            rpow *= rr;
+            tail += 2.0 * pn * rpow * zeta[mm - 1];
+        }
+    }
+    out[i + (int64_t)j * ld] = acc + tail;
+}
+
+// ---- triply periodic Stokes (Hasimoto)
+__device__ void hasimoto_real(const double d[3], double rn, double xi, double S[3][3]) {
+    const double c = 2.0 * xi / sqrt(M_PI);
+    double g = c * exp(-xi * xi * rn * rn);
+    double ec = erfc(xi * rn) / rn;
+    double a = ec - g, b = (ec + g) / (rn * rn);
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) S[p][q] = (p == q ? a : 0.0) + b * d[p] * d[q];
+}
+
+__device__ void hasimoto_smooth(const double d[3], double rn, double xi, double S[3][3]) {
+    const double c = 2.0 * xi / sqrt(M_PI);
+    double x2 = xi * xi * rn * rn;
+    double g = c * exp(-x2);
+    double ef, arr;
+    if (rn < 1e-3) {
+        ef = c * (1.0 - x2 / 3.0 + x2 * x2 / 10.0 - x2 * x2 * x2 / 42.0);
+        arr = c * xi * xi * (2.0 / 3.0 - 0.4 * x2 + x2 * x2 / 7.0);
+    } else {
+        ef = erf(xi * rn) / rn;
+        arr = (ef - g) / (rn * rn);
+    }
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) S[p][q] = (p == q ? ef + g : 0.0) + arr * d[p] * d[q];
+}
+
+__global__ void k_far_tp_stokes(const double* __restrict__ X, int m, const double* __restrict__ Y, int n,
+                                double* __restrict__ out, int64_t ld, const double4* __restrict__ kv, int nk,
+                                double rc, int P) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    if (i >= m) return;
+    const double xi = kXi;
+    double r[3] = {X[3 * i] - Y[3 * j], X[3 * i + 1] - Y[3 * j + 1], X[3 * i + 2] - Y[3 * j + 2]};
+    double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double S[3][3];
+    for (int px = -P; px <= P; ++px)
+        for (int py = -P; py <= P; ++py)
+            for (int pz = -P; pz <= P; ++pz) {
+                double d[3] = {r[0] - px, r[1] - py, r[2] - pz};
+                double rn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                int pin = max(abs(px), max(abs(py), abs(pz)));
+                if (pin <= 1) {
+                    hasimoto_smooth(d, rn, xi, S);
+                    for (int p = 0; p < 3; ++p)
+                        for (int q = 0; q < 3; ++q) A[p][q] -= S[p][q];
+                } else if (rn < rc) {
+                    hasimoto_real(d, rn, xi, S);
+                    for (int p = 0; p < 3; ++p)
+                        for (int q = 0; q < 3; ++q) A[p][q] += S[p][q];
+                }
+            }
+    // Fourier part: kv = (kx, ky, kz, weight) over half the lattice, weight includes the pair
+    double f0 = 0.0, f[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int t = nk - 1; t >= 0; --t) {    // small terms first
+        double4 k = kv[t];
+        double cw = k.w * cos(k.x * r[0] + k.y * r[1] + k.z * r[2]);
+        double kk = k.x * k.x + k.y * k.y + k.z * k.z;
+        double kh[3] = {k.x, k.y, k.z};
+        f0 += cw;
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) f[p][q] += cw * kh[p] * kh[q] / kk;
+    }
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) {
+            double v = A[p][q] + (p == q ? f0 : 0.0) - f[p][q];
+            out[(3 * i + p) + (int64_t)(3 * j + q) * ld] = v;
+        }
+}
+
+// ---- triply periodic Laplace
+__global__ void k_far_tp_laplace(const double* __restrict__ X, int m, const double* __restrict__ Y, int n,
+                                 double* __restrict__ out, int64_t ld, const double4* __restrict__ kv, int nk,
+                                 double rc, int P) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    if (i >= m) return;
+    const double xi = kXi;
+    const double c = 2.0 * xi / sqrt(M_PI);
+    double r[3] = {X[3 * i] - Y[3 * j], X[3 * i + 1] - Y[3 * j + 1], X[3 * i + 2] - Y[3 * j + 2]};
+    double acc = -M_PI / (xi * xi);
+    for (int px = -P; px <= P; ++px)
+        for (int py = -P; py <= P; ++py)
+            for (int pz = -P; pz <= P; ++pz) {
+                double d[3] = {r[0] - px, r[1] - py, r[2] - pz};
+                double rn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                int pin = max(abs(px), max(abs(py), abs(pz)));
+                if (pin <= 1) acc -= rn > 0.0 ? erf(xi * rn) / rn : c;
+                else if (rn < rc) acc += erfc(xi * rn) / rn;
+            }
+    double fs = 0.0;
+    for (int t = nk - 1; t >= 0; --t) {
+        double4 k = kv[t];
+        fs += k.w * cos(k.x * r[0] + k.y * r[1] + k.z * r[2]);
+    }
+    out[i + (int64_t)j * ld] = acc + fs;
+}
+
+__global__ void k_pinv_factors(const double* __restrict__ U, const double* __restrict__ Vt,
+                               const double* __restrict__ S, int kn, int r, double* __restrict__ Ut_r,
+                               double* __restrict__ VS) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;   // 0..kn-1
+    int i = blockIdx.y;                               // 0..r-1
+    if (j >= kn) return;
+    Ut_r[i + (int64_t)j * r] = U[j + (int64_t)i * kn];
+    VS[j + (int64_t)i * kn] = Vt[i + (int64_t)j * kn] / S[i];
+}
+
+// Hurwitz zeta(s, a) = sum_{k>=0} (k + a)^-s for a > 1, s > 1: ten terms summed
+// directly, the rest by Euler-Maclaurin with Bernoulli numbers B2..B12.
+double hurwitz_zeta(double s, double a) {
+    double sum = 0.0;
+    const int M = 10;
+    for (int k = M - 1; k >= 0; --k) sum += std::pow(a + k, -s);
+    double b = a + M;
+    sum += std::pow(b, 1.0 - s) / (s - 1.0) + 0.5 * std::pow(b, -s);
+    const double B[6] = {1.0 / 6, -1.0 / 30, 1.0 / 42, -1.0 / 30, 5.0 / 66, -691.0 / 2730};
+    double fact = 1.0, rising = s;   // (2j)! and s(s+1)...(s+2j-2)
+    double term_pow = std::pow(b, -s - 1.0);
+    for (int j = 1; j <= 6; ++j) {
+        fact *= (2.0 * j - 1.0) * (2.0 * j);
+        sum += B[j - 1] / fact * rising * term_pow;
+        rising *= (s + 2.0 * j - 1.0) * (s + 2.0 * j);
+        term_pow /= b * b;
+    }
+    return sum;
+}
+
+// half of the nonzero k = 2 pi m with |k| <= kmax, weights for the Fourier sums
+std::vector<double> kvectors(double kmax, bool stokes) {
+    std::vector<double> out;
+    int M = (int)std::ceil(kmax / (2.0 * M_PI));
+    const double xi2 = kXi * kXi;
+    for (int a = -M; a <= M; ++a)
+        for (int b = -M; b <= M; ++b)
+            for (int c = -M; c <= M; ++c) {
+                int first = a != 0 ? a : (b != 0 ? b : c);
+                if (first <= 0) continue;
+                double kx = 2 * M_PI * a, ky = 2 * M_PI * b, kz = 2 * M_PI * c;
+                double k2 = kx * kx + ky * ky + kz * kz;
+                if (k2 > kmax * kmax) continue;
+                double e = std::exp(-k2 / (4 * xi2));
+                // two of each +-k pair; 8 pi (Stokes) or 4 pi (Laplace) undoes the kernel factor
+                double w = stokes ? 2.0 * 8.0 * M_PI * (1.0 + k2 / (4 * xi2)) * e / k2 : 2.0 * 4.0 * M_PI * e / k2;
+                out.insert(out.end(), {kx, ky, kz, w});
+            }
+    return out;
+}
+
+}  // namespace
+
+void launch_kmat(int kernel, const double* X, int m, const double* Y, int n, double* out, int64_t ld,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(k_kmat, dim3((m + 127) / 128, n), dim3(128), 0, s, kernel, X, m, Y, n, out, ld);
+    PK_HIP(hipGetLastError());
+}
+
+void launch_far_kmat(int kernel, unsigned mask, const double* X, int m, const double* Y, int n, double* out,
+                     int64_t ld, const double*, hipStream_t s) {
+    int naxes = __builtin_popcount(mask & 7u);
+    dim3 grid((m + 127) / 128, n);
+    if (naxes == 1 && kernel == PKIFMM_LAPLACE) {
+        int axis = mask & 1u ? 0 : (mask & 2u ? 1 : 2);
+        std::vector<double> z(kLegendre);
+        for (int mm = 1; mm <= kLegendre; ++mm) z[mm - 1] = hurwitz_zeta(2.0 * mm + 1.0, kNear + 1.0);
+        DBuf<double> dz;
+        dz.upload(z, s);
+        hipLaunchKernelGGL(k_far_sp_laplace, grid, dim3(128), 0, s, axis, X, m, Y, n, out, ld, dz.p);
+        PK_HIP(hipGetLastError());
+        PK_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    if (naxes == 3) {
+        // real space: erfc(xi rho) < 1e-18 beyond rc; Fourier: (1+k^2/4xi^2) e^{-k^2/4xi^2} < 1e-18 beyond kmax
+        const double rc = 6.3 / kXi;
+        const double kmax = 2.0 * kXi * 6.7;
+        double rmax = 0.0;
+        std::vector<double> hx(3 * (size_t)m), hy(3 * (size_t)n);
+        PK_HIP(hipMemcpyAsync(hx.data(), X, hx.size() * 8, hipMemcpyDeviceToHost, s));
+        PK_HIP(hipMemcpyAsync(hy.data(), Y, hy.size() * 8, hipMemcpyDeviceToHost, s));
+        PK_HIP(hipStreamSynchronize(s));
+        for (int c = 0; c < 3; ++c) {
+            double xlo = 1e300, xhi = -1e300, ylo = 1e300, yhi = -1e300;
+            for (int i = 0; i < m; ++i) { xlo = std::min(xlo, hx[3 * i + c]); xhi = std::max(xhi, hx[3 * i + c]); }
+            for (int j = 0; j < n; ++j) { ylo = std::min(ylo, hy[3 * j + c]); yhi = std::max(yhi, hy[3 * j + c]); }
+            rmax = std::max(rmax, std::max(std::fabs(xhi - ylo), std::fabs(xlo - yhi)));
+        }
+        int P = (int)std::ceil(rmax + rc) + 1;
+        std::vector<double> kv = kvectors(kmax, kernel == PKIFMM_STOKES);
+        DBuf<double> dk;
+        dk.upload(kv, s);
+        int nk = (int)(kv.size() / 4);
+        if (kernel == PKIFMM_STOKES)
+            hipLaunchKernelGGL(k_far_tp_stokes, grid, dim3(128), 0, s, X, m, Y, n, out, ld, (const double4*)dk.p, nk,
+                               rc, P);
+        else
+            hipLaunchKernelGGL(k_far_tp_laplace, grid, dim3(128), 0, s, X, m, Y, n, out, ld, (const double4*)dk.p,
+                               nk, rc, P);
+        PK_HIP(hipGetLastError());
+        PK_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    throw Error(PKIFMM_ERR_UNSUPPORTED, "no far-field operator for this kernel and periodicity");
+}
+
+void launch_pinv_factors(const double* U, const double* Vt, const double* S, int kn, int r, double* Ut_r, double* VS,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_pinv_factors, dim3((kn + 127) / 128, r), dim3(128), 0, s, U, Vt, S, kn, r, Ut_r, VS);
+    PK_HIP(hipGetLastError());
+}
+
+}  // namespace pk

@@ -1,0 +1,170 @@
+// Point-wise kernels: wrap/validate/quantise/Morton keys, radix sort,
+// gathers and density permutations.  All are HBM-bound streaming kernels with
+// one point per thread and coalesced SoA accesses.
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "launch.h"
+
+namespace pk {
+
+namespace {
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1fffff;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+// Periodic axes: w = v - floor(v), a result of exactly 1.0 (from a tiny
+// negative v) becomes 0.0.  Other axes: the closed [0, 1] is accepted.
+// Quantisation: min(floor(w * 2^21), 2^21 - 1), exact in double.
+__global__ void k_keys(const double* __restrict__ xyz, int64_t n, double L, unsigned mask,
+                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, double* __restrict__ u,
+                       int* __restrict__ err) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t q[3];
+    bool bad = false;
+    for (int c = 0; c < 3; ++c) {
+        double v = xyz[3 * i + c] / L;
+        double w;
+        if (mask & (1u << c)) {
+            if (!isfinite(v)) bad = true;
+            w = v - floor(v);
+            if (w >= 1.0) w = 0.0;
+        } else {
+            if (!(v >= 0.0 && v <= 1.0)) bad = true;
+            w = v;
+        }
+        if (bad) w = 0.0;
+        u[c * n + i] = w;
+        double f = floor(w * 2097152.0);
+        q[c] = (uint32_t)fmin(f, 2097151.0);
+    }
+    if (bad) atomicOr(err, 1);
+    keys[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    vals[i] = (uint32_t)i;
+}
+
+__global__ void k_gather_points(const double* __restrict__ u, const uint32_t* __restrict__ perm, int64_t n,
+                                double* __restrict__ xs) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t j = perm[i];
+    xs[i] = u[j];
+    xs[n + i] = u[n + j];
+    xs[2 * n + i] = u[2 * n + j];
+}
+
+// offsets from the leaf centre as a float hi + lo pair (the centre (i + 1/2) 2^-l
+// is dyadic, so the offset itself is exact in double).
+__global__ void k_leaf_offsets(const double* __restrict__ xs, int64_t n, const int* __restrict__ pt_box,
+                               const int* __restrict__ lv, const int* __restrict__ bx, const int* __restrict__ by,
+                               const int* __restrict__ bz, float* __restrict__ off) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = pt_box[i];
+    double h = ldexp(1.0, -lv[b]);
+    double o[3] = {xs[i] - (bx[b] + 0.5) * h, xs[n + i] - (by[b] + 0.5) * h, xs[2 * n + i] - (bz[b] + 0.5) * h};
+    for (int c = 0; c < 3; ++c) {
+        float hi = (float)o[c];
+        off[c * n + i] = hi;
+        off[(3 + c) * n + i] = (float)(o[c] - (double)hi);
+    }
+}
+
+__global__ void k_permute_density(const double* __restrict__ dens, const uint32_t* __restrict__ perm, int64_t n,
+                                  int R, int k, double* __restrict__ ds, float* __restrict__ ds32) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t j = perm[i];
+    for (int r = 0; r < R; ++r)
+        for (int c = 0; c < k; ++c) {
+            double v = dens[((int64_t)r * n + j) * k + c];
+            ds[((int64_t)r * k + c) * n + i] = v;
+            if (ds32) ds32[((int64_t)r * k + c) * n + i] = (float)v;
+        }
+}
+
+__global__ void k_unpermute(const double* __restrict__ pot, const uint32_t* __restrict__ perm, int64_t n, int R,
+                            int k, double scale, double* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t j = perm[i];
+    for (int r = 0; r < R; ++r)
+        for (int c = 0; c < k; ++c)
+            out[((int64_t)r * n + j) * k + c] = scale * pot[((int64_t)r * k + c) * n + i];
+}
+
+// one workgroup per (rhs, component); deterministic tree reduction in LDS
+__global__ void k_density_sums(const double* __restrict__ ds, int64_t n, double* __restrict__ out) {
+    __shared__ double sh[256];
+    const double* src = ds + (int64_t)blockIdx.x * n;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) acc += src[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+void launch_keys(const double* xyz, int64_t n, double L, unsigned mask, uint64_t* keys, uint32_t* vals, double* u,
+                 int* err, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_keys, dim3(nblk(n, 256)), dim3(256), 0, s, xyz, n, L, mask, keys, vals, u, err);
+    PK_HIP(hipGetLastError());
+}
+
+void radix_sort_pairs(uint64_t* kin, uint64_t* kout, uint32_t* vin, uint32_t* vout, int64_t n, DBuf<char>& temp,
+                      hipStream_t s) {
+    if (n == 0) return;
+    size_t bytes = 0;
+    PK_HIP(rocprim::radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, (size_t)n, 0, 63, s));
+    temp.ensure(bytes);
+    PK_HIP(rocprim::radix_sort_pairs(temp.p, bytes, kin, kout, vin, vout, (size_t)n, 0, 63, s));
+}
+
+void launch_gather_points(const double* u, const uint32_t* perm, int64_t n, double* xs, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gather_points, dim3(nblk(n, 256)), dim3(256), 0, s, u, perm, n, xs);
+    PK_HIP(hipGetLastError());
+}
+
+void launch_leaf_offsets(const double* xs, int64_t n, const int* pt_box, const int* lv, const int* bx, const int* by,
+                         const int* bz, float* off, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_leaf_offsets, dim3(nblk(n, 256)), dim3(256), 0, s, xs, n, pt_box, lv, bx, by, bz, off);
+    PK_HIP(hipGetLastError());
+}
+
+void launch_permute_density(const double* dens, const uint32_t* perm, int64_t n, int R, int k, double* ds,
+                            float* ds32, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_permute_density, dim3(nblk(n, 256)), dim3(256), 0, s, dens, perm, n, R, k, ds, ds32);
+    PK_HIP(hipGetLastError());
+}
+
+void launch_unpermute(const double* pot, const uint32_t* perm, int64_t n, int R, int k, double scale, double* out,
+                      hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_unpermute, dim3(nblk(n, 256)), dim3(256), 0, s, pot, perm, n, R, k, scale, out);
+    PK_HIP(hipGetLastError());
+}
+
+void launch_density_sums(const double* ds, int64_t n, int R, int k, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_density_sums, dim3(R * k), dim3(256), 0, s, ds, n, out);
+    PK_HIP(hipGetLastError());
+}
+
+}  // namespace pk

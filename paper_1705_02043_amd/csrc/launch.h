@@ -1,0 +1,109 @@
+// Kernel launchers shared between the schedule (plan.hip) and the kernel files.
+#pragma once
+
+#include "internal.h"
+
+namespace pk {
+
+// ---- points and densities (kernels_points.hip)
+// Coordinates are divided by L, periodic axes wrapped into [0,1), the others checked to lie in [0,1]; then quantised and
+// interleaved.  xyz: [n][3] input order.  Writes keys, values
+// (= input index) and the wrapped coordinates u [3][n] (SoA).  Bit 0 of *err is
+// set for a coordinate outside the box or not finite.
+void launch_keys(const double* xyz, int64_t n, double L, unsigned mask, uint64_t* keys,
+                 uint32_t* vals, double* u, int* err, hipStream_t s);
+// Stable radix sort of (key, index) pairs; temp storage is grown as needed.
+void radix_sort_pairs(uint64_t* keys_in, uint64_t* keys_out, uint32_t* vals_in, uint32_t* vals_out,
+                      int64_t n, DBuf<char>& temp, hipStream_t s);
+// Sorted SoA coordinates xs[3][n] = u[:, perm]; per-point float offsets from the
+// centre of the point's leaf (pt_box[sorted index] gives the leaf box).
+void launch_gather_points(const double* u, const uint32_t* perm, int64_t n, double* xs, hipStream_t s);
+void launch_leaf_offsets(const double* xs, int64_t n, const int* pt_box, const int* box_level,
+                         const int* box_ix, const int* box_iy, const int* box_iz, float* off, hipStream_t s);
+// density [R][n][k] input order -> ds [R][k][n] sorted (double) and optionally float
+void launch_permute_density(const double* dens, const uint32_t* perm, int64_t n, int R, int k,
+                            double* ds, float* ds32, hipStream_t s);
+// pot_sorted [R][k][n] -> out [R][n][k] input order, times scale
+void launch_unpermute(const double* pot, const uint32_t* perm, int64_t n, int R, int k, double scale,
+                      double* out, hipStream_t s);
+// per-RHS, per-component sums of the sorted densities (neutrality check): out [R*k]
+void launch_density_sums(const double* ds, int64_t n, int R, int k, double* out, hipStream_t s);
+
+// ---- direct interactions (kernels_p2p.hip)
+struct Seg {         // one source segment
+    int kind;        // 0: points of box, 1: inner surface (phi_u), 2: outer surface (phi_d)
+    int box;
+    int shift;       // (sx+1)*9 + (sy+1)*3 + (sz+1)
+};
+struct Work {        // one workgroup's targets and its segment range
+    int tbox;        // target box
+    int tkind;       // 0: points, 1: inner surface (downward check), 2: outer surface (upward check)
+    int t0, tcount;  // first target (sorted index for points, surface index for surfaces) and count
+    int seg0, seg1;
+};
+struct P2PArgs {
+    int kernel;          // 1 Laplace, 2 Stokes
+    int n_surf;          // surface points per box
+    int R;               // right-hand sides
+    int64_t n;           // points
+    const double* xs;    // [3][n] sorted absolute coordinates
+    const float* off;    // [6][n] float hi (x,y,z) then lo (x,y,z) offsets from the leaf centre (mixed)
+    const double* ds;    // [R][k][n] sorted densities
+    const float* ds32;   // [R][k][n] (mixed)
+    const double* phi_u; // [nbox*R][kn]
+    const double* phi_d;
+    const int* box_level;
+    const int* box_ix;
+    const int* box_iy;
+    const int* box_iz;
+    const int* box_begin;
+    const int* box_end;
+    const double* usurf; // [n_surf][3] unit surface grid on [-1,1]^3
+    const Seg* segs;
+    const Work* work;
+    int n_work;
+    double* out_pts;     // [R][k][n] sorted potentials (targets = points)
+    int accumulate_pts;  // add into out_pts instead of storing
+    double* out_surf;    // [nbox*R][kn] check potentials (targets = surfaces), accumulated
+};
+void launch_p2p(const P2PArgs& a, bool mixed, hipStream_t s);
+
+// ---- dense operator products (kernels_gemm.hip)
+struct Tile {
+    int op;       // operator index
+    int col0;     // first entry in the column lists
+    int ncol;     // columns in this tile (<= 64)
+    int row0;     // first row
+};
+struct GemmArgs {
+    const double* ops;    // operator g at ops + g * op_stride, column-major M x K
+    int64_t op_stride;
+    int M, K;
+    const double* B;      // column j at B + j * ldb
+    int64_t ldb;
+    double* C;            // column j at C + j * ldc
+    int64_t ldc;
+    const Tile* tiles;
+    int n_tiles;
+    const int* in_col;
+    const int* out_col;
+    const double* scale;
+    int accumulate;       // C = scale*Op*B (+ C)
+};
+void launch_gemm(const GemmArgs& a, hipStream_t s);
+// q[b] += sum_{e in [off[b], off[b+1])} temp[e]  over R columns each; rows kn
+void launch_segment_reduce(const double* temp, const int64_t* off, const int* boxes, int nboxes,
+                           int R, int kn, double* q, hipStream_t s);
+
+// ---- operator construction (kernels_ops.hip), raw kernels (no 1/(4pi), 1/(8pi))
+// out[(k*i+a) + (k*j+b)*ld] = K(X_i - Y_j)_{ab}; X, Y: [m][3], [n][3]
+void launch_kmat(int kernel, const double* X, int m, const double* Y, int n, double* out, int64_t ld,
+                 hipStream_t s);
+// far-field periodic kernel over images |p|_inf >= 2 between point sets (same layout)
+void launch_far_kmat(int kernel, unsigned mask, const double* X, int m, const double* Y, int n, double* out,
+                     int64_t ld, const double* host_zeta, hipStream_t s);
+// small helpers for the SVD factors
+void launch_pinv_factors(const double* U, const double* Vt, const double* S, int kn, int r, double* Ut_r,
+                         double* VS, hipStream_t s);
+
+}  // namespace pk

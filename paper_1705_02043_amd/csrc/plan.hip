@@ -1,0 +1,791 @@
+// The C interface: plan construction (operators), point set-up (tree and
+// lists) and the evaluation schedule of the periodic KIFMM.
+//
+// Evaluation schedule (Algorithm 2, Stage 2, with step d folded into the
+// downward pass; all arrays Morton-ordered, one column of kn = k n values per
+// box and right-hand side):
+//   1. permute densities into Morton order
+//   2. S2M at the leaves (direct sums to the upward check surface)
+//   3. upward pass, deepest level first: M2M from children, then the upward
+//      check-to-equivalent solve phi = h (V S^+)(U^T q)
+//   4. root far field: q^{B0,d} += M_root phi^{B0,u}
+//   5. V-list M2L for every level at once (grouped by offset, summed per
+//      target in a fixed order) and X-list direct sums to downward check
+//      surfaces
+//   6. downward pass, root first: L2L from the parent, downward solve
+//   7. leaves: U-list direct sums, W-list M2T and L2T into the potentials
+//   8. un-permute and apply 1/(4 pi) or 1/(8 pi) and 1/L
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "launch.h"
+
+using namespace pk;
+
+namespace {
+
+constexpr double kInnerHalf = 0.525;   // half edge of the 1.05 cube, in box edges
+constexpr double kOuterHalf = 1.475;   // half edge of the 2.95 cube
+
+std::vector<double> unit_surface(int p) {
+    std::vector<double> u;
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j)
+            for (int k = 0; k < p; ++k) {
+                bool face = i == 0 || i == p - 1 || j == 0 || j == p - 1 || k == 0 || k == p - 1;
+                if (!face) continue;
+                u.push_back(-1.0 + 2.0 * i / (p - 1));
+                u.push_back(-1.0 + 2.0 * j / (p - 1));
+                u.push_back(-1.0 + 2.0 * k / (p - 1));
+            }
+    return u;
+}
+
+std::vector<double> scaled(const std::vector<double>& u, double f, double cx, double cy, double cz) {
+    std::vector<double> o(u.size());
+    for (size_t i = 0; i < u.size(); i += 3) {
+        o[i] = cx + f * u[i];
+        o[i + 1] = cy + f * u[i + 1];
+        o[i + 2] = cz + f * u[i + 2];
+    }
+    return o;
+}
+
+struct Gemm {      // host-side description of one grouped GEMM launch
+    std::vector<Tile> tiles;
+    std::vector<int> in, out;
+    std::vector<double> scale;
+};
+
+struct GemmRange {
+    int tile0 = 0, ntile = 0;
+};
+
+struct SegRange {
+    int work0 = 0, nwork = 0;
+};
+
+}  // namespace
+
+struct pkifmm_plan {
+    pkifmm_config cfg{};
+    int k = 1, n_surf = 0, kn = 0;
+    int r_up = 0, r_dn = 0;
+    std::string last_error;
+    hipStream_t setup_stream = nullptr;
+
+    // operators (device, float64, column-major kn x kn unless noted)
+    DBuf<double> usurf;                 // [n][3]
+    DBuf<double> up_Ut, up_VS, dn_Ut, dn_VS;   // U^T: r x kn, V S^+: kn x r
+    DBuf<double> m2m, l2l;              // [8][kn*kn]
+    DBuf<double> m2l;                   // [316][kn*kn]
+    DBuf<double> mroot;                 // [kn*kn]
+
+    // points and tree
+    int64_t n = 0;
+    bool have_points = false;
+    HostTree tree;
+    HostLists lists;
+    std::vector<int64_t> perm_host;
+    DBuf<uint64_t> keys_a, keys_b;
+    DBuf<uint32_t> vals_a, perm;
+    DBuf<double> u_wrapped, xs;
+    DBuf<float> off;
+    DBuf<char> sort_temp;
+    DBuf<int> err_flag;
+    DBuf<int> b_level, b_ix, b_iy, b_iz, b_begin, b_end, pt_box;
+    DBuf<int64_t> v_off;
+    DBuf<int> v_targets;
+    int n_v_targets = 0;
+
+    // work lists for the current R
+    int R_built = -1;
+    std::vector<Seg> segs_h;
+    std::vector<Work> work_h;
+    SegRange w_s2m, w_x, w_leaf_u, w_leaf_far;
+    DBuf<Seg> segs;
+    DBuf<Work> work;
+    std::vector<GemmRange> g_m2m[8];    // per level
+    std::vector<GemmRange> g_up1, g_up2, g_dn1, g_dn2, g_l2l;   // per level
+    GemmRange g_root, g_m2l;
+    DBuf<Tile> tiles;
+    DBuf<int> col_in, col_out;
+    DBuf<double> col_scale;
+
+    // workspace
+    DBuf<double> ds, q_u, phi_u, q_d, phi_d, tmp, m2l_tmp, pot, sums;
+    DBuf<float> ds32;
+
+    pkifmm_stats stats{};
+    std::vector<std::vector<hipEvent_t>> pending_events;   // per timed evaluation: NUM_PHASES + 1
+};
+
+namespace {
+
+int fail(pkifmm_plan* p, const Error& e) {
+    if (p) p->last_error = e.what();
+    return e.code;
+}
+
+void check_config(const pkifmm_config& c) {
+    if (c.kernel != PKIFMM_LAPLACE && c.kernel != PKIFMM_STOKES) throw Error(PKIFMM_ERR_INVALID_ARG, "kernel");
+    if (c.periodic_mask & ~7u) throw Error(PKIFMM_ERR_INVALID_ARG, "periodic_mask");
+    if (c.p < 4 || c.p > 16) throw Error(PKIFMM_ERR_INVALID_ARG, "p must be in [4, 16]");
+    if (c.max_pts_per_leaf < 1) throw Error(PKIFMM_ERR_INVALID_ARG, "max_pts_per_leaf");
+    if (c.precision != PKIFMM_FP64 && c.precision != PKIFMM_MIXED) throw Error(PKIFMM_ERR_INVALID_ARG, "precision");
+    if (!(c.box_length > 0.0) || !std::isfinite(c.box_length)) throw Error(PKIFMM_ERR_INVALID_ARG, "box_length");
+    if (c.svd_rel_threshold < 0.0 || c.svd_rel_threshold >= 1.0) throw Error(PKIFMM_ERR_INVALID_ARG, "svd_rel_threshold");
+    int naxes = __builtin_popcount(c.periodic_mask);
+    if (naxes == 2) throw Error(PKIFMM_ERR_UNSUPPORTED, "doubly periodic far field not available");
+    if (naxes == 1 && c.kernel == PKIFMM_STOKES) throw Error(PKIFMM_ERR_UNSUPPORTED, "singly periodic Stokes far field not available");
+}
+
+// SVD of a kn x kn matrix on the device (rocSOLVER, one-sided bidiagonal QR);
+// drops singular values <= thr * s_max and stores U^T (r x kn) and V S^+ (kn x r).
+int pinv_build(rocblas_handle h, hipStream_t s, const double* A_dev, int kn, double thr, DBuf<double>& Ut,
+               DBuf<double>& VS) {
+    DBuf<double> A, S, U, Vt, E;
+    DBuf<rocblas_int> info;
+    A.ensure((size_t)kn * kn);
+    S.ensure(kn);
+    U.ensure((size_t)kn * kn);
+    Vt.ensure((size_t)kn * kn);
+    E.ensure(kn);
+    info.ensure(1);
+    PK_HIP(hipMemcpyAsync(A.p, A_dev, sizeof(double) * kn * kn, hipMemcpyDeviceToDevice, s));
+    rocblas_status st = rocsolver_dgesvd(h, rocblas_svect_all, rocblas_svect_all, kn, kn, A.p, kn, S.p, U.p, kn, Vt.p,
+                                         kn, E.p, rocblas_outofplace, info.p);
+    if (st != rocblas_status_success) throw Error(PKIFMM_ERR_HIP, "rocsolver_dgesvd failed");
+    std::vector<double> sv(kn);
+    rocblas_int inf = 0;
+    PK_HIP(hipMemcpyAsync(sv.data(), S.p, sizeof(double) * kn, hipMemcpyDeviceToHost, s));
+    PK_HIP(hipMemcpyAsync(&inf, info.p, sizeof(inf), hipMemcpyDeviceToHost, s));
+    PK_HIP(hipStreamSynchronize(s));
+    if (inf != 0) throw Error(PKIFMM_ERR_NUMERICS, "SVD did not converge");
+    int r = 0;
+    while (r < kn && sv[r] > thr * sv[0]) ++r;
+    if (r == 0) throw Error(PKIFMM_ERR_NUMERICS, "zero matrix");
+    Ut.ensure((size_t)r * kn);
+    VS.ensure((size_t)kn * r);
+    launch_pinv_factors(U.p, Vt.p, S.p, kn, r, Ut.p, VS.p, s);
+    PK_HIP(hipStreamSynchronize(s));
+    // backward-stability self-check on q = A x for a fixed x: ||A (V S^+ U^T q) - q|| small
+    std::vector<double> hA((size_t)kn * kn), hUt((size_t)r * kn), hVS((size_t)kn * r);
+    PK_HIP(hipMemcpy(hA.data(), A_dev, sizeof(double) * kn * kn, hipMemcpyDeviceToHost));
+    PK_HIP(hipMemcpy(hUt.data(), Ut.p, sizeof(double) * r * kn, hipMemcpyDeviceToHost));
+    PK_HIP(hipMemcpy(hVS.data(), VS.p, sizeof(double) * kn * r, hipMemcpyDeviceToHost));
+    std::vector<double> x(kn), q(kn, 0.0), t(r, 0.0), ph(kn, 0.0), aq(kn, 0.0);
+    for (int i = 0; i < kn; ++i) x[i] = std::sin(1.0 + 0.37 * i);
+    for (int j = 0; j < kn; ++j)
+        for (int i = 0; i < kn; ++i) q[i] += hA[i + (size_t)j * kn] * x[j];
+    for (int j = 0; j < kn; ++j)
+        for (int i = 0; i < r; ++i) t[i] += hUt[i + (size_t)j * r] * q[j];
+    for (int j = 0; j < r; ++j)
+        for (int i = 0; i < kn; ++i) ph[i] += hVS[i + (size_t)j * kn] * t[j];
+    for (int j = 0; j < kn; ++j)
+        for (int i = 0; i < kn; ++i) aq[i] += hA[i + (size_t)j * kn] * ph[j];
+    double num = 0, den = 0;
+    for (int i = 0; i < kn; ++i) {
+        num += (aq[i] - q[i]) * (aq[i] - q[i]);
+        den += q[i] * q[i];
+    }
+    double tol = std::max(1e-10, 100.0 * thr);
+    if (!(std::sqrt(num / den) < tol))
+        throw Error(PKIFMM_ERR_NUMERICS, "check-to-equivalent solve failed its backward-error check");
+    return r;
+}
+
+void add_gemm(Gemm& g, int op, int M, const std::vector<int>& in, const std::vector<int>& out,
+              const std::vector<double>& sc) {
+    for (size_t c0 = 0; c0 < in.size(); c0 += 64) {
+        int ncol = (int)std::min<size_t>(64, in.size() - c0);
+        int col0 = (int)g.in.size();
+        g.in.insert(g.in.end(), in.begin() + c0, in.begin() + c0 + ncol);
+        g.out.insert(g.out.end(), out.begin() + c0, out.begin() + c0 + ncol);
+        g.scale.insert(g.scale.end(), sc.begin() + c0, sc.begin() + c0 + ncol);
+        for (int r0 = 0; r0 < M; r0 += 64) g.tiles.push_back(Tile{op, col0, ncol, r0});
+    }
+}
+
+double box_edge(const HostTree& t, int b) { return std::ldexp(1.0, -t.level[b]); }
+
+void build_work(pkifmm_plan* P, int R) {
+    const HostTree& t = P->tree;
+    const HostLists& L = P->lists;
+    const int nb = t.nbox();
+    const int ns = P->n_surf;
+    auto& segs = P->segs_h;
+    auto& work = P->work_h;
+    segs.clear();
+    work.clear();
+    const int kSelf = 13;
+    auto code = [](const Entry& e) { return (e.sx + 1) * 9 + (e.sy + 1) * 3 + (e.sz + 1); };
+    // S2M: leaf points -> own upward check surface
+    P->w_s2m.work0 = (int)work.size();
+    for (int b : t.leaves) {
+        int s0 = (int)segs.size();
+        segs.push_back(Seg{0, b, kSelf});
+        for (int c0 = 0; c0 < ns; c0 += 512) work.push_back(Work{b, 2, c0, std::min(512, ns - c0), s0, s0 + 1});
+    }
+    P->w_s2m.nwork = (int)work.size() - P->w_s2m.work0;
+    // X list: leaf points -> downward check surfaces
+    P->w_x.work0 = (int)work.size();
+    for (int b = 0; b < nb; ++b) {
+        if (L.x_off[b + 1] == L.x_off[b]) continue;
+        int s0 = (int)segs.size();
+        for (int64_t e = L.x_off[b]; e < L.x_off[b + 1]; ++e) segs.push_back(Seg{0, L.x[e].src, code(L.x[e])});
+        int s1 = (int)segs.size();
+        for (int c0 = 0; c0 < ns; c0 += 512) work.push_back(Work{b, 1, c0, std::min(512, ns - c0), s0, s1});
+    }
+    P->w_x.nwork = (int)work.size() - P->w_x.work0;
+    // leaves: U (points), W (upward equivalent surfaces), L2T (own downward equivalent surface);
+    // all three in one pass, or U alone and W + L2T alone
+    auto leaf_pass = [&](SegRange& out, bool with_u, bool with_far) {
+        out.work0 = (int)work.size();
+        for (int b : t.leaves) {
+            int s0 = (int)segs.size();
+            if (with_u)
+                for (int64_t e = L.u_off[b]; e < L.u_off[b + 1]; ++e) segs.push_back(Seg{0, L.u[e].src, code(L.u[e])});
+            if (with_far) {
+                for (int64_t e = L.w_off[b]; e < L.w_off[b + 1]; ++e) segs.push_back(Seg{1, L.w[e].src, code(L.w[e])});
+                segs.push_back(Seg{2, b, kSelf});
+            }
+            int s1 = (int)segs.size();
+            int cnt = t.end[b] - t.begin[b];
+            for (int c0 = 0; c0 < cnt; c0 += 512)
+                work.push_back(Work{b, 0, t.begin[b] + c0, std::min(512, cnt - c0), s0, s1});
+        }
+        out.nwork = (int)work.size() - out.work0;
+    };
+    leaf_pass(P->w_leaf_u, true, false);
+    leaf_pass(P->w_leaf_far, false, true);
+    hipStream_t s = P->setup_stream;
+    P->segs.upload(segs, s);
+    P->work.upload(work, s);
+
+    // GEMM launches
+    Gemm g;
+    const int kn = P->kn;
+    auto range = [&](auto&& fill) {
+        GemmRange r;
+        r.tile0 = (int)g.tiles.size();
+        fill();
+        r.ntile = (int)g.tiles.size() - r.tile0;
+        return r;
+    };
+    const int depth = t.depth;
+    for (int o = 0; o < 8; ++o) P->g_m2m[o].assign(depth + 1, GemmRange());
+    P->g_up1.assign(depth + 1, GemmRange());
+    P->g_up2.assign(depth + 1, GemmRange());
+    P->g_dn1.assign(depth + 1, GemmRange());
+    P->g_dn2.assign(depth + 1, GemmRange());
+    P->g_l2l.assign(depth + 1, GemmRange());
+    for (int lv = 0; lv <= depth; ++lv) {
+        const int b0 = t.level_start[lv], b1 = t.level_start[lv + 1];
+        const double h = std::ldexp(1.0, -lv);
+        // M2M into the non-leaf boxes of this level, one octant per launch (no write conflicts)
+        for (int o = 0; o < 8; ++o)
+            P->g_m2m[o][lv] = range([&] {
+                std::vector<int> in, out;
+                std::vector<double> sc;
+                for (int b = b0; b < b1; ++b) {
+                    int c = t.child[8 * b + o];
+                    if (c < 0) continue;
+                    for (int r = 0; r < R; ++r) {
+                        in.push_back(c * R + r);
+                        out.push_back(b * R + r);
+                        sc.push_back(1.0 / h);
+                    }
+                }
+                add_gemm(g, o, kn, in, out, sc);
+            });
+        std::vector<int> cols;
+        std::vector<double> one, hs;
+        for (int b = b0; b < b1; ++b)
+            for (int r = 0; r < R; ++r) {
+                cols.push_back(b * R + r);
+                one.push_back(1.0);
+                hs.push_back(h);
+            }
+        P->g_up1[lv] = range([&] { add_gemm(g, 0, P->r_up, cols, cols, one); });
+        P->g_up2[lv] = range([&] { add_gemm(g, 0, kn, cols, cols, hs); });
+        P->g_dn1[lv] = range([&] { add_gemm(g, 0, P->r_dn, cols, cols, one); });
+        P->g_dn2[lv] = range([&] { add_gemm(g, 0, kn, cols, cols, hs); });
+        if (lv >= 1)
+            P->g_l2l[lv] = range([&] {
+                const double hp = 2.0 * h;
+                for (int o = 0; o < 8; ++o) {
+                    std::vector<int> in, out;
+                    std::vector<double> sc;
+                    for (int b = b0; b < b1; ++b) {
+                        int par = t.parent[b];
+                        if (t.child[8 * par + o] != b) continue;
+                        for (int r = 0; r < R; ++r) {
+                            in.push_back(par * R + r);
+                            out.push_back(b * R + r);
+                            sc.push_back(1.0 / hp);
+                        }
+                    }
+                    add_gemm(g, o, kn, in, out, sc);
+                }
+            });
+    }
+    P->g_root = range([&] {
+        std::vector<int> c;
+        std::vector<double> one;
+        for (int r = 0; r < R; ++r) {
+            c.push_back(r);
+            one.push_back(1.0);
+        }
+        add_gemm(g, 0, kn, c, c, one);
+    });
+    // M2L grouped by offset; output column = V-list entry (summed per target afterwards)
+    P->g_m2l = range([&] {
+        std::vector<std::vector<int>> in(kNumM2L), out(kNumM2L);
+        std::vector<std::vector<double>> sc(kNumM2L);
+        for (int b = 0; b < nb; ++b)
+            for (int64_t e = L.v_off[b]; e < L.v_off[b + 1]; ++e) {
+                const Entry& v = L.v[e];
+                const int lv = t.level[b];
+                const int side = 1 << lv;
+                int dx = t.ix[v.src] + v.sx * side - t.ix[b];
+                int dy = t.iy[v.src] + v.sy * side - t.iy[b];
+                int dz = t.iz[v.src] + v.sz * side - t.iz[b];
+                int idx = m2l_offset_index(dx, dy, dz);
+                if (idx < 0) throw Error(PKIFMM_ERR_NUMERICS, "V-list offset out of range");
+                for (int r = 0; r < R; ++r) {
+                    in[idx].push_back(v.src * R + r);
+                    out[idx].push_back((int)(e * R + r));
+                    sc[idx].push_back(std::ldexp(1.0, lv));
+                }
+            }
+        for (int d = 0; d < kNumM2L; ++d)
+            if (!in[d].empty()) add_gemm(g, d, kn, in[d], out[d], sc[d]);
+    });
+    P->tiles.upload(g.tiles, s);
+    P->col_in.upload(g.in, s);
+    P->col_out.upload(g.out, s);
+    P->col_scale.upload(g.scale, s);
+
+    // workspace
+    const size_t cols = (size_t)nb * R;
+    P->q_u.ensure(cols * kn);
+    P->phi_u.ensure(cols * kn);
+    P->q_d.ensure(cols * kn);
+    P->phi_d.ensure(cols * kn);
+    P->tmp.ensure(cols * kn);
+    P->m2l_tmp.ensure(std::max<size_t>(1, (size_t)L.v.size() * R * kn));
+    P->ds.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
+    if (P->cfg.precision == PKIFMM_MIXED) P->ds32.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
+    P->pot.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
+    P->sums.ensure((size_t)R * P->k);
+    PK_HIP(hipStreamSynchronize(s));
+    P->R_built = R;
+}
+
+void run_gemm(pkifmm_plan* P, const GemmRange& gr, const double* ops, int64_t op_stride, int M, int K,
+              const double* B, int64_t ldb, double* C, int64_t ldc, bool acc, hipStream_t s) {
+    if (gr.ntile == 0) return;
+    GemmArgs a{};
+    a.ops = ops;
+    a.op_stride = op_stride;
+    a.M = M;
+    a.K = K;
+    a.B = B;
+    a.ldb = ldb;
+    a.C = C;
+    a.ldc = ldc;
+    a.tiles = P->tiles.p + gr.tile0;
+    a.n_tiles = gr.ntile;
+    a.in_col = P->col_in.p;
+    a.out_col = P->col_out.p;
+    a.scale = P->col_scale.p;
+    a.accumulate = acc ? 1 : 0;
+    launch_gemm(a, s);
+}
+
+void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_surf, int R, bool f32, bool acc_pts,
+             hipStream_t s) {
+    if (w.nwork == 0) return;
+    P2PArgs a{};
+    a.kernel = P->cfg.kernel;
+    a.n_surf = P->n_surf;
+    a.R = R;
+    a.n = P->n;
+    a.xs = P->xs.p;
+    a.off = P->off.p;
+    a.ds = P->ds.p;
+    a.ds32 = P->ds32.p;
+    a.phi_u = P->phi_u.p;
+    a.phi_d = P->phi_d.p;
+    a.box_level = P->b_level.p;
+    a.box_ix = P->b_ix.p;
+    a.box_iy = P->b_iy.p;
+    a.box_iz = P->b_iz.p;
+    a.box_begin = P->b_begin.p;
+    a.box_end = P->b_end.p;
+    a.usurf = P->usurf.p;
+    a.segs = P->segs.p;
+    a.work = P->work.p + w.work0;
+    a.n_work = w.nwork;
+    a.out_pts = out_pts;
+    a.out_surf = out_surf;
+    a.accumulate_pts = acc_pts ? 1 : 0;
+    launch_p2p(a, f32, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pkifmm_config_default(pkifmm_config* c) {
+    if (!c) return PKIFMM_ERR_INVALID_ARG;
+    std::memset(c, 0, sizeof(*c));
+    c->kernel = PKIFMM_LAPLACE;
+    c->periodic_mask = 0;
+    c->p = 8;
+    c->max_pts_per_leaf = 64;
+    c->precision = PKIFMM_FP64;
+    c->m2l_mode = PKIFMM_M2L_FP32;
+    c->box_length = 1.0;
+    c->svd_rel_threshold = 0.0;
+    c->flags = 0;
+    return PKIFMM_OK;
+}
+
+int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
+    if (!cfg || !out) return PKIFMM_ERR_INVALID_ARG;
+    *out = nullptr;
+    std::unique_ptr<pkifmm_plan> P(new pkifmm_plan());
+    rocblas_handle h = nullptr;
+    try {
+        check_config(*cfg);
+        P->cfg = *cfg;
+        P->k = cfg->kernel == PKIFMM_LAPLACE ? 1 : 3;
+        const int p = cfg->p;
+        std::vector<double> u = unit_surface(p);
+        P->n_surf = (int)u.size() / 3;
+        P->kn = P->k * P->n_surf;
+        const int kn = P->kn, ns = P->n_surf;
+        PK_HIP(hipStreamCreate(&P->setup_stream));
+        hipStream_t s = P->setup_stream;
+        if (rocblas_create_handle(&h) != rocblas_status_success) throw Error(PKIFMM_ERR_HIP, "rocblas handle");
+        rocblas_set_stream(h, s);
+        P->usurf.upload(u, s);
+        const auto inner = scaled(u, kInnerHalf, 0, 0, 0), outer = scaled(u, kOuterHalf, 0, 0, 0);
+        DBuf<double> d_in, d_out, d_tmp, A;
+        d_in.upload(inner, s);
+        d_out.upload(outer, s);
+        A.ensure((size_t)kn * kn);
+        double thr = cfg->svd_rel_threshold;
+        if (thr == 0.0) thr = std::ldexp(1.0, -52);
+        // upward: check = outer, equivalent = inner;  downward: check = inner, equivalent = outer
+        launch_kmat(cfg->kernel, d_out.p, ns, d_in.p, ns, A.p, kn, s);
+        P->r_up = pinv_build(h, s, A.p, kn, thr, P->up_Ut, P->up_VS);
+        launch_kmat(cfg->kernel, d_in.p, ns, d_out.p, ns, A.p, kn, s);
+        P->r_dn = pinv_build(h, s, A.p, kn, thr, P->dn_Ut, P->dn_VS);
+        // M2M / L2L: parent edge 1 centred at 0, child o centred at +-1/4
+        P->m2m.ensure((size_t)8 * kn * kn);
+        P->l2l.ensure((size_t)8 * kn * kn);
+        for (int o = 0; o < 8; ++o) {
+            double cx = ((o >> 2) & 1) ? 0.25 : -0.25, cy = ((o >> 1) & 1) ? 0.25 : -0.25, cz = (o & 1) ? 0.25 : -0.25;
+            d_tmp.upload(scaled(u, 0.5 * kInnerHalf, cx, cy, cz), s);
+            launch_kmat(cfg->kernel, d_out.p, ns, d_tmp.p, ns, P->m2m.p + (size_t)o * kn * kn, kn, s);
+            launch_kmat(cfg->kernel, d_tmp.p, ns, d_out.p, ns, P->l2l.p + (size_t)o * kn * kn, kn, s);
+            PK_HIP(hipStreamSynchronize(s));
+        }
+        // M2L: target box centred at 0, source box centred at delta, both edge 1
+        P->m2l.ensure((size_t)kNumM2L * kn * kn);
+        for (int d = 0; d < kNumM2L; ++d) {
+            int dx, dy, dz;
+            m2l_offset_vector(d, dx, dy, dz);
+            d_tmp.upload(scaled(u, kInnerHalf, dx, dy, dz), s);
+            launch_kmat(cfg->kernel, d_in.p, ns, d_tmp.p, ns, P->m2l.p + (size_t)d * kn * kn, kn, s);
+            PK_HIP(hipStreamSynchronize(s));
+        }
+        // root far field: K^{P,F}(x^{B0,d}, y^{B0,u}), both the 1.05 cube of the unit box
+        P->mroot.ensure((size_t)kn * kn);
+        if (cfg->periodic_mask == 0) {
+            PK_HIP(hipMemsetAsync(P->mroot.p, 0, sizeof(double) * kn * kn, s));
+        } else {
+            d_tmp.upload(scaled(u, kInnerHalf, 0.5, 0.5, 0.5), s);
+            launch_far_kmat(cfg->kernel, cfg->periodic_mask, d_tmp.p, ns, d_tmp.p, ns, P->mroot.p, kn, nullptr, s);
+        }
+        P->err_flag.ensure(1);
+        PK_HIP(hipStreamSynchronize(s));
+        rocblas_destroy_handle(h);
+        h = nullptr;
+        P->stats.svd_rank_up = P->r_up;
+        P->stats.svd_rank_down = P->r_dn;
+    } catch (const Error& e) {
+        if (h) rocblas_destroy_handle(h);
+        if (P->setup_stream) (void)hipStreamDestroy(P->setup_stream);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (h) rocblas_destroy_handle(h);
+        return PKIFMM_ERR_OOM;
+    }
+    *out = P.release();
+    return PKIFMM_OK;
+}
+
+int pkifmm_set_points(pkifmm_plan* P, int64_t n, const double* xyz, void* stream) {
+    if (!P) return PKIFMM_ERR_INVALID_ARG;
+    if (n < 0 || n > (int64_t)INT32_MAX || (n > 0 && !xyz)) return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n or xyz"));
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        P->have_points = false;
+        P->R_built = -1;
+        P->n = n;
+        const size_t m = std::max<int64_t>(n, 1);
+        P->keys_a.ensure(m);
+        P->keys_b.ensure(m);
+        P->vals_a.ensure(m);
+        P->perm.ensure(m);
+        P->u_wrapped.ensure(3 * m);
+        P->xs.ensure(3 * m);
+        PK_HIP(hipMemsetAsync(P->err_flag.p, 0, sizeof(int), s));
+        launch_keys(xyz, n, P->cfg.box_length, P->cfg.periodic_mask, P->keys_a.p, P->vals_a.p, P->u_wrapped.p,
+                    P->err_flag.p, s);
+        int err = 0;
+        PK_HIP(hipMemcpyAsync(&err, P->err_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        radix_sort_pairs(P->keys_a.p, P->keys_b.p, P->vals_a.p, P->perm.p, n, P->sort_temp, s);
+        launch_gather_points(P->u_wrapped.p, P->perm.p, n, P->xs.p, s);
+        std::vector<uint64_t> keys(n);
+        if (n) PK_HIP(hipMemcpyAsync(keys.data(), P->keys_b.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
+        PK_HIP(hipStreamSynchronize(s));
+        if (err) throw Error(PKIFMM_ERR_OUT_OF_BOX, "coordinate outside the box on a non-periodic axis, or not finite");
+        build_tree_host(keys.data(), n, P->cfg.max_pts_per_leaf, P->tree);
+        build_lists_host(P->tree, P->cfg.periodic_mask, P->lists);
+        const HostTree& t = P->tree;
+        P->b_level.upload(t.level, s);
+        P->b_ix.upload(t.ix, s);
+        P->b_iy.upload(t.iy, s);
+        P->b_iz.upload(t.iz, s);
+        P->b_begin.upload(t.begin, s);
+        P->b_end.upload(t.end, s);
+        std::vector<int> pb(m, 0);
+        for (int b : t.leaves)
+            for (int i = t.begin[b]; i < t.end[b]; ++i) pb[i] = b;
+        P->pt_box.upload(pb, s);
+        if (P->cfg.precision == PKIFMM_MIXED) {
+            P->off.ensure(6 * m);
+            launch_leaf_offsets(P->xs.p, n, P->pt_box.p, P->b_level.p, P->b_ix.p, P->b_iy.p, P->b_iz.p, P->off.p, s);
+        }
+        std::vector<int> vt;
+        for (int b = 0; b < t.nbox(); ++b)
+            if (P->lists.v_off[b + 1] > P->lists.v_off[b]) vt.push_back(b);
+        P->n_v_targets = (int)vt.size();
+        P->v_targets.upload(vt, s);
+        P->v_off.upload(P->lists.v_off, s);
+        PK_HIP(hipStreamSynchronize(s));
+        P->have_points = true;
+        auto& st = P->stats;
+        st.n_points = n;
+        st.n_boxes = t.nbox();
+        st.n_leaves = (int)t.leaves.size();
+        st.depth = t.depth;
+        st.n_u = (int64_t)P->lists.u.size();
+        st.n_v = (int64_t)P->lists.v.size();
+        st.n_w = (int64_t)P->lists.w.size();
+        st.n_x = (int64_t)P->lists.x.size();
+        int64_t up = 0;
+        for (int b : t.leaves)
+            for (int64_t e = P->lists.u_off[b]; e < P->lists.u_off[b + 1]; ++e) {
+                int a = P->lists.u[e].src;
+                up += (int64_t)(t.end[b] - t.begin[b]) * (t.end[a] - t.begin[a]);
+            }
+        st.u_pairs = up;
+    } catch (const Error& e) {
+        return fail(P, e);
+    } catch (const std::bad_alloc&) {
+        return fail(P, Error(PKIFMM_ERR_OOM, "host allocation"));
+    }
+    P->stats.ms_set_points = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return PKIFMM_OK;
+}
+
+int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potential, void* stream) {
+    if (!P) return PKIFMM_ERR_INVALID_ARG;
+    if (!P->have_points) return fail(P, Error(PKIFMM_ERR_NO_POINTS, "set_points has not succeeded"));
+    if (R < 1 || (P->n > 0 && (!density || !potential))) return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n_rhs or pointers"));
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        const int64_t n = P->n;
+        const int k = P->k, kn = P->kn;
+        if (n == 0) return PKIFMM_OK;
+        if (P->R_built != R) build_work(P, R);
+        const HostTree& t = P->tree;
+        const bool mixed = P->cfg.precision == PKIFMM_MIXED;
+        const bool timing = (P->cfg.flags & PKIFMM_PHASE_TIMING) != 0;
+        std::vector<hipEvent_t> ev;
+        auto mark = [&]() {
+            if (!timing) return;
+            hipEvent_t e;
+            PK_HIP(hipEventCreate(&e));
+            PK_HIP(hipEventRecord(e, s));
+            ev.push_back(e);
+        };
+        launch_permute_density(density, P->perm.p, n, R, k, P->ds.p, mixed ? P->ds32.p : nullptr, s);
+        if (__builtin_popcount(P->cfg.periodic_mask) == 1 && !(P->cfg.flags & PKIFMM_SKIP_CHECKS)) {
+            std::vector<double> sums(R * k);
+            launch_density_sums(P->ds.p, n, R, k, P->sums.p, s);
+            PK_HIP(hipMemcpyAsync(sums.data(), P->sums.p, sizeof(double) * R * k, hipMemcpyDeviceToHost, s));
+            PK_HIP(hipStreamSynchronize(s));
+            for (int i = 0; i < R * k; ++i)
+                if (!(std::fabs(sums[i]) <= 1e-10 * std::max(1.0, (double)n)))
+                    throw Error(PKIFMM_ERR_INCOMPATIBLE, "singly periodic input needs a zero net density");
+        }
+        const size_t cols = (size_t)t.nbox() * R;
+        const int64_t kk = (int64_t)kn * kn;
+        mark();
+        // 7a. U-list near field: depends on nothing else (float32 in the mixed mode)
+        run_p2p(P, P->w_leaf_u, P->pot.p, nullptr, R, mixed, false, s);
+        mark();
+        // 2-3. S2M and the upward pass
+        PK_HIP(hipMemsetAsync(P->q_u.p, 0, sizeof(double) * cols * kn, s));
+        PK_HIP(hipMemsetAsync(P->q_d.p, 0, sizeof(double) * cols * kn, s));
+        run_p2p(P, P->w_s2m, nullptr, P->q_u.p, R, false, false, s);
+        for (int lv = t.depth; lv >= 0; --lv) {
+            for (int o = 0; o < 8; ++o)
+                run_gemm(P, P->g_m2m[o][lv], P->m2m.p + (size_t)o * kk, 0, kn, kn, P->phi_u.p, kn, P->q_u.p, kn, true, s);
+            run_gemm(P, P->g_up1[lv], P->up_Ut.p, 0, P->r_up, kn, P->q_u.p, kn, P->tmp.p, kn, false, s);
+            run_gemm(P, P->g_up2[lv], P->up_VS.p, 0, kn, P->r_up, P->tmp.p, kn, P->phi_u.p, kn, false, s);
+        }
+        mark();
+        // 4-5. root far field and V-list M2L
+        run_gemm(P, P->g_root, P->mroot.p, 0, kn, kn, P->phi_u.p, kn, P->q_d.p, kn, true, s);
+        run_gemm(P, P->g_m2l, P->m2l.p, kk, kn, kn, P->phi_u.p, kn, P->m2l_tmp.p, kn, false, s);
+        launch_segment_reduce(P->m2l_tmp.p, P->v_off.p, P->v_targets.p, P->n_v_targets, R, kn, P->q_d.p, s);
+        mark();
+        // 5-6. X list and the downward pass
+        run_p2p(P, P->w_x, nullptr, P->q_d.p, R, false, false, s);
+        for (int lv = 0; lv <= t.depth; ++lv) {
+            if (lv >= 1) run_gemm(P, P->g_l2l[lv], P->l2l.p, kk, kn, kn, P->phi_d.p, kn, P->q_d.p, kn, true, s);
+            run_gemm(P, P->g_dn1[lv], P->dn_Ut.p, 0, P->r_dn, kn, P->q_d.p, kn, P->tmp.p, kn, false, s);
+            run_gemm(P, P->g_dn2[lv], P->dn_VS.p, 0, kn, P->r_dn, P->tmp.p, kn, P->phi_d.p, kn, false, s);
+        }
+        mark();
+        // 7b. W list and L2T (float64: they consume equivalent densities)
+        run_p2p(P, P->w_leaf_far, P->pot.p, nullptr, R, false, true, s);
+        // 8. output
+        const double c = (P->cfg.kernel == PKIFMM_LAPLACE ? 1.0 / (4.0 * M_PI) : 1.0 / (8.0 * M_PI)) / P->cfg.box_length;
+        launch_unpermute(P->pot.p, P->perm.p, n, R, k, c, potential, s);
+        mark();
+        if (timing) P->pending_events.push_back(ev);
+    } catch (const Error& e) {
+        return fail(P, e);
+    } catch (const std::bad_alloc&) {
+        return fail(P, Error(PKIFMM_ERR_OOM, "host allocation"));
+    }
+    P->stats.ms_evaluate = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return PKIFMM_OK;
+}
+
+int pkifmm_get_stats(pkifmm_plan* P, pkifmm_stats* out) {
+    if (!P || !out) return PKIFMM_ERR_INVALID_ARG;
+    if (!P->pending_events.empty()) {
+        double sum[PKIFMM_NUM_PHASES] = {0};
+        int cnt = 0;
+        hipError_t bad = hipSuccess;
+        for (auto& ev : P->pending_events) {
+            if (ev.size() == PKIFMM_NUM_PHASES + 1) {
+                if (hipEventSynchronize(ev.back()) != hipSuccess) bad = hipErrorUnknown;
+                for (int i = 0; i < PKIFMM_NUM_PHASES && bad == hipSuccess; ++i) {
+                    float ms = 0.f;
+                    if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) bad = hipErrorUnknown;
+                    sum[i] += ms;
+                }
+                ++cnt;
+            }
+            for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        }
+        P->pending_events.clear();
+        if (bad != hipSuccess) return fail(P, Error(PKIFMM_ERR_HIP, "phase timing events"));
+        P->stats.n_timed = cnt;
+        for (int i = 0; i < PKIFMM_NUM_PHASES; ++i) P->stats.ms_phase[i] = cnt ? sum[i] / cnt : 0.0;
+    }
+    *out = P->stats;
+    return PKIFMM_OK;
+}
+
+int pkifmm_get_tree(const pkifmm_plan* P, int64_t* perm, int32_t* boxes) {
+    if (!P) return PKIFMM_ERR_INVALID_ARG;
+    if (!P->have_points) return PKIFMM_ERR_NO_POINTS;
+    const HostTree& t = P->tree;
+    if (perm && P->n > 0) {
+        std::vector<uint32_t> h(P->n);
+        if (hipMemcpy(h.data(), P->perm.p, sizeof(uint32_t) * P->n, hipMemcpyDeviceToHost) != hipSuccess)
+            return PKIFMM_ERR_HIP;
+        for (int64_t i = 0; i < P->n; ++i) perm[i] = h[i];
+    }
+    if (boxes)
+        for (int b = 0; b < t.nbox(); ++b) {
+            int fc = -1;
+            for (int o = 0; o < 8 && fc < 0; ++o) fc = t.child[8 * b + o];
+            int32_t row[8] = {t.level[b], t.ix[b], t.iy[b], t.iz[b], t.begin[b], t.end[b], t.parent[b], fc};
+            std::memcpy(boxes + 8 * b, row, sizeof(row));
+        }
+    return PKIFMM_OK;
+}
+
+int pkifmm_get_list(const pkifmm_plan* P, char which, int64_t* offsets, int32_t* entries) {
+    if (!P || !offsets) return PKIFMM_ERR_INVALID_ARG;
+    if (!P->have_points) return PKIFMM_ERR_NO_POINTS;
+    const HostLists& L = P->lists;
+    const std::vector<int64_t>* off;
+    const std::vector<Entry>* ent;
+    switch (which) {
+        case 'U': off = &L.u_off; ent = &L.u; break;
+        case 'V': off = &L.v_off; ent = &L.v; break;
+        case 'W': off = &L.w_off; ent = &L.w; break;
+        case 'X': off = &L.x_off; ent = &L.x; break;
+        default: return PKIFMM_ERR_INVALID_ARG;
+    }
+    std::memcpy(offsets, off->data(), sizeof(int64_t) * off->size());
+    if (entries)
+        for (size_t e = 0; e < ent->size(); ++e) {
+            const Entry& x = (*ent)[e];
+            entries[4 * e] = x.src;
+            entries[4 * e + 1] = x.sx;
+            entries[4 * e + 2] = x.sy;
+            entries[4 * e + 3] = x.sz;
+        }
+    return PKIFMM_OK;
+}
+
+int pkifmm_plan_destroy(pkifmm_plan* P) {
+    if (!P) return PKIFMM_OK;
+    for (auto& ev : P->pending_events)
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    if (P->setup_stream) (void)hipStreamDestroy(P->setup_stream);
+    delete P;
+    return PKIFMM_OK;
+}
+
+const char* pkifmm_status_string(int s) {
+    switch (s) {
+        case PKIFMM_OK: return "ok";
+        case PKIFMM_ERR_INVALID_ARG: return "invalid argument";
+        case PKIFMM_ERR_OUT_OF_BOX: return "coordinate outside the box";
+        case PKIFMM_ERR_INCOMPATIBLE: return "density violates the compatibility condition";
+        case PKIFMM_ERR_UNSUPPORTED: return "unsupported kernel/periodicity";
+        case PKIFMM_ERR_OOM: return "out of memory";
+        case PKIFMM_ERR_HIP: return "HIP runtime error";
+        case PKIFMM_ERR_NO_POINTS: return "no points set";
+        case PKIFMM_ERR_NUMERICS: return "operator construction failed its self-check";
+        default: return "unknown status";
+    }
+}
+
+const char* pkifmm_last_error(const pkifmm_plan* P) { return P ? P->last_error.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,257 @@
+// Octree topology and periodic interaction lists, built on the host from the
+// Morton keys the device has already sorted.  The topology is small (a few
+// thousand boxes for a million points), so it is cheaper to build here than
+// to launch a dependent kernel per level.
+//
+// Tree rule (the paper's notation table: at most s points per leaf): a box is
+// split into its non-empty octants while it holds more than s points, up to
+// level 21.  Boxes are numbered level by level and in Morton order within a
+// level.
+//
+// Lists (Section 2: the near field of a box is its same-level adjacent boxes;
+// adaptive KIFMM U/V/W/X lists), with adjacency taken through the periodic
+// wrap on periodic axes and every entry carrying its image shift p in
+// {-1,0,1}^3 (the source box is translated by +p):
+//   U(B)  B leaf: all leaves A with A+p adjacent to B (B itself included)
+//   V(B)  children of the colleagues of parent(B) not adjacent to B
+//   W(B)  B leaf: descendants A of B's colleagues, not adjacent to B, whose
+//         parent is adjacent to B
+//   X(B)  all (A, p) with (B, -p) in W(A)
+// The root has no V list; its far field is the periodic root operator.
+#include <algorithm>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace pk {
+
+namespace {
+
+inline uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1fffff;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+}
+
+}  // namespace
+
+void build_tree_host(const uint64_t* keys, int64_t n, int s, HostTree& t) {
+    t = HostTree();
+    auto add = [&](int lv, int x, int y, int z, int b0, int b1, int par) {
+        t.level.push_back(lv); t.ix.push_back(x); t.iy.push_back(y); t.iz.push_back(z);
+        t.begin.push_back(b0); t.end.push_back(b1); t.parent.push_back(par);
+        for (int o = 0; o < 8; ++o) t.child.push_back(-1);
+        return (int)t.level.size() - 1;
+    };
+    add(0, 0, 0, 0, 0, (int)n, -1);
+    t.level_start.push_back(0);
+    int lv = 0;
+    std::vector<int> frontier{0};
+    while (!frontier.empty() && lv < kMaxLevel) {
+        std::vector<int> next;
+        const int sh = 3 * (kMaxLevel - (lv + 1));
+        for (int b : frontier) {
+            if (t.end[b] - t.begin[b] <= s) continue;
+            const uint64_t* lo_ptr = keys + t.begin[b];
+            const uint64_t* hi_ptr = keys + t.end[b];
+            for (int o = 0; o < 8; ++o) {
+                int cx = 2 * t.ix[b] + ((o >> 2) & 1);
+                int cy = 2 * t.iy[b] + ((o >> 1) & 1);
+                int cz = 2 * t.iz[b] + (o & 1);
+                uint64_t prefix = morton3(cx, cy, cz);
+                uint64_t klo = prefix << sh;
+                uint64_t khi = ((prefix + 1) << sh) - 1;
+                const uint64_t* a = std::lower_bound(lo_ptr, hi_ptr, klo);
+                const uint64_t* e = std::upper_bound(a, hi_ptr, khi);
+                if (e <= a) continue;
+                int c = add(lv + 1, cx, cy, cz, (int)(a - keys), (int)(e - keys), b);
+                t.child[8 * b + o] = c;
+                next.push_back(c);
+            }
+        }
+        if (next.empty()) break;
+        ++lv;
+        t.level_start.push_back(next.front());
+        frontier.swap(next);
+    }
+    t.depth = lv;
+    t.level_start.push_back(t.nbox());
+    t.leaf_id.assign(t.nbox(), -1);
+    for (int b = 0; b < t.nbox(); ++b)
+        if (t.is_leaf(b)) {
+            t.leaf_id[b] = (int)t.leaves.size();
+            t.leaves.push_back(b);
+        }
+}
+
+int m2l_offset_index(int dx, int dy, int dz) {
+    int idx = 0;
+    for (int a = -3; a <= 3; ++a)
+        for (int b = -3; b <= 3; ++b)
+            for (int c = -3; c <= 3; ++c) {
+                if (std::max(std::abs(a), std::max(std::abs(b), std::abs(c))) < 2) continue;
+                if (a == dx && b == dy && c == dz) return idx;
+                ++idx;
+            }
+    return -1;
+}
+
+void m2l_offset_vector(int idx, int& dx, int& dy, int& dz) {
+    int i = 0;
+    for (int a = -3; a <= 3; ++a)
+        for (int b = -3; b <= 3; ++b)
+            for (int c = -3; c <= 3; ++c) {
+                if (std::max(std::abs(a), std::max(std::abs(b), std::abs(c))) < 2) continue;
+                if (i == idx) { dx = a; dy = b; dz = c; return; }
+                ++i;
+            }
+    dx = dy = dz = 0;
+}
+
+void build_lists_host(const HostTree& t, unsigned mask, HostLists& L) {
+    const int nb = t.nbox();
+    // per-level lookup of (ix, iy, iz) -> box
+    std::vector<std::unordered_map<uint64_t, int>> at(t.depth + 1);
+    for (int b = 0; b < nb; ++b)
+        at[t.level[b]][morton3(t.ix[b], t.iy[b], t.iz[b])] = b;
+
+    auto coord = [&](int b, int c) { return c == 0 ? t.ix[b] : (c == 1 ? t.iy[b] : t.iz[b]); };
+    // closed boxes A+p and B touch or overlap
+    auto adjacent = [&](int a, const int p[3], int b) {
+        int la = t.level[a], lb = t.level[b];
+        int m = std::max(la, lb);
+        int64_t sa = int64_t(1) << (m - la), sb = int64_t(1) << (m - lb), per = int64_t(1) << m;
+        for (int c = 0; c < 3; ++c) {
+            int64_t alo = coord(a, c) * sa + p[c] * per, ahi = alo + sa;
+            int64_t blo = coord(b, c) * sb, bhi = blo + sb;
+            if (alo > bhi || blo > ahi) return false;
+        }
+        return true;
+    };
+    struct Col { int box; int p[3]; };
+    std::vector<std::vector<Col>> coll(nb);
+    for (int b = 0; b < nb; ++b) {
+        const int lv = t.level[b];
+        const int side = 1 << lv;
+        for (int ox = -1; ox <= 1; ++ox)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int oz = -1; oz <= 1; ++oz) {
+                    int g[3] = {t.ix[b] + ox, t.iy[b] + oy, t.iz[b] + oz};
+                    int p[3] = {0, 0, 0};
+                    bool ok = true;
+                    for (int c = 0; c < 3; ++c) {
+                        if (g[c] >= 0 && g[c] < side) continue;
+                        if (mask & (1u << c)) {
+                            p[c] = g[c] < 0 ? -1 : 1;
+                            g[c] -= p[c] * side;
+                        } else {
+                            ok = false;
+                        }
+                    }
+                    if (!ok) continue;
+                    auto it = at[lv].find(morton3(g[0], g[1], g[2]));
+                    if (it != at[lv].end()) coll[b].push_back({it->second, {p[0], p[1], p[2]}});
+                }
+    }
+    auto mk = [](int a, const int p[3]) { return Entry{a, (int8_t)p[0], (int8_t)p[1], (int8_t)p[2]}; };
+    std::vector<std::vector<Entry>> U(nb), V(nb), Wl(nb), X(nb);
+    for (int b = 0; b < nb; ++b) {
+        if (t.level[b] >= 1) {
+            for (const Col& pc : coll[t.parent[b]])
+                for (int o = 0; o < 8; ++o) {
+                    int a = t.child[8 * pc.box + o];
+                    if (a >= 0 && !adjacent(a, pc.p, b)) V[b].push_back(mk(a, pc.p));
+                }
+            std::sort(V[b].begin(), V[b].end());
+        }
+        if (!t.is_leaf(b)) continue;
+        std::vector<Col> stack(coll[b].begin(), coll[b].end());
+        while (!stack.empty()) {
+            Col c = stack.back();
+            stack.pop_back();
+            if (t.is_leaf(c.box)) {
+                U[b].push_back(mk(c.box, c.p));
+                continue;
+            }
+            for (int o = 0; o < 8; ++o) {
+                int d = t.child[8 * c.box + o];
+                if (d < 0) continue;
+                if (adjacent(d, c.p, b)) stack.push_back({d, {c.p[0], c.p[1], c.p[2]}});
+                else Wl[b].push_back(mk(d, c.p));
+            }
+        }
+        for (int anc = t.parent[b]; anc >= 0; anc = t.parent[anc])
+            for (const Col& c : coll[anc])
+                if (t.is_leaf(c.box) && adjacent(c.box, c.p, b)) U[b].push_back(mk(c.box, c.p));
+        std::sort(U[b].begin(), U[b].end());
+        U[b].erase(std::unique(U[b].begin(), U[b].end()), U[b].end());
+        std::sort(Wl[b].begin(), Wl[b].end());
+        Wl[b].erase(std::unique(Wl[b].begin(), Wl[b].end()), Wl[b].end());
+    }
+    for (int a = 0; a < nb; ++a)
+        for (const Entry& e : Wl[a]) X[e.src].push_back(Entry{a, (int8_t)-e.sx, (int8_t)-e.sy, (int8_t)-e.sz});
+    for (int b = 0; b < nb; ++b) std::sort(X[b].begin(), X[b].end());
+
+    auto flatten = [nb](std::vector<std::vector<Entry>>& in, std::vector<int64_t>& off, std::vector<Entry>& out) {
+        off.assign(nb + 1, 0);
+        for (int b = 0; b < nb; ++b) off[b + 1] = off[b] + (int64_t)in[b].size();
+        out.clear();
+        out.reserve(off[nb]);
+        for (int b = 0; b < nb; ++b) out.insert(out.end(), in[b].begin(), in[b].end());
+    };
+    flatten(U, L.u_off, L.u);
+    flatten(V, L.v_off, L.v);
+    flatten(Wl, L.w_off, L.w);
+    flatten(X, L.x_off, L.x);
+}
+
+}  // namespace pk
+
+extern "C" int pkifmm_host_topology(const uint64_t* keys, int64_t n, int s, unsigned mask, char which,
+                                    int64_t* n_boxes, int32_t* boxes, int64_t* offsets, int32_t* entries) {
+    using namespace pk;
+    if (!n_boxes || n < 0 || s < 1 || (n > 0 && !keys) || (mask & ~7u)) return PKIFMM_ERR_INVALID_ARG;
+    try {
+        HostTree t;
+        build_tree_host(keys, n, s, t);
+        *n_boxes = t.nbox();
+        if (boxes)
+            for (int b = 0; b < t.nbox(); ++b) {
+                int fc = -1;
+                for (int o = 0; o < 8 && fc < 0; ++o) fc = t.child[8 * b + o];
+                int32_t row[8] = {t.level[b], t.ix[b], t.iy[b], t.iz[b], t.begin[b], t.end[b], t.parent[b], fc};
+                for (int c = 0; c < 8; ++c) boxes[8 * b + c] = row[c];
+            }
+        if (!offsets) return PKIFMM_OK;
+        HostLists L;
+        build_lists_host(t, mask, L);
+        const std::vector<int64_t>* off;
+        const std::vector<Entry>* ent;
+        switch (which) {
+            case 'U': off = &L.u_off; ent = &L.u; break;
+            case 'V': off = &L.v_off; ent = &L.v; break;
+            case 'W': off = &L.w_off; ent = &L.w; break;
+            case 'X': off = &L.x_off; ent = &L.x; break;
+            default: return PKIFMM_ERR_INVALID_ARG;
+        }
+        for (size_t i = 0; i < off->size(); ++i) offsets[i] = (*off)[i];
+        if (entries)
+            for (size_t e = 0; e < ent->size(); ++e) {
+                entries[4 * e] = (*ent)[e].src;
+                entries[4 * e + 1] = (*ent)[e].sx;
+                entries[4 * e + 2] = (*ent)[e].sy;
+                entries[4 * e + 3] = (*ent)[e].sz;
+            }
+    } catch (const std::bad_alloc&) {
+        return PKIFMM_ERR_OOM;
+    }
+    return PKIFMM_OK;
+}

@@ -1,0 +1,62 @@
+"""CPU checks of the C-ABI library: symbols, and the host topology code against the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1705_02043_amd as pk
+from oracle import tree as otree
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "pkifmm.h")).read()
+    declared = set(re.findall(r"\b(pkifmm_\w+)\s*\(", hdr))
+    assert declared == set(pk.EXPORTED), declared ^ set(pk.EXPORTED)
+    L = pk.lib()
+    for name in declared:
+        assert getattr(L, name) is not None
+
+
+def test_status_strings_and_bad_config():
+    L = pk.lib()
+    assert L.pkifmm_status_string(0) == b"ok"
+    assert L.pkifmm_status_string(pk.ERR_OUT_OF_BOX).startswith(b"coordinate")
+    cfg = pk.pkifmm_config()
+    assert L.pkifmm_config_default(ctypes.byref(cfg)) == 0
+    assert cfg.p == 8 and cfg.box_length == 1.0
+    cfg.p = 2        # invalid order is rejected before any device call
+    h = ctypes.c_void_p()
+    assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_INVALID_ARG
+    cfg.p = 8
+    cfg.periodic_mask = 3   # doubly periodic far field is not provided
+    assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_UNSUPPORTED
+    assert L.pkifmm_plan_destroy(None) == 0
+
+
+def _oracle_rows(t):
+    rows = []
+    for b in range(t.nbox):
+        fc = next((c for c in t.children[b] if c >= 0), -1)
+        rows.append([t.level[b], *t.coord[b], t.begin[b], t.end[b], t.parent[b], fc])
+    return np.array(rows, dtype=np.int32)
+
+
+@pytest.mark.parametrize("mask,n,s,seed", [(0, 2000, 30, 1), (1, 2000, 50, 2), (7, 3000, 40, 3),
+                                           (4, 1500, 20, 4), (7, 5, 1, 5), (7, 1, 4, 6), (1, 0, 4, 7)])
+def test_host_topology_matches_oracle(mask, n, s, seed):
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 3)) ** 3            # strongly graded -> adaptive, W/X lists present
+    u = otree.wrap(pts, mask)
+    t = otree.build_tree(u, s)
+    lists = otree.build_lists(t, mask)
+    for which in "UVWX":
+        boxes, off, ent = pk.host_topology(t.keys, s, mask, which)
+        assert np.array_equal(boxes, _oracle_rows(t))
+        ref = getattr(lists, which)
+        for b in range(t.nbox):
+            got = [(int(e[0]), (int(e[1]), int(e[2]), int(e[3]))) for e in ent[off[b]:off[b + 1]]]
+            assert got == list(ref.get(b, [])), (which, b)

@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path through the C-ABI against the oracle (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import kifmm as okifmm, tree as otree
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _pk():
+    import paper_1705_02043_amd as pk
+    return pk
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _run(pb, precision, density=None, rhs=None):
+    pk = _pk()
+    plan = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=precision)
+    plan.set_points(_dev(pb.points))
+    d = pb.density if density is None else density
+    out = plan.evaluate(_dev(d)).cpu().numpy()
+    torch.cuda.synchronize()
+    return plan, out
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# FP64 tolerance: 1e-10, except for the Stokes kernel at p = 8, where the check-to-equivalent
+# matrix has condition number 1.26e13 (Table 1) and two backward-stable SVDs give solutions that
+# differ in the near-null space; inside the oracle itself, LAPACK's gesdd and gesvd drivers already
+# move the final potentials by ~5e-9 (pinned in test_oracle_pins.py), so the gate there is 10x that.
+STOKES_P8_FP64_TOL = 5e-8
+
+CASES = {
+    # name: (workload, fp64 tol, mixed tol)
+    "laplace_sp_n2000": (lambda: W.laplace_sp_uniform(n=2000, seed=1, p=8, s=50), 1e-10, 1e-6),
+    "stokes_tp_n20000": (lambda: W.stokes_tp_uniform(n=20000, seed=21, p=8, s=600), STOKES_P8_FP64_TOL, 1e-6),
+    "laplace_free_n5000": (lambda: W.laplace_sp_uniform(n=5000, seed=22, p=6, s=40, mask=0), 1e-10, 1e-6),
+    "stokes_free_graded": (lambda: _graded_stokes(), 1e-10, 1e-6),
+    "laplace_tp_n3000": (lambda: W.laplace_sp_uniform(n=3000, seed=23, p=6, s=60, mask=7), 1e-10, 1e-6),
+}
+
+
+def _graded_stokes():
+    pb = W.stokes_tp_uniform(n=6000, seed=24, p=6, s=40, mask=0)
+    pb.points = pb.points ** 2        # denser near the origin corner: adaptive tree with W/X lists
+    return pb
+
+
+_oracle_cache = {}
+
+
+def _oracle(name):
+    if name not in _oracle_cache:
+        pb = CASES[name][0]()
+        f = okifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+        ref = np.stack([f.evaluate(d) for d in pb.density])
+        _oracle_cache[name] = (pb, f, ref)
+    return _oracle_cache[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_tree_and_lists_bit_exact(name):
+    pb, f, _ = _oracle(name)
+    plan, _ = _run(pb, 0)
+    perm, boxes = plan.tree()
+    assert np.array_equal(perm, f.tree.perm)
+    t = f.tree
+    assert boxes.shape[0] == t.nbox
+    for b in range(t.nbox):
+        fc = next((c for c in t.children[b] if c >= 0), -1)
+        assert list(boxes[b]) == [t.level[b], *t.coord[b], t.begin[b], t.end[b], t.parent[b], fc]
+    for which in "UVWX":
+        off, ent = plan.lists(which)
+        ref = getattr(f.lists, which)
+        for b in range(t.nbox):
+            got = [(int(e[0]), (int(e[1]), int(e[2]), int(e[3]))) for e in ent[off[b]:off[b + 1]]]
+            assert got == list(ref.get(b, [])), (which, b)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_parity(name):
+    pb, f, ref = _oracle(name)
+    plan, out = _run(pb, 0)
+    err = _rel(out, ref)
+    print(f"{name} fp64 rel L2 {err:.3e} stats {plan.stats()}", flush=True)
+    assert err < CASES[name][1]
+    # elementwise: no single target far off
+    assert np.max(np.abs(out - ref)) < 100 * CASES[name][1] * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mixed_parity(name):
+    pb, f, ref = _oracle(name)
+    _, out = _run(pb, 1)
+    err = _rel(out, ref)
+    print(f"{name} mixed rel L2 {err:.3e}", flush=True)
+    assert err < CASES[name][2]
+
+
+def test_multiple_rhs_and_linearity():
+    pb = W.stokes_tp_uniform(n=4000, seed=25, p=6, s=200, n_rhs=3)
+    _, out = _run(pb, 0)
+    f = okifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+    for r in range(3):
+        assert _rel(out[r], f.evaluate(pb.density[r])) < 1e-10
+
+
+def test_root_leaf_and_tiny_inputs():
+    pk = _pk()
+    pts, q = W.madelung_chain(0)
+    plan = pk.Plan(pk.LAPLACE, pk.PERIODIC_X, 10, 10)
+    plan.set_points(_dev(pts))
+    out = plan.evaluate(_dev(q[:, None])).cpu().numpy()[:, 0]
+    f = okifmm.KIFMM(1, 1, 10, 10, pts)
+    ref = f.evaluate(q[:, None])[:, 0]
+    # p = 10 Laplace: A has numerical rank 444/488 (Table 1), so the two solvers truncate
+    # slightly differently; the potentials agree to ~1e-11
+    assert np.max(np.abs(out - ref)) < 1e-10
+    assert abs(out[0] - (-2 * np.log(2) / np.pi)) < 1e-9
+    # a single point and its own images only (TP Stokes allows a net force)
+    p1, f1 = W.one_point_force()
+    plan = pk.Plan(pk.STOKES, 7, 6, 4)
+    plan.set_points(_dev(p1))
+    out = plan.evaluate(_dev(f1)).cpu().numpy()
+    ref = okifmm.KIFMM(2, 7, 6, 4, p1).evaluate(f1)
+    assert np.max(np.abs(out - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_boundary_coordinates_and_errors():
+    pk = _pk()
+    rng = np.random.default_rng(26)
+    pts = rng.random((500, 3))
+    pts[:20, 0] = 1.0          # periodic axis: wraps to 0
+    pts[20:40, 1] = 1.0        # non-periodic: closed interval, last cell
+    pts[40:60, 2] = 0.0
+    pts[60:80, 0] = -0.25      # periodic axis: wraps to 0.75
+    q = rng.uniform(-1, 1, 500); q -= q.mean()
+    plan = pk.Plan(pk.LAPLACE, pk.PERIODIC_X, 6, 16)
+    plan.set_points(_dev(pts))
+    out = plan.evaluate(_dev(q[:, None])).cpu().numpy()
+    f = okifmm.KIFMM(1, 1, 6, 16, pts)
+    assert np.array_equal(plan.tree()[0], f.tree.perm)
+    assert _rel(out, f.evaluate(q[:, None])) < 1e-10
+    bad = pts.copy(); bad[3, 1] = 1.0 + 1e-9
+    with pytest.raises(pk.PkifmmError) as e:
+        plan.set_points(_dev(bad))
+    assert e.value.status == pk.ERR_OUT_OF_BOX
+    bad[3, 1] = np.nan
+    with pytest.raises(pk.PkifmmError):
+        plan.set_points(_dev(bad))
+    plan.set_points(_dev(pts))
+    with pytest.raises(pk.PkifmmError) as e:
+        plan.evaluate(_dev((q + 1.0)[:, None]))
+    assert e.value.status == pk.ERR_INCOMPATIBLE
+    plan.set_points(_dev(np.zeros((0, 3))))
+    out = plan.evaluate(torch.zeros((1, 0, 1), dtype=torch.float64, device="cuda"))
+    assert out.shape == (1, 0, 1)
+
+
+def test_repeat_is_bitwise_deterministic():
+    pb = W.stokes_tp_uniform(n=30000, seed=27, p=6, s=400)
+    plan, a = _run(pb, 1)
+    b = plan.evaluate(_dev(pb.density)).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, STOKES_P8_FP64_TOL), (1, 1e-6)])
+def test_full_size_stokes_tp_sampled(precision, tol):
+    """N = 1M Stokes TP, p = 8, s = 2000: every target of a sample of leaves against the oracle."""
+    pb = W.stokes_tp_uniform()
+    plan, out = _run(pb, precision)
+    f = okifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+    leaves = f.tree.leaves()
+    rng = np.random.default_rng(0)
+    pick = sorted(rng.choice(len(leaves), 4, replace=False))
+    sub = f.evaluate(pb.density[0], target_leaves=[leaves[i] for i in pick])
+    num = den = 0.0
+    for b, ref in sub.items():
+        idx = f.tree.perm[f.tree.begin[b]:f.tree.end[b]]
+        num += np.sum((out[0][idx] - ref) ** 2)
+        den += np.sum(ref ** 2)
+    err = np.sqrt(num / den)
+    print(f"full-size precision={precision} sampled rel L2 {err:.3e} over {len(pick)} leaves", flush=True)
+    assert err < tol

@@ -415,3 +415,28 @@ def test_kifmm_target_subset_matches_full():
     sub = f.evaluate(pb.density[0], target_leaves=leaves)
     for b in leaves:
         assert np.allclose(sub[b], full[f.tree.begin[b]:f.tree.end[b]], rtol=0, atol=1e-14)
+
+
+def test_solver_spread_stokes_p8():
+    """Two backward-stable SVD drivers (LAPACK gesdd, gesvd) give Stokes p = 8 potentials that differ
+    at the 1e-9 level (A has condition number 1.26e13, Table 1; the solution is not unique,
+    Appendix B); this spread sets the FP64 parity tolerance for that kernel and order."""
+    import scipy.linalg as sl
+    pb = W.stokes_tp_uniform(n=4000, seed=21, p=8, s=300)
+    f = kifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+    a = f.evaluate(pb.density[0])
+    ops = f.ops
+    keep_up, keep_dn = ops.up, ops.down
+
+    def gesvd(A):
+        U, s, Vt = sl.svd(A, lapack_driver="gesvd")
+        keep = s > kifmm.EPS * s[0]
+        return kifmm.Pinv(Ut=U[:, keep].T.copy(), VS=(Vt[keep].T / s[keep][None, :]).copy())
+    try:
+        ops.up = gesvd(K.kernel_matrix(K.STOKES, ops.outer, ops.inner))
+        ops.down = gesvd(K.kernel_matrix(K.STOKES, ops.inner, ops.outer))
+        b = f.evaluate(pb.density[0])
+    finally:
+        ops.up, ops.down = keep_up, keep_dn
+    spread = np.linalg.norm(a - b) / np.linalg.norm(a)
+    assert 1e-11 < spread < 2e-8, spread
