@@ -95,7 +95,8 @@ typedef struct {
 #define PKIFMM_PHASE_TIMING 2u   /* record HIP events around the phases of every evaluate on its
                                     stream; pkifmm_get_stats waits for them and reports averages */
 
-/* phases of one evaluation, in stream order */
+/* phases of one evaluation; the near field runs on a library-owned second stream,
+ * concurrently with the other phases, which run in this order on the caller's stream */
 #define PKIFMM_PHASE_NEAR 0      /* U-list direct sums (leaf points to leaf points) */
 #define PKIFMM_PHASE_UP 1        /* density permutation, S2M, M2M, upward solves */
 #define PKIFMM_PHASE_M2L 2       /* root far field, V-list M2L and its per-target sums */
@@ -108,6 +109,8 @@ typedef struct {
     int n_boxes, n_leaves, depth;
     int64_t n_u, n_v, n_w, n_x;  /* list entries */
     int64_t u_pairs;             /* point pairs summed directly over the U lists */
+    int64_t near_pairs;          /* point pairs of the near-field launch: U lists plus the W/X
+                                    entries evaluated directly */
     int svd_rank_up, svd_rank_down;
     double ms_set_points;        /* host wall time of the last pkifmm_set_points */
     double ms_evaluate;          /* host wall time of the last pkifmm_evaluate call (enqueue only
@@ -143,9 +146,11 @@ int pkifmm_set_points(pkifmm_plan *plan, int64_t n, const double *xyz, void *str
  * Evaluate the periodic sum for n_rhs densities on the current points.
  *   density:   device, [n_rhs][n][k] float64 (k = 1 Laplace, 3 Stokes), input order
  *   potential: device, [n_rhs][n][k] float64, overwritten, input order
- * Work is enqueued on `stream`; the call returns after enqueueing unless the
- * SP neutrality check runs (it reads one reduction back).  The output is
- * float64 in every precision mode.
+ * Work is enqueued on `stream` (the near field on a library-owned stream that
+ * forks from and joins back into `stream`, so completion of `stream` covers
+ * all of it); the call returns after enqueueing unless the SP neutrality
+ * check runs (it reads one reduction back).  The output is float64 in every
+ * precision mode.
  * Errors: NO_POINTS, INVALID_ARG, INCOMPATIBLE, OOM, HIP.
  */
 int pkifmm_evaluate(pkifmm_plan *plan, int n_rhs, const double *density, double *potential,

@@ -23,6 +23,11 @@ discussion:
        downward solves from the root to the leaves;
     d. at leaves: L2T from phi^{B,d}, W-list M2T from phi^{A,u} and the
        U-list direct sums over adjacent leaves and their periodic images.
+  A W-list box that is a leaf with no more points than a surface has acts on
+  the targets directly (its points instead of its upward surface), and a leaf
+  with no more points than a surface has takes its X list directly (the
+  sources straight to its points instead of through its downward surface):
+  the cheaper form of the same interaction, and exact.
 
 Every direct sum goes through the oracle's plain C loop; every dense
 operator product is a numpy matmul.  Test infrastructure only.
@@ -119,6 +124,17 @@ class KIFMM:
         self.ops = operators(kernel, mask, p, rel_threshold)
         self.sorted_pts = self.u[self.tree.perm]
 
+    # -- W/X lists: the cheaper of the surface operator and the direct sum
+    def direct_source(self, a) -> bool:
+        """A W-list box whose points are fewer than its surface points acts directly."""
+        t = self.tree
+        return t.is_leaf(a) and (t.end[a] - t.begin[a]) <= self.ops.n
+
+    def direct_target(self, b) -> bool:
+        """A leaf with fewer points than surface points takes its X list directly."""
+        t = self.tree
+        return t.is_leaf(b) and (t.end[b] - t.begin[b]) <= self.ops.n
+
     # -- geometry helpers
     def _pts(self, b, shift=(0, 0, 0)):
         t = self.tree
@@ -185,6 +201,8 @@ class KIFMM:
             for i, b in enumerate(tb):
                 qd[b] += contrib[i]
         for b in need:
+            if self.direct_target(b):
+                continue                     # its X-list sources go straight to its points below
             for (a, p) in self.lists.X[b]:
                 direct(self.kernel, self._surf(b, INNER), self._pts(a, p), ds[t.begin[a]:t.end[a]], qd[b])
         # root far field (folded step c), L2L and downward solves
@@ -205,7 +223,13 @@ class KIFMM:
             pot = np.zeros((x.shape[0], k))
             direct(self.kernel, x, self._surf(b, OUTER), phi_d[b], pot)
             for (a, p) in self.lists.W[b]:
-                direct(self.kernel, x, self._surf(a, INNER, p), phi_u[a], pot)
+                if self.direct_source(a):
+                    direct(self.kernel, x, self._pts(a), ds[t.begin[a]:t.end[a]], pot, shift=p)
+                else:
+                    direct(self.kernel, x, self._surf(a, INNER, p), phi_u[a], pot)
+            if self.direct_target(b):
+                for (a, p) in self.lists.X[b]:
+                    direct(self.kernel, x, self._pts(a), ds[t.begin[a]:t.end[a]], pot, shift=p)
             for (a, p) in self.lists.U[b]:
                 direct(self.kernel, x, self._pts(a), ds[t.begin[a]:t.end[a]], pot, shift=p)
             out[b] = pot / L

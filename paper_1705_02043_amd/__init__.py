@@ -42,6 +42,7 @@ class pkifmm_stats(ctypes.Structure):
     _fields_ = [("n_points", ctypes.c_int64), ("n_boxes", ctypes.c_int), ("n_leaves", ctypes.c_int),
                 ("depth", ctypes.c_int), ("n_u", ctypes.c_int64), ("n_v", ctypes.c_int64),
                 ("n_w", ctypes.c_int64), ("n_x", ctypes.c_int64), ("u_pairs", ctypes.c_int64),
+                ("near_pairs", ctypes.c_int64),
                 ("svd_rank_up", ctypes.c_int), ("svd_rank_down", ctypes.c_int),
                 ("ms_set_points", ctypes.c_double), ("ms_evaluate", ctypes.c_double),
                 ("n_timed", ctypes.c_int), ("ms_phase", ctypes.c_double * 5)]

@@ -25,7 +25,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
         objs.append(obj)
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        lang = ["-x", "hip"] if src.endswith(".hip") else ["-fopenmp"]
         cmd = [hipcc] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -36,7 +36,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     _wait(procs)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc, "-shared", "--offload-arch=gfx950", "-o", tmp] + objs + \
-          ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+          ["-fopenmp", "-L/opt/rocm/lib", "-L/opt/rocm/llvm/lib", "-lrocsolver", "-lrocblas",
+           "-Wl,-rpath,/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/llvm/lib"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

@@ -3,65 +3,142 @@
 // far-field operator.  All are "grouped gather GEMMs": a tile multiplies one
 // operator (column-major M x K) with up to 64 gathered input columns and
 // writes (or accumulates into) scattered output columns, each with its own
-// scale (the 2^l factors of the homogeneous kernels).
+// scale (the 2^l factors of the homogeneous kernels).  The K dimension may be
+// split into blocks that gather from different input columns: M2M multiplies
+// [M2M_0 | ... | M2M_7] with the stacked densities of a parent's eight
+// children in one pass (absent children read as zero).
 //
-// Float64 path: 64x64 output tiles, K staged through LDS in steps of 16,
-// 4x4 register micro-tiles per thread.
+// Float64 on the matrix cores: v_mfma_f64_16x16x4f64.  A 64x64 output tile
+// per workgroup (four waves, 32x32 each = 2x2 MFMA blocks), K staged through
+// LDS 16 at a time with the next slice prefetched into registers while the
+// current one is multiplied.  Tiles are laid out operator-major and mapped so
+// that the tiles of one operator run on the same XCD (its L2 keeps the
+// operator rows).  Launches with few tiles (the upper tree levels) split K
+// over several workgroups; the partial tiles are summed in a fixed order by a
+// second kernel, so results do not depend on scheduling.
 #include "launch.h"
 
 namespace pk {
 
 namespace {
 
-constexpr int TM = 64, TN = 64, TK = 16;
+typedef double v4d __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs a) {
-    const Tile t = a.tiles[blockIdx.x];
+constexpr int TM = 64, TN = 64, TK = 16, PAD = 2;
+
+struct Stage {     // one thread's share of a K slice: 4 elements of A and 4 of B
+    double a[4], b[4];
+};
+
+__device__ __forceinline__ void load_stage(const GemmArgs& a, const Tile& t, const double* __restrict__ A,
+                                           const int* s_in, int nkb, int k0, int k_end, int tid, Stage& st) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int idx = tid + 256 * e;
+        const int m = idx & (TM - 1), kk = idx >> 6;
+        const int row = t.row0 + m, k = k0 + kk;
+        st.a[e] = (row < a.M && k < k_end) ? A[row + (int64_t)k * a.M] : 0.0;
+        const int kk2 = idx & (TK - 1), nn = idx >> 4;
+        const int k2 = k0 + kk2;
+        double v = 0.0;
+        if (k2 < k_end) {
+            const int kb = nkb == 1 ? 0 : k2 / a.kblock;
+            const int col = s_in[nn * nkb + kb];
+            if (col >= 0) v = a.B[(int64_t)col * a.ldb + (k2 - kb * a.kblock)];
+        }
+        st.b[e] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_mfma_f64(GemmArgs a, int split, double* __restrict__ partial) {
+    // XCD-aware order: workgroup i runs on XCD i % 8; give each XCD a contiguous range
+    const int n_items = a.n_tiles * split;
+    const int per = (n_items + 7) / 8;
+    const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (logical >= n_items) return;
+    const int tile_id = logical / split, part = logical % split;
+    const Tile t = a.tiles[tile_id];
     const double* __restrict__ A = a.ops + (int64_t)t.op * a.op_stride;
-    __shared__ double sA[TK][TM + 1];
-    __shared__ double sB[TK][TN + 1];
-    __shared__ int s_in[TN];
+    const int kchunk = ((a.K + split - 1) / split + TK - 1) / TK * TK;
+    const int k_begin = part * kchunk, k_end = min(a.K, k_begin + kchunk);
+    __shared__ double sA[TK][TM + PAD];
+    __shared__ double sB[TK][TN + PAD];
+    __shared__ int s_in[TN * 8];
     const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
-    if (tid < TN) s_in[tid] = tid < t.ncol ? a.in_col[t.col0 + tid] : -1;
-    double acc[4][4];
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int nkb = a.in_stride;
+    for (int i = tid; i < TN * nkb; i += 256) {
+        int c = i / nkb;
+        s_in[i] = c < t.ncol ? a.in_col[(int64_t)(t.col0 + c) * 8 + (i % nkb)] : -1;
+    }
+    v4d acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
     __syncthreads();
-    for (int k0 = 0; k0 < a.K; k0 += TK) {
+    Stage st;
+    if (k_begin < k_end) load_stage(a, t, A, s_in, nkb, k_begin, k_end, tid, st);
+    for (int k0 = k_begin; k0 < k_end; k0 += TK) {
+#pragma unroll
         for (int e = 0; e < 4; ++e) {
-            int idx = tid + 256 * e;
-            int m = idx & (TM - 1), kk = idx >> 6;
-            int row = t.row0 + m, k = k0 + kk;
-            sA[kk][m] = (row < a.M && k < a.K) ? A[row + (int64_t)k * a.M] : 0.0;
-            int kk2 = idx & (TK - 1), nn = idx >> 4;
-            int col = s_in[nn];
-            int k2 = k0 + kk2;
-            sB[kk2][nn] = (col >= 0 && k2 < a.K) ? a.B[(int64_t)col * a.ldb + k2] : 0.0;
+            const int idx = tid + 256 * e;
+            sA[idx >> 6][idx & (TM - 1)] = st.a[e];
+            sB[idx & (TK - 1)][idx >> 4] = st.b[e];
         }
         __syncthreads();
+        if (k0 + TK < k_end) load_stage(a, t, A, s_in, nkb, k0 + TK, k_end, tid, st);   // next slice in flight
 #pragma unroll
-        for (int kk = 0; kk < TK; ++kk) {
-            double av[4], bv[4];
-            for (int i = 0; i < 4; ++i) av[i] = sA[kk][ty + 16 * i];
-            for (int j = 0; j < 4; ++j) bv[j] = sB[kk][tx + 16 * j];
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        for (int ks = 0; ks < TK; ks += 4) {
+            const int kr = ks + (lane >> 4);
+            double af[2], bf[2];
+            for (int i = 0; i < 2; ++i) af[i] = sA[kr][wm + 16 * i + (lane & 15)];
+            for (int j = 0; j < 2; ++j) bf[j] = sB[kr][wn + 16 * j + (lane & 15)];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
-    for (int j = 0; j < 4; ++j) {
-        int n = tx + 16 * j;
+    // D layout of the f64 16x16 block: lane holds column (lane & 15) and rows (lane >> 4) + 4 v
+    if (split > 1) {
+        double* P = partial + ((int64_t)tile_id * split + part) * (TM * TN);
+        for (int j = 0; j < 2; ++j)
+            for (int i = 0; i < 2; ++i)
+                for (int v = 0; v < 4; ++v) {
+                    const int rr = wm + 16 * i + (lane >> 4) + 4 * v, cc = wn + 16 * j + (lane & 15);
+                    P[cc * TM + rr] = acc[i][j][v];
+                }
+        return;
+    }
+    for (int j = 0; j < 2; ++j) {
+        const int n = wn + 16 * j + (lane & 15);
         if (n >= t.ncol) continue;
-        int oc = a.out_col[t.col0 + n];
-        double sc = a.scale[t.col0 + n];
+        const int oc = a.out_col[t.col0 + n];
+        const double sc = a.scale[t.col0 + n];
         double* C = a.C + (int64_t)oc * a.ldc;
-        for (int i = 0; i < 4; ++i) {
-            int row = t.row0 + ty + 16 * i;
-            if (row >= a.M) continue;
-            double v = sc * acc[i][j];
-            C[row] = a.accumulate ? C[row] + v : v;
-        }
+        for (int i = 0; i < 2; ++i)
+            for (int v = 0; v < 4; ++v) {
+                const int row = t.row0 + wm + 16 * i + (lane >> 4) + 4 * v;
+                if (row >= a.M) continue;
+                const double r = sc * acc[i][j][v];
+                C[row] = a.accumulate ? C[row] + r : r;
+            }
+    }
+}
+
+// sum of the split-K partial tiles in a fixed order, then scale and store/accumulate
+__global__ __launch_bounds__(256) void k_gemm_split_reduce(GemmArgs a, int split, const double* __restrict__ partial) {
+    const Tile t = a.tiles[blockIdx.x];
+    const double* P = partial + (int64_t)blockIdx.x * split * (TM * TN);
+    for (int e = threadIdx.x; e < TM * TN; e += 256) {
+        const int cc = e / TM, rr = e % TM;
+        const int row = t.row0 + rr;
+        if (cc >= t.ncol || row >= a.M) continue;
+        double s = 0.0;
+        for (int q = 0; q < split; ++q) s += P[(int64_t)q * (TM * TN) + e];
+        const int oc = a.out_col[t.col0 + cc];
+        double* C = a.C + (int64_t)oc * a.ldc;
+        const double r = a.scale[t.col0 + cc] * s;
+        C[row] = a.accumulate ? C[row] + r : r;
     }
 }
 
@@ -79,10 +156,26 @@ __global__ void k_segment_reduce(const double* __restrict__ temp, const int64_t*
 
 }  // namespace
 
-void launch_gemm(const GemmArgs& a, hipStream_t s) {
+int gemm_split_factor(int n_tiles, int K) {
+    // enough workgroups to cover the chip with at least 64 K values each
+    int s = 1;
+    while (s < 8 && n_tiles * s < 1024 && K / (2 * s) >= 64) s *= 2;
+    return s;
+}
+
+void launch_gemm(const GemmArgs& a, hipStream_t s, double* partial, int64_t partial_cap) {
     if (a.n_tiles == 0) return;
-    hipLaunchKernelGGL(k_gemm_f64, dim3(a.n_tiles), dim3(256), 0, s, a);
+    if (a.in_stride < 1 || a.in_stride > 8 || a.kblock * a.in_stride < a.K)
+        throw Error(PKIFMM_ERR_INVALID_ARG, "gemm: bad K blocking");
+    int split = partial ? gemm_split_factor(a.n_tiles, a.K) : 1;
+    if ((int64_t)a.n_tiles * split * TM * TN > partial_cap) split = 1;
+    const int per = (a.n_tiles * split + 7) / 8;
+    hipLaunchKernelGGL(k_gemm_mfma_f64, dim3(8 * per), dim3(256), 0, s, a, split, partial);
     PK_HIP(hipGetLastError());
+    if (split > 1) {
+        hipLaunchKernelGGL(k_gemm_split_reduce, dim3(a.n_tiles), dim3(256), 0, s, a, split, (const double*)partial);
+        PK_HIP(hipGetLastError());
+    }
 }
 
 void launch_segment_reduce(const double* temp, const int64_t* off, const int* boxes, int nboxes, int R, int kn,

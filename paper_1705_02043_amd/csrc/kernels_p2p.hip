@@ -50,11 +50,13 @@ __device__ __forceinline__ void interact(T tx, T ty, T tz, T sx, T sy, T sz, con
     }
 }
 
-// float32 interaction from a precomputed separation (mixed mode)
-template <int KD>
+// float32 interaction from a precomputed separation (mixed mode).  Only a leaf's own
+// segment can hold a zero separation (coincident points share a leaf; a point never
+// meets its own image), so the guard is compiled in only for that segment.
+template <int KD, bool GUARD>
 __device__ __forceinline__ void interact_d(float dx, float dy, float dz, const float* d, float* acc) {
     float r2 = dx * dx + dy * dy + dz * dz;
-    float ri = r2 > 0.f ? rsq(r2) : 0.f;
+    float ri = GUARD ? (r2 > 0.f ? rsq(r2) : 0.f) : rsq(r2);
     if constexpr (KD == 1) {
         acc[0] += d[0] * ri;
     } else {
@@ -73,7 +75,10 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r) {
     __shared__ T s_x[kThreads], s_y[kThreads], s_z[kThreads], s_d[KD][kThreads];
     __shared__ float s_lx[MIXED ? kThreads : 1], s_ly[MIXED ? kThreads : 1], s_lz[MIXED ? kThreads : 1];
 
-    const Work w = a.work[blockIdx.x];
+    // persistent: workgroup g takes items g, g + grid, ... (items are ordered longest first)
+    for (int item = blockIdx.x; item < a.n_work; item += gridDim.x) {
+    __syncthreads();
+    const Work w = a.work[item];
     const double* __restrict__ c_usurf = a.usurf;
     const int kn = KD * a.n_surf;
     const int64_t n = a.n;
@@ -140,6 +145,7 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r) {
                 lx[j] = ly[j] = lz[j] = 0.f;
             }
         }
+        const bool self_seg = seg.kind == 0 && b == w.tbox && seg.shift == 13;
         const double* phi = seg.kind == 1 ? a.phi_u : a.phi_d;
         const double sf = (seg.kind == 1 ? kInner : kOuter) * sh;
         for (int c0 = 0; c0 < count; c0 += kThreads) {
@@ -177,9 +183,15 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r) {
                         for (int c = 0; c < KD; ++c) d[c] = s_d[c][q];
                         const float sx = s_x[q], sy = s_y[q], sz = s_z[q];
                         const float slx = s_lx[q], sly = s_ly[q], slz = s_lz[q];
-                        for (int j = 0; j < kTPT; ++j)
-                            interact_d<KD>((ux[j] - sx) + (lx[j] - slx), (uy[j] - sy) + (ly[j] - sly),
-                                           (uz[j] - sz) + (lz[j] - slz), d, part[j]);
+                        if (self_seg) {
+                            for (int j = 0; j < kTPT; ++j)
+                                interact_d<KD, true>((ux[j] - sx) + (lx[j] - slx), (uy[j] - sy) + (ly[j] - sly),
+                                                     (uz[j] - sz) + (lz[j] - slz), d, part[j]);
+                        } else {
+                            for (int j = 0; j < kTPT; ++j)
+                                interact_d<KD, false>((ux[j] - sx) + (lx[j] - slx), (uy[j] - sy) + (ly[j] - sly),
+                                                      (uz[j] - sz) + (lz[j] - slz), d, part[j]);
+                        }
                     }
                     for (int j = 0; j < kTPT; ++j)
                         for (int c = 0; c < KD; ++c) acc[j][c] += (double)part[j][c];
@@ -212,19 +224,83 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r) {
             for (int c = 0; c < KD; ++c) q[c] += acc[j][c];
         }
     }
+    }   // work items
+}
+
+// Points to a surface (S2M: a leaf's own points to its upward check surface; X list:
+// leaf points to a box's downward check surface), float64.  A workgroup owns up
+// to 64 surface targets; its 256 threads form 4 groups that sweep interleaved
+// quarters of every source tile, and the four partial sums are added in a
+// fixed order at the end.
+template <int KD>
+__global__ __launch_bounds__(kThreads) void k_p2s(P2PArgs a, int r) {
+    __shared__ double s_x[kThreads], s_y[kThreads], s_z[kThreads], s_d[KD][kThreads];
+    __shared__ double s_red[4][64][KD];
+    const Work w = a.work[blockIdx.x];
+    const int kn = KD * a.n_surf;
+    const int64_t n = a.n;
+    const int tid = threadIdx.x;
+    const int lt = tid & 63, grp = tid >> 6;
+    const double th = box_h(a, w.tbox);
+    const double f = (w.tkind == 1 ? kInner : kOuter) * th;
+    const int t = w.t0 + min(lt, w.tcount - 1);
+    const double tx = (a.box_ix[w.tbox] + 0.5) * th + f * a.usurf[3 * t];
+    const double ty = (a.box_iy[w.tbox] + 0.5) * th + f * a.usurf[3 * t + 1];
+    const double tz = (a.box_iz[w.tbox] + 0.5) * th + f * a.usurf[3 * t + 2];
+    double acc[KD];
+    for (int c = 0; c < KD; ++c) acc[c] = 0.0;
+    for (int sg = w.seg0; sg < w.seg1; ++sg) {
+        const Seg seg = a.segs[sg];
+        const int b = seg.box;
+        const double shx = (double)(seg.shift / 9 - 1), shy = (double)((seg.shift / 3) % 3 - 1),
+                     shz = (double)(seg.shift % 3 - 1);
+        const double ux = tx - shx, uy = ty - shy, uz = tz - shz;
+        const int base = a.box_begin[b], count = a.box_end[b] - base;
+        for (int c0 = 0; c0 < count; c0 += kThreads) {
+            const int cnt = min(kThreads, count - c0);
+            __syncthreads();
+            if (tid < cnt) {
+                const int64_t q = base + c0 + tid;
+                s_x[tid] = a.xs[q]; s_y[tid] = a.xs[n + q]; s_z[tid] = a.xs[2 * n + q];
+                for (int c = 0; c < KD; ++c) s_d[c][tid] = a.ds[((int64_t)r * KD + c) * n + q];
+            }
+            __syncthreads();
+            for (int q = grp; q < cnt; q += 4) {
+                double d[KD];
+                for (int c = 0; c < KD; ++c) d[c] = s_d[c][q];
+                interact<KD, double>(ux, uy, uz, s_x[q], s_y[q], s_z[q], d, acc);
+            }
+        }
+    }
+    for (int c = 0; c < KD; ++c) s_red[grp][lt][c] = acc[c];
+    __syncthreads();
+    if (grp == 0 && lt < w.tcount) {
+        double* q = a.out_surf + ((int64_t)w.tbox * a.R + r) * kn + KD * (w.t0 + lt);
+        for (int c = 0; c < KD; ++c) q[c] += ((s_red[0][lt][c] + s_red[1][lt][c]) + s_red[2][lt][c]) + s_red[3][lt][c];
+    }
 }
 
 }  // namespace
 
-void launch_p2p(const P2PArgs& a, bool mixed, hipStream_t s) {
+void launch_p2s(const P2PArgs& a, hipStream_t s) {
     if (a.n_work == 0) return;
     for (int r = 0; r < a.R; ++r) {
+        if (a.kernel == PKIFMM_LAPLACE) hipLaunchKernelGGL((k_p2s<1>), dim3(a.n_work), dim3(kThreads), 0, s, a, r);
+        else hipLaunchKernelGGL((k_p2s<3>), dim3(a.n_work), dim3(kThreads), 0, s, a, r);
+        PK_HIP(hipGetLastError());
+    }
+}
+
+void launch_p2p(const P2PArgs& a, bool mixed, hipStream_t s, int max_groups) {
+    if (a.n_work == 0) return;
+    const int grid = max_groups > 0 ? std::min(a.n_work, max_groups) : a.n_work;
+    for (int r = 0; r < a.R; ++r) {
         if (a.kernel == PKIFMM_LAPLACE) {
-            if (mixed) hipLaunchKernelGGL((k_p2p<1, true>), dim3(a.n_work), dim3(kThreads), 0, s, a, r);
-            else hipLaunchKernelGGL((k_p2p<1, false>), dim3(a.n_work), dim3(kThreads), 0, s, a, r);
+            if (mixed) hipLaunchKernelGGL((k_p2p<1, true>), dim3(grid), dim3(kThreads), 0, s, a, r);
+            else hipLaunchKernelGGL((k_p2p<1, false>), dim3(grid), dim3(kThreads), 0, s, a, r);
         } else {
-            if (mixed) hipLaunchKernelGGL((k_p2p<3, true>), dim3(a.n_work), dim3(kThreads), 0, s, a, r);
-            else hipLaunchKernelGGL((k_p2p<3, false>), dim3(a.n_work), dim3(kThreads), 0, s, a, r);
+            if (mixed) hipLaunchKernelGGL((k_p2p<3, true>), dim3(grid), dim3(kThreads), 0, s, a, r);
+            else hipLaunchKernelGGL((k_p2p<3, false>), dim3(grid), dim3(kThreads), 0, s, a, r);
         }
         PK_HIP(hipGetLastError());
     }

@@ -66,7 +66,10 @@ struct P2PArgs {
     int accumulate_pts;  // add into out_pts instead of storing
     double* out_surf;    // [nbox*R][kn] check potentials (targets = surfaces), accumulated
 };
-void launch_p2p(const P2PArgs& a, bool mixed, hipStream_t s);
+// max_groups > 0: persistent launch with at most that many workgroups striding over the items
+void launch_p2p(const P2PArgs& a, bool mixed, hipStream_t s, int max_groups = 0);
+// points to surfaces only (S2M, X), float64, up to 64 targets per work item
+void launch_p2s(const P2PArgs& a, hipStream_t s);
 
 // ---- dense operator products (kernels_gemm.hip)
 struct Tile {
@@ -85,12 +88,16 @@ struct GemmArgs {
     int64_t ldc;
     const Tile* tiles;
     int n_tiles;
-    const int* in_col;
+    const int* in_col;    // 8 slots per column entry; slot kb = input column of K block kb (-1: zero)
+    int in_stride;        // K blocks used (1..8)
+    int kblock;           // rows of B per K block
     const int* out_col;
     const double* scale;
     int accumulate;       // C = scale*Op*B (+ C)
 };
-void launch_gemm(const GemmArgs& a, hipStream_t s);
+// partial: workspace for split-K partial tiles (NULL disables splitting), capacity in doubles
+void launch_gemm(const GemmArgs& a, hipStream_t s, double* partial = nullptr, int64_t partial_cap = 0);
+int gemm_split_factor(int n_tiles, int K);
 // q[b] += sum_{e in [off[b], off[b+1])} temp[e]  over R columns each; rows kn
 void launch_segment_reduce(const double* temp, const int64_t* off, const int* boxes, int nboxes,
                            int R, int kn, double* q, hipStream_t s);

@@ -14,6 +14,9 @@
 //      surfaces
 //   6. downward pass, root first: L2L from the parent, downward solve
 //   7. leaves: U-list direct sums, W-list M2T and L2T into the potentials
+// W/X-list interactions take the cheaper of their two forms: a leaf with no more
+// points than a surface acts (W) or is acted on (X) by direct sums instead of
+// through its equivalent/check surface.
 //   8. un-permute and apply 1/(4 pi) or 1/(8 pi) and 1/L
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -79,6 +82,9 @@ struct pkifmm_plan {
     int r_up = 0, r_dn = 0;
     std::string last_error;
     hipStream_t setup_stream = nullptr;
+    hipStream_t near_stream = nullptr;          // U-list near field, concurrent with the tree passes
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int n_cu = 256;
 
     // operators (device, float64, column-major kn x kn unless noted)
     DBuf<double> usurf;                 // [n][3]
@@ -111,7 +117,7 @@ struct pkifmm_plan {
     SegRange w_s2m, w_x, w_leaf_u, w_leaf_far;
     DBuf<Seg> segs;
     DBuf<Work> work;
-    std::vector<GemmRange> g_m2m[8];    // per level
+    std::vector<GemmRange> g_m2m;       // per level
     std::vector<GemmRange> g_up1, g_up2, g_dn1, g_dn2, g_l2l;   // per level
     GemmRange g_root, g_m2l;
     DBuf<Tile> tiles;
@@ -119,7 +125,7 @@ struct pkifmm_plan {
     DBuf<double> col_scale;
 
     // workspace
-    DBuf<double> ds, q_u, phi_u, q_d, phi_d, tmp, m2l_tmp, pot, sums;
+    DBuf<double> ds, q_u, phi_u, q_d, phi_d, tmp, m2l_tmp, pot, sums, split_tmp;
     DBuf<float> ds32;
 
     pkifmm_stats stats{};
@@ -201,12 +207,14 @@ int pinv_build(rocblas_handle h, hipStream_t s, const double* A_dev, int kn, dou
     return r;
 }
 
+// in: nkb input columns per output column (K blocks), -1 for a zero block
 void add_gemm(Gemm& g, int op, int M, const std::vector<int>& in, const std::vector<int>& out,
-              const std::vector<double>& sc) {
-    for (size_t c0 = 0; c0 < in.size(); c0 += 64) {
-        int ncol = (int)std::min<size_t>(64, in.size() - c0);
-        int col0 = (int)g.in.size();
-        g.in.insert(g.in.end(), in.begin() + c0, in.begin() + c0 + ncol);
+              const std::vector<double>& sc, int nkb = 1) {
+    for (size_t c0 = 0; c0 < out.size(); c0 += 64) {
+        int ncol = (int)std::min<size_t>(64, out.size() - c0);
+        int col0 = (int)g.out.size();
+        for (int c = 0; c < ncol; ++c)
+            for (int kb = 0; kb < 8; ++kb) g.in.push_back(kb < nkb ? in[(c0 + c) * nkb + kb] : -1);
         g.out.insert(g.out.end(), out.begin() + c0, out.begin() + c0 + ncol);
         g.scale.insert(g.scale.end(), sc.begin() + c0, sc.begin() + c0 + ncol);
         for (int r0 = 0; r0 < M; r0 += 64) g.tiles.push_back(Tile{op, col0, ncol, r0});
@@ -231,17 +239,21 @@ void build_work(pkifmm_plan* P, int R) {
     for (int b : t.leaves) {
         int s0 = (int)segs.size();
         segs.push_back(Seg{0, b, kSelf});
-        for (int c0 = 0; c0 < ns; c0 += 512) work.push_back(Work{b, 2, c0, std::min(512, ns - c0), s0, s0 + 1});
+        for (int c0 = 0; c0 < ns; c0 += 64) work.push_back(Work{b, 2, c0, std::min(64, ns - c0), s0, s0 + 1});
     }
     P->w_s2m.nwork = (int)work.size() - P->w_s2m.work0;
+    // W/X lists take the cheaper form of the interaction: a W-list box that is a leaf with
+    // no more points than a surface acts through its points, and a leaf with no more points
+    // than a surface takes its X-list sources directly at its points
+    auto small_leaf = [&](int b) { return t.is_leaf(b) && t.end[b] - t.begin[b] <= ns; };
     // X list: leaf points -> downward check surfaces
     P->w_x.work0 = (int)work.size();
     for (int b = 0; b < nb; ++b) {
-        if (L.x_off[b + 1] == L.x_off[b]) continue;
+        if (L.x_off[b + 1] == L.x_off[b] || small_leaf(b)) continue;
         int s0 = (int)segs.size();
         for (int64_t e = L.x_off[b]; e < L.x_off[b + 1]; ++e) segs.push_back(Seg{0, L.x[e].src, code(L.x[e])});
         int s1 = (int)segs.size();
-        for (int c0 = 0; c0 < ns; c0 += 512) work.push_back(Work{b, 1, c0, std::min(512, ns - c0), s0, s1});
+        for (int c0 = 0; c0 < ns; c0 += 64) work.push_back(Work{b, 1, c0, std::min(64, ns - c0), s0, s1});
     }
     P->w_x.nwork = (int)work.size() - P->w_x.work0;
     // leaves: U (points), W (upward equivalent surfaces), L2T (own downward equivalent surface);
@@ -250,10 +262,16 @@ void build_work(pkifmm_plan* P, int R) {
         out.work0 = (int)work.size();
         for (int b : t.leaves) {
             int s0 = (int)segs.size();
-            if (with_u)
+            if (with_u) {
                 for (int64_t e = L.u_off[b]; e < L.u_off[b + 1]; ++e) segs.push_back(Seg{0, L.u[e].src, code(L.u[e])});
+                for (int64_t e = L.w_off[b]; e < L.w_off[b + 1]; ++e)
+                    if (small_leaf(L.w[e].src)) segs.push_back(Seg{0, L.w[e].src, code(L.w[e])});
+                if (small_leaf(b))
+                    for (int64_t e = L.x_off[b]; e < L.x_off[b + 1]; ++e) segs.push_back(Seg{0, L.x[e].src, code(L.x[e])});
+            }
             if (with_far) {
-                for (int64_t e = L.w_off[b]; e < L.w_off[b + 1]; ++e) segs.push_back(Seg{1, L.w[e].src, code(L.w[e])});
+                for (int64_t e = L.w_off[b]; e < L.w_off[b + 1]; ++e)
+                    if (!small_leaf(L.w[e].src)) segs.push_back(Seg{1, L.w[e].src, code(L.w[e])});
                 segs.push_back(Seg{2, b, kSelf});
             }
             int s1 = (int)segs.size();
@@ -264,7 +282,23 @@ void build_work(pkifmm_plan* P, int R) {
         out.nwork = (int)work.size() - out.work0;
     };
     leaf_pass(P->w_leaf_u, true, false);
+    {   // longest items first, so the persistent near-field kernel ends balanced
+        auto cost = [&](const Work& w) {
+            int64_t c = 0;
+            for (int sg = w.seg0; sg < w.seg1; ++sg) c += t.end[segs[sg].box] - t.begin[segs[sg].box];
+            return c * (int64_t)w.tcount;
+        };
+        std::stable_sort(work.begin() + P->w_leaf_u.work0, work.end(),
+                         [&](const Work& x, const Work& y) { return cost(x) > cost(y); });
+    }
     leaf_pass(P->w_leaf_far, false, true);
+    {
+        int64_t np = 0;
+        for (int i = P->w_leaf_u.work0; i < P->w_leaf_u.work0 + P->w_leaf_u.nwork; ++i)
+            for (int sg = work[i].seg0; sg < work[i].seg1; ++sg)
+                np += (int64_t)work[i].tcount * (t.end[segs[sg].box] - t.begin[segs[sg].box]);
+        P->stats.near_pairs = np;
+    }
     hipStream_t s = P->setup_stream;
     P->segs.upload(segs, s);
     P->work.upload(work, s);
@@ -280,7 +314,7 @@ void build_work(pkifmm_plan* P, int R) {
         return r;
     };
     const int depth = t.depth;
-    for (int o = 0; o < 8; ++o) P->g_m2m[o].assign(depth + 1, GemmRange());
+    P->g_m2m.assign(depth + 1, GemmRange());
     P->g_up1.assign(depth + 1, GemmRange());
     P->g_up2.assign(depth + 1, GemmRange());
     P->g_dn1.assign(depth + 1, GemmRange());
@@ -289,22 +323,24 @@ void build_work(pkifmm_plan* P, int R) {
     for (int lv = 0; lv <= depth; ++lv) {
         const int b0 = t.level_start[lv], b1 = t.level_start[lv + 1];
         const double h = std::ldexp(1.0, -lv);
-        // M2M into the non-leaf boxes of this level, one octant per launch (no write conflicts)
-        for (int o = 0; o < 8; ++o)
-            P->g_m2m[o][lv] = range([&] {
-                std::vector<int> in, out;
-                std::vector<double> sc;
-                for (int b = b0; b < b1; ++b) {
-                    int c = t.child[8 * b + o];
-                    if (c < 0) continue;
-                    for (int r = 0; r < R; ++r) {
-                        in.push_back(c * R + r);
-                        out.push_back(b * R + r);
-                        sc.push_back(1.0 / h);
+        // M2M into the non-leaf boxes of this level: [M2M_0 | ... | M2M_7] times the stacked
+        // densities of the eight children (K blocked by octant), one launch
+        P->g_m2m[lv] = range([&] {
+            std::vector<int> in, out;
+            std::vector<double> sc;
+            for (int b = b0; b < b1; ++b) {
+                if (t.is_leaf(b)) continue;
+                for (int r = 0; r < R; ++r) {
+                    for (int o = 0; o < 8; ++o) {
+                        int c = t.child[8 * b + o];
+                        in.push_back(c < 0 ? -1 : c * R + r);
                     }
+                    out.push_back(b * R + r);
+                    sc.push_back(1.0 / h);
                 }
-                add_gemm(g, o, kn, in, out, sc);
-            });
+            }
+            add_gemm(g, 0, kn, in, out, sc, 8);
+        });
         std::vector<int> cols;
         std::vector<double> one, hs;
         for (int b = b0; b < b1; ++b)
@@ -385,12 +421,27 @@ void build_work(pkifmm_plan* P, int R) {
     if (P->cfg.precision == PKIFMM_MIXED) P->ds32.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
     P->pot.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
     P->sums.ensure((size_t)R * P->k);
+    {   // split-K partial tiles: the largest small launch of the tree passes
+        int64_t need = 1;
+        auto consider = [&](const GemmRange& gr, int K) {
+            if (gr.ntile == 0) return;
+            need = std::max<int64_t>(need, (int64_t)gr.ntile * gemm_split_factor(gr.ntile, K) * 64 * 64);
+        };
+        for (int lv = 0; lv <= depth; ++lv) {
+            consider(P->g_m2m[lv], 8 * kn);
+            consider(P->g_up1[lv], kn); consider(P->g_up2[lv], P->r_up);
+            consider(P->g_dn1[lv], kn); consider(P->g_dn2[lv], P->r_dn);
+            consider(P->g_l2l[lv], kn);
+        }
+        consider(P->g_root, kn);
+        P->split_tmp.ensure(need);
+    }
     PK_HIP(hipStreamSynchronize(s));
     P->R_built = R;
 }
 
 void run_gemm(pkifmm_plan* P, const GemmRange& gr, const double* ops, int64_t op_stride, int M, int K,
-              const double* B, int64_t ldb, double* C, int64_t ldc, bool acc, hipStream_t s) {
+              const double* B, int64_t ldb, double* C, int64_t ldc, bool acc, hipStream_t s, int nkb = 1) {
     if (gr.ntile == 0) return;
     GemmArgs a{};
     a.ops = ops;
@@ -404,14 +455,16 @@ void run_gemm(pkifmm_plan* P, const GemmRange& gr, const double* ops, int64_t op
     a.tiles = P->tiles.p + gr.tile0;
     a.n_tiles = gr.ntile;
     a.in_col = P->col_in.p;
+    a.in_stride = nkb;
+    a.kblock = K / nkb;
     a.out_col = P->col_out.p;
     a.scale = P->col_scale.p;
     a.accumulate = acc ? 1 : 0;
-    launch_gemm(a, s);
+    launch_gemm(a, s, P->split_tmp.p, (int64_t)P->split_tmp.n);
 }
 
 void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_surf, int R, bool f32, bool acc_pts,
-             hipStream_t s) {
+             hipStream_t s, int max_groups = 0, bool to_surface = false) {
     if (w.nwork == 0) return;
     P2PArgs a{};
     a.kernel = P->cfg.kernel;
@@ -437,7 +490,8 @@ void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_sur
     a.out_pts = out_pts;
     a.out_surf = out_surf;
     a.accumulate_pts = acc_pts ? 1 : 0;
-    launch_p2p(a, f32, s);
+    if (to_surface) launch_p2s(a, s);
+    else launch_p2p(a, f32, s, max_groups);
 }
 
 }  // namespace
@@ -474,7 +528,16 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
         P->kn = P->k * P->n_surf;
         const int kn = P->kn, ns = P->n_surf;
         PK_HIP(hipStreamCreate(&P->setup_stream));
+        // non-blocking: no implicit synchronisation with the legacy null stream; default priority
+        PK_HIP(hipStreamCreateWithFlags(&P->near_stream, hipStreamNonBlocking));
+        PK_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+        PK_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
         hipStream_t s = P->setup_stream;
+        {
+            int dev = 0;
+            PK_HIP(hipGetDevice(&dev));
+            PK_HIP(hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        }
         if (rocblas_create_handle(&h) != rocblas_status_success) throw Error(PKIFMM_ERR_HIP, "rocblas handle");
         rocblas_set_stream(h, s);
         P->usurf.upload(u, s);
@@ -526,6 +589,9 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
     } catch (const Error& e) {
         if (h) rocblas_destroy_handle(h);
         if (P->setup_stream) (void)hipStreamDestroy(P->setup_stream);
+        if (P->near_stream) (void)hipStreamDestroy(P->near_stream);
+        if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+        if (P->ev_join) (void)hipEventDestroy(P->ev_join);
         return e.code;
     } catch (const std::bad_alloc&) {
         if (h) rocblas_destroy_handle(h);
@@ -627,13 +693,14 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
         const bool mixed = P->cfg.precision == PKIFMM_MIXED;
         const bool timing = (P->cfg.flags & PKIFMM_PHASE_TIMING) != 0;
         std::vector<hipEvent_t> ev;
-        auto mark = [&]() {
+        auto mark_on = [&](hipStream_t st) {
             if (!timing) return;
             hipEvent_t e;
             PK_HIP(hipEventCreate(&e));
-            PK_HIP(hipEventRecord(e, s));
+            PK_HIP(hipEventRecord(e, st));
             ev.push_back(e);
         };
+        auto mark = [&]() { mark_on(s); };
         launch_permute_density(density, P->perm.p, n, R, k, P->ds.p, mixed ? P->ds32.p : nullptr, s);
         if (__builtin_popcount(P->cfg.periodic_mask) == 1 && !(P->cfg.flags & PKIFMM_SKIP_CHECKS)) {
             std::vector<double> sums(R * k);
@@ -646,17 +713,23 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
         }
         const size_t cols = (size_t)t.nbox() * R;
         const int64_t kk = (int64_t)kn * kn;
+        // 2. S2M first, with the whole chip (float64 direct sums feeding the upward solves)
         mark();
-        // 7a. U-list near field: depends on nothing else (float32 in the mixed mode)
-        run_p2p(P, P->w_leaf_u, P->pot.p, nullptr, R, mixed, false, s);
-        mark();
-        // 2-3. S2M and the upward pass
         PK_HIP(hipMemsetAsync(P->q_u.p, 0, sizeof(double) * cols * kn, s));
         PK_HIP(hipMemsetAsync(P->q_d.p, 0, sizeof(double) * cols * kn, s));
-        run_p2p(P, P->w_s2m, nullptr, P->q_u.p, R, false, false, s);
+        run_p2p(P, P->w_s2m, nullptr, P->q_u.p, R, false, false, s, 0, true);
+        // 7a. U-list near field: depends only on the permuted densities, so it runs on a
+        // second stream while the tree passes below run on the caller's stream
+        hipStream_t sn = P->near_stream;
+        PK_HIP(hipEventRecord(P->ev_fork, s));
+        PK_HIP(hipStreamWaitEvent(sn, P->ev_fork, 0));
+        mark_on(sn);
+        run_p2p(P, P->w_leaf_u, P->pot.p, nullptr, R, mixed, false, sn);
+        mark_on(sn);
+        PK_HIP(hipEventRecord(P->ev_join, sn));
+        // 3. upward pass
         for (int lv = t.depth; lv >= 0; --lv) {
-            for (int o = 0; o < 8; ++o)
-                run_gemm(P, P->g_m2m[o][lv], P->m2m.p + (size_t)o * kk, 0, kn, kn, P->phi_u.p, kn, P->q_u.p, kn, true, s);
+            run_gemm(P, P->g_m2m[lv], P->m2m.p, 0, kn, 8 * kn, P->phi_u.p, kn, P->q_u.p, kn, true, s, 8);
             run_gemm(P, P->g_up1[lv], P->up_Ut.p, 0, P->r_up, kn, P->q_u.p, kn, P->tmp.p, kn, false, s);
             run_gemm(P, P->g_up2[lv], P->up_VS.p, 0, kn, P->r_up, P->tmp.p, kn, P->phi_u.p, kn, false, s);
         }
@@ -667,14 +740,15 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
         launch_segment_reduce(P->m2l_tmp.p, P->v_off.p, P->v_targets.p, P->n_v_targets, R, kn, P->q_d.p, s);
         mark();
         // 5-6. X list and the downward pass
-        run_p2p(P, P->w_x, nullptr, P->q_d.p, R, false, false, s);
+        run_p2p(P, P->w_x, nullptr, P->q_d.p, R, false, false, s, 0, true);
         for (int lv = 0; lv <= t.depth; ++lv) {
             if (lv >= 1) run_gemm(P, P->g_l2l[lv], P->l2l.p, kk, kn, kn, P->phi_d.p, kn, P->q_d.p, kn, true, s);
             run_gemm(P, P->g_dn1[lv], P->dn_Ut.p, 0, P->r_dn, kn, P->q_d.p, kn, P->tmp.p, kn, false, s);
             run_gemm(P, P->g_dn2[lv], P->dn_VS.p, 0, kn, P->r_dn, P->tmp.p, kn, P->phi_d.p, kn, false, s);
         }
         mark();
-        // 7b. W list and L2T (float64: they consume equivalent densities)
+        // 7b. W list and L2T (float64: they consume equivalent densities), after the near field
+        PK_HIP(hipStreamWaitEvent(s, P->ev_join, 0));
         run_p2p(P, P->w_leaf_far, P->pot.p, nullptr, R, false, true, s);
         // 8. output
         const double c = (P->cfg.kernel == PKIFMM_LAPLACE ? 1.0 / (4.0 * M_PI) : 1.0 / (8.0 * M_PI)) / P->cfg.box_length;
@@ -697,11 +771,14 @@ int pkifmm_get_stats(pkifmm_plan* P, pkifmm_stats* out) {
         int cnt = 0;
         hipError_t bad = hipSuccess;
         for (auto& ev : P->pending_events) {
-            if (ev.size() == PKIFMM_NUM_PHASES + 1) {
+            if (ev.size() == PKIFMM_NUM_PHASES + 2) {
                 if (hipEventSynchronize(ev.back()) != hipSuccess) bad = hipErrorUnknown;
+                // ev[0]: start of the tree passes; ev[1], ev[2]: near field on its own stream;
+                // ev[3..6]: ends of the up, M2L, down and leaf phases
+                const int a[PKIFMM_NUM_PHASES] = {1, 0, 3, 4, 5}, b[PKIFMM_NUM_PHASES] = {2, 3, 4, 5, 6};
                 for (int i = 0; i < PKIFMM_NUM_PHASES && bad == hipSuccess; ++i) {
                     float ms = 0.f;
-                    if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) bad = hipErrorUnknown;
+                    if (hipEventElapsedTime(&ms, ev[a[i]], ev[b[i]]) != hipSuccess) bad = hipErrorUnknown;
                     sum[i] += ms;
                 }
                 ++cnt;
@@ -767,6 +844,9 @@ int pkifmm_plan_destroy(pkifmm_plan* P) {
     for (auto& ev : P->pending_events)
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (P->setup_stream) (void)hipStreamDestroy(P->setup_stream);
+    if (P->near_stream) (void)hipStreamDestroy(P->near_stream);
+    if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+    if (P->ev_join) (void)hipEventDestroy(P->ev_join);
     delete P;
     return PKIFMM_OK;
 }

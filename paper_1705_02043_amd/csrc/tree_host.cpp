@@ -92,28 +92,40 @@ void build_tree_host(const uint64_t* keys, int64_t n, int s, HostTree& t) {
         }
 }
 
+namespace {
+struct OffsetTable {
+    int idx[7][7][7];
+    int vec[kNumM2L][3];
+    OffsetTable() {
+        int i = 0;
+        for (int a = -3; a <= 3; ++a)
+            for (int b = -3; b <= 3; ++b)
+                for (int c = -3; c <= 3; ++c) {
+                    if (std::max(std::abs(a), std::max(std::abs(b), std::abs(c))) < 2) {
+                        idx[a + 3][b + 3][c + 3] = -1;
+                        continue;
+                    }
+                    idx[a + 3][b + 3][c + 3] = i;
+                    vec[i][0] = a; vec[i][1] = b; vec[i][2] = c;
+                    ++i;
+                }
+    }
+};
+const OffsetTable& offsets() {
+    static const OffsetTable t;
+    return t;
+}
+}  // namespace
+
+// offsets in [-3,3]^3 with |delta|_inf >= 2, numbered in lexicographic order (x slowest)
 int m2l_offset_index(int dx, int dy, int dz) {
-    int idx = 0;
-    for (int a = -3; a <= 3; ++a)
-        for (int b = -3; b <= 3; ++b)
-            for (int c = -3; c <= 3; ++c) {
-                if (std::max(std::abs(a), std::max(std::abs(b), std::abs(c))) < 2) continue;
-                if (a == dx && b == dy && c == dz) return idx;
-                ++idx;
-            }
-    return -1;
+    if (dx < -3 || dx > 3 || dy < -3 || dy > 3 || dz < -3 || dz > 3) return -1;
+    return offsets().idx[dx + 3][dy + 3][dz + 3];
 }
 
 void m2l_offset_vector(int idx, int& dx, int& dy, int& dz) {
-    int i = 0;
-    for (int a = -3; a <= 3; ++a)
-        for (int b = -3; b <= 3; ++b)
-            for (int c = -3; c <= 3; ++c) {
-                if (std::max(std::abs(a), std::max(std::abs(b), std::abs(c))) < 2) continue;
-                if (i == idx) { dx = a; dy = b; dz = c; return; }
-                ++i;
-            }
-    dx = dy = dz = 0;
+    const OffsetTable& o = offsets();
+    dx = o.vec[idx][0]; dy = o.vec[idx][1]; dz = o.vec[idx][2];
 }
 
 void build_lists_host(const HostTree& t, unsigned mask, HostLists& L) {
@@ -138,6 +150,7 @@ void build_lists_host(const HostTree& t, unsigned mask, HostLists& L) {
     };
     struct Col { int box; int p[3]; };
     std::vector<std::vector<Col>> coll(nb);
+#pragma omp parallel for schedule(dynamic, 16)
     for (int b = 0; b < nb; ++b) {
         const int lv = t.level[b];
         const int side = 1 << lv;
@@ -162,15 +175,36 @@ void build_lists_host(const HostTree& t, unsigned mask, HostLists& L) {
                 }
     }
     auto mk = [](int a, const int p[3]) { return Entry{a, (int8_t)p[0], (int8_t)p[1], (int8_t)p[2]}; };
+    // sort by (source, shift) through a packed 64-bit key (the shift code is lexicographic)
+    auto sort_entries = [](std::vector<Entry>& v) {
+        std::vector<int64_t> key(v.size());
+        for (size_t i = 0; i < v.size(); ++i)
+            key[i] = ((int64_t)v[i].src << 8) | ((v[i].sx + 1) * 9 + (v[i].sy + 1) * 3 + (v[i].sz + 1));
+        std::sort(key.begin(), key.end());
+        key.erase(std::unique(key.begin(), key.end()), key.end());
+        v.resize(key.size());
+        for (size_t i = 0; i < key.size(); ++i) {
+            int code = (int)(key[i] & 0xff);
+            v[i] = Entry{(int)(key[i] >> 8), (int8_t)(code / 9 - 1), (int8_t)((code / 3) % 3 - 1), (int8_t)(code % 3 - 1)};
+        }
+    };
     std::vector<std::vector<Entry>> U(nb), V(nb), Wl(nb), X(nb);
+#pragma omp parallel for schedule(dynamic, 8)
     for (int b = 0; b < nb; ++b) {
         if (t.level[b] >= 1) {
+            // same-level boxes: A + p is adjacent to B iff every integer offset is in [-1, 1]
+            const int side = 1 << t.level[b];
+            V[b].reserve(189);
             for (const Col& pc : coll[t.parent[b]])
                 for (int o = 0; o < 8; ++o) {
                     int a = t.child[8 * pc.box + o];
-                    if (a >= 0 && !adjacent(a, pc.p, b)) V[b].push_back(mk(a, pc.p));
+                    if (a < 0) continue;
+                    int dx = t.ix[a] + pc.p[0] * side - t.ix[b];
+                    int dy = t.iy[a] + pc.p[1] * side - t.iy[b];
+                    int dz = t.iz[a] + pc.p[2] * side - t.iz[b];
+                    if (std::abs(dx) > 1 || std::abs(dy) > 1 || std::abs(dz) > 1) V[b].push_back(mk(a, pc.p));
                 }
-            std::sort(V[b].begin(), V[b].end());
+            sort_entries(V[b]);
         }
         if (!t.is_leaf(b)) continue;
         std::vector<Col> stack(coll[b].begin(), coll[b].end());
@@ -191,14 +225,12 @@ void build_lists_host(const HostTree& t, unsigned mask, HostLists& L) {
         for (int anc = t.parent[b]; anc >= 0; anc = t.parent[anc])
             for (const Col& c : coll[anc])
                 if (t.is_leaf(c.box) && adjacent(c.box, c.p, b)) U[b].push_back(mk(c.box, c.p));
-        std::sort(U[b].begin(), U[b].end());
-        U[b].erase(std::unique(U[b].begin(), U[b].end()), U[b].end());
-        std::sort(Wl[b].begin(), Wl[b].end());
-        Wl[b].erase(std::unique(Wl[b].begin(), Wl[b].end()), Wl[b].end());
+        sort_entries(U[b]);
+        sort_entries(Wl[b]);
     }
     for (int a = 0; a < nb; ++a)
         for (const Entry& e : Wl[a]) X[e.src].push_back(Entry{a, (int8_t)-e.sx, (int8_t)-e.sy, (int8_t)-e.sz});
-    for (int b = 0; b < nb; ++b) std::sort(X[b].begin(), X[b].end());
+    for (int b = 0; b < nb; ++b) sort_entries(X[b]);
 
     auto flatten = [nb](std::vector<std::vector<Entry>>& in, std::vector<int64_t>& off, std::vector<Entry>& out) {
         off.assign(nb + 1, 0);
