@@ -106,6 +106,7 @@ typedef struct {
 
 typedef struct {
     int64_t n_points;
+    int n_problems;
     int n_boxes, n_leaves, depth;
     int64_t n_u, n_v, n_w, n_x;  /* list entries */
     int64_t u_pairs;             /* point pairs summed directly over the U lists */
@@ -143,6 +144,20 @@ int pkifmm_plan_create(const pkifmm_config *cfg, pkifmm_plan **out);
 int pkifmm_set_points(pkifmm_plan *plan, int64_t n, const double *xyz, void *stream);
 
 /*
+ * Several independent problems in one plan (the batched form): problem i owns
+ * counts[i] points, packed one problem after another in `xyz` (device,
+ * [sum counts][3] float64).  Each problem is its own periodic box [0, L)^3 with
+ * its own octree and lists; pkifmm_evaluate then evaluates every problem in
+ * one launch sequence, with densities and potentials packed the same way
+ * ([n_rhs][sum counts][k]).  A problem's result does not depend on the other
+ * problems in the batch (bitwise).  counts: host, n_problems entries >= 0.
+ * pkifmm_set_points(plan, n, xyz, s) is this call with one problem.
+ * Errors: as pkifmm_set_points.
+ */
+int pkifmm_set_points_batch(pkifmm_plan *plan, int n_problems, const int64_t *counts, const double *xyz,
+                            void *stream);
+
+/*
  * Evaluate the periodic sum for n_rhs densities on the current points.
  *   density:   device, [n_rhs][n][k] float64 (k = 1 Laplace, 3 Stokes), input order
  *   potential: device, [n_rhs][n][k] float64, overwritten, input order
@@ -165,7 +180,9 @@ int pkifmm_get_stats(pkifmm_plan *plan, pkifmm_stats *out);
  * Copy the tree to host arrays for inspection (each may be NULL):
  *   perm   [n]        int64: sorted position -> input index
  *   boxes  [nbox][8]  int32: level, ix, iy, iz, begin, end, parent, first child or -1
- * Boxes are numbered level by level, in Morton order within a level.
+ * Boxes are numbered level by level, in Morton order within a level (for a
+ * batch: level by level, problems in order within a level, Morton order
+ * within a problem; begin/end index the packed points).
  */
 int pkifmm_get_tree(const pkifmm_plan *plan, int64_t *perm, int32_t *boxes);
 

@@ -26,7 +26,8 @@ OK = 0
 ERR_INVALID_ARG, ERR_OUT_OF_BOX, ERR_INCOMPATIBLE, ERR_UNSUPPORTED = -1, -2, -3, -4
 ERR_OOM, ERR_HIP, ERR_NO_POINTS, ERR_NUMERICS = -5, -6, -7, -8
 
-EXPORTED = ["pkifmm_config_default", "pkifmm_plan_create", "pkifmm_set_points", "pkifmm_evaluate",
+EXPORTED = ["pkifmm_config_default", "pkifmm_plan_create", "pkifmm_set_points", "pkifmm_set_points_batch",
+            "pkifmm_evaluate",
             "pkifmm_get_stats", "pkifmm_get_tree", "pkifmm_get_list", "pkifmm_plan_destroy",
             "pkifmm_status_string", "pkifmm_last_error", "pkifmm_host_topology"]
 
@@ -39,7 +40,8 @@ class pkifmm_config(ctypes.Structure):
 
 
 class pkifmm_stats(ctypes.Structure):
-    _fields_ = [("n_points", ctypes.c_int64), ("n_boxes", ctypes.c_int), ("n_leaves", ctypes.c_int),
+    _fields_ = [("n_points", ctypes.c_int64), ("n_problems", ctypes.c_int),
+                ("n_boxes", ctypes.c_int), ("n_leaves", ctypes.c_int),
                 ("depth", ctypes.c_int), ("n_u", ctypes.c_int64), ("n_v", ctypes.c_int64),
                 ("n_w", ctypes.c_int64), ("n_x", ctypes.c_int64), ("u_pairs", ctypes.c_int64),
                 ("near_pairs", ctypes.c_int64),
@@ -65,6 +67,7 @@ def lib():
             "pkifmm_config_default": (i32, [ctypes.POINTER(pkifmm_config)]),
             "pkifmm_plan_create": (i32, [ctypes.POINTER(pkifmm_config), ctypes.POINTER(vp)]),
             "pkifmm_set_points": (i32, [vp, i64, vp, vp]),
+            "pkifmm_set_points_batch": (i32, [vp, i32, vp, vp, vp]),
             "pkifmm_evaluate": (i32, [vp, i32, vp, vp, vp]),
             "pkifmm_get_stats": (i32, [vp, ctypes.POINTER(pkifmm_stats)]),
             "pkifmm_get_tree": (i32, [vp, vp, vp]),
@@ -146,6 +149,18 @@ class Plan:
         xyz = xyz.contiguous()
         _check(lib().pkifmm_set_points(self._h, xyz.shape[0], ctypes.c_void_p(xyz.data_ptr()),
                                        _stream_ptr(stream)), self._h)
+        self.n = xyz.shape[0]
+
+    def set_points_batch(self, counts, xyz, stream=None):
+        """counts: point count of each problem; xyz: float64 CUDA [sum(counts), 3], problems packed."""
+        import numpy as np
+        import torch
+        assert xyz.is_cuda and xyz.dtype == torch.float64 and xyz.dim() == 2 and xyz.shape[1] == 3
+        c = np.ascontiguousarray(counts, dtype=np.int64)
+        assert int(c.sum()) == xyz.shape[0]
+        xyz = xyz.contiguous()
+        _check(lib().pkifmm_set_points_batch(self._h, len(c), c.ctypes.data, ctypes.c_void_p(xyz.data_ptr()),
+                                             _stream_ptr(stream)), self._h)
         self.n = xyz.shape[0]
 
     def evaluate(self, density, out=None, stream=None):

@@ -95,6 +95,8 @@ struct HostLists {
 
 void build_tree_host(const uint64_t* sorted_keys, int64_t n, int s, HostTree& t);
 void build_lists_host(const HostTree& t, unsigned periodic_mask, HostLists& l);
+void merge_forest(const std::vector<HostTree>& trees, const std::vector<HostLists>& lists,
+                  const std::vector<int64_t>& poff, HostTree& t, HostLists& l, std::vector<int>& box_prob);
 int m2l_offset_index(int dx, int dy, int dz);   // -> 0..315
 void m2l_offset_vector(int idx, int& dx, int& dy, int& dz);
 

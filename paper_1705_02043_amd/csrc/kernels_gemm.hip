@@ -156,11 +156,10 @@ __global__ void k_segment_reduce(const double* __restrict__ temp, const int64_t*
 
 }  // namespace
 
-int gemm_split_factor(int n_tiles, int K) {
-    // enough workgroups to cover the chip with at least 64 K values each
-    int s = 1;
-    while (s < 8 && n_tiles * s < 1024 && K / (2 * s) >= 64) s *= 2;
-    return s;
+int gemm_split_factor(int, int K) {
+    // K chunks of about 128: a function of K alone, so that the summation order (and so
+    // every result bit) does not depend on how many problems or boxes share the launch
+    return std::max(1, std::min(8, K / 128));
 }
 
 void launch_gemm(const GemmArgs& a, hipStream_t s, double* partial, int64_t partial_cap) {

@@ -1,24 +1,25 @@
 // Direct kernel sums of the evaluation pass:
-//   S2M  (leaf points -> the leaf's upward check surface),
-//   X    (leaf points  -> a box's downward check surface),
 //   U    (leaf points  -> the points of an adjacent leaf or of its image),
-//   W    (upward equivalent surface of a box -> a leaf's points),
+//   W    (a small leaf's points, or a box's upward equivalent surface -> a leaf's points),
+//   X    (leaf points  -> a small leaf's points, or a box's downward check surface),
+//   S2M  (leaf points  -> the leaf's upward check surface),
 //   L2T  (a leaf's downward equivalent surface -> its own points).
 // All are q_t = sum_s K(x_t - y_s) phi_s with the raw kernels 1/|r| and
 // I/|r| + r r^T/|r|^3 (the 1/(4 pi), 1/(8 pi) factors are applied once at the
 // end of the pass).  A zero separation contributes nothing.
 //
-// One workgroup of 256 threads owns up to 2*256 targets held in registers and
-// walks its list of source segments; each segment is staged through LDS in
-// tiles of 256 sources, loaded coalesced from the Morton-sorted SoA arrays
-// (or generated from the surface grid), and every thread sweeps the tile.
-// Sources of one tile are read by all lanes at the same LDS address
-// (broadcast, no bank conflicts).
+// Points-target kernel (k_p2p): one workgroup of 256 threads owns up to 2*256
+// targets held in registers and walks its list of source segments; each
+// segment is staged through LDS in tiles of 256 sources, loaded coalesced
+// from the Morton-sorted SoA arrays (or generated from the surface grid), and
+// every thread sweeps the tile; all lanes read the same LDS word (broadcast).
+// The geometry of a pair is computed once for a block of RB right-hand sides.
 //
-// Mixed precision: coordinates are float offsets from the target leaf centre
-// (source offsets plus the exact dyadic difference of the box centres), the
-// kernel is evaluated in float32 with v_rsq_f32, partial sums over 32 sources
-// are kept in float32 and added into float64 accumulators.
+// Mixed precision (U lists and direct W/X): coordinates are float hi + lo
+// offsets from the leaf centres (source offsets plus the exact dyadic
+// difference of the box centres), so only the final differences are rounded;
+// the kernel is evaluated in float32 with v_rsq_f32; partial sums over 32
+// sources are kept in float32 and added into float64 accumulators.
 #include "launch.h"
 
 namespace pk {
@@ -30,56 +31,43 @@ constexpr int kTPT = 2;                 // targets per thread
 constexpr double kInner = 0.525;        // half of 1.05
 constexpr double kOuter = 1.475;        // half of 2.95
 
-template <typename T> struct Vec3 { T x, y, z; };
-
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
 
-template <int KD, typename T>
-__device__ __forceinline__ void interact(T tx, T ty, T tz, T sx, T sy, T sz, const T* d, T* acc) {
-    T dx = tx - sx, dy = ty - sy, dz = tz - sz;
+// K(d) applied to RB densities; GUARD drops a zero separation.  Only a leaf's own
+// segment can hold one (coincident points share a leaf; a point never meets its
+// own image), so the guard is compiled in only for that segment.
+template <int KD, int RB, bool GUARD, typename T>
+__device__ __forceinline__ void interact(T dx, T dy, T dz, const T* d, T* acc) {
     T r2 = dx * dx + dy * dy + dz * dz;
-    T ri = r2 > T(0) ? rsq(r2) : T(0);
+    T ri = GUARD ? (r2 > T(0) ? rsq(r2) : T(0)) : rsq(r2);
     if constexpr (KD == 1) {
-        acc[0] += d[0] * ri;
+#pragma unroll
+        for (int q = 0; q < RB; ++q) acc[q] += d[q] * ri;
     } else {
-        T fdr = (d[0] * dx + d[1] * dy + d[2] * dz) * (ri * ri);
-        acc[0] += ri * (d[0] + dx * fdr);
-        acc[1] += ri * (d[1] + dy * fdr);
-        acc[2] += ri * (d[2] + dz * fdr);
-    }
-}
-
-// float32 interaction from a precomputed separation (mixed mode).  Only a leaf's own
-// segment can hold a zero separation (coincident points share a leaf; a point never
-// meets its own image), so the guard is compiled in only for that segment.
-template <int KD, bool GUARD>
-__device__ __forceinline__ void interact_d(float dx, float dy, float dz, const float* d, float* acc) {
-    float r2 = dx * dx + dy * dy + dz * dz;
-    float ri = GUARD ? (r2 > 0.f ? rsq(r2) : 0.f) : rsq(r2);
-    if constexpr (KD == 1) {
-        acc[0] += d[0] * ri;
-    } else {
-        float fdr = (d[0] * dx + d[1] * dy + d[2] * dz) * (ri * ri);
-        acc[0] += ri * (d[0] + dx * fdr);
-        acc[1] += ri * (d[1] + dy * fdr);
-        acc[2] += ri * (d[2] + dz * fdr);
+        T ri2 = ri * ri;
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const T* f = d + 3 * q;
+            T fdr = (f[0] * dx + f[1] * dy + f[2] * dz) * ri2;
+            acc[3 * q + 0] += ri * (f[0] + dx * fdr);
+            acc[3 * q + 1] += ri * (f[1] + dy * fdr);
+            acc[3 * q + 2] += ri * (f[2] + dz * fdr);
+        }
     }
 }
 
 __device__ __forceinline__ double box_h(const P2PArgs& a, int b) { return ldexp(1.0, -a.box_level[b]); }
 
-template <int KD, bool MIXED>
-__global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r) {
+template <int KD, bool MIXED, int RB>
+__global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
     using T = typename std::conditional<MIXED, float, double>::type;
-    __shared__ T s_x[kThreads], s_y[kThreads], s_z[kThreads], s_d[KD][kThreads];
+    constexpr int ND = KD * RB;
+    __shared__ T s_x[kThreads], s_y[kThreads], s_z[kThreads], s_d[ND][kThreads];
     __shared__ float s_lx[MIXED ? kThreads : 1], s_ly[MIXED ? kThreads : 1], s_lz[MIXED ? kThreads : 1];
 
-    // persistent: workgroup g takes items g, g + grid, ... (items are ordered longest first)
-    for (int item = blockIdx.x; item < a.n_work; item += gridDim.x) {
-    __syncthreads();
-    const Work w = a.work[item];
-    const double* __restrict__ c_usurf = a.usurf;
+    const Work w = a.work[blockIdx.x];
+    const double* __restrict__ usurf = a.usurf;
     const int kn = KD * a.n_surf;
     const int64_t n = a.n;
     const int tid = threadIdx.x;
@@ -90,26 +78,18 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r) {
     const double tcy = (a.box_iy[w.tbox] + 0.5) * th;
     const double tcz = (a.box_iz[w.tbox] + 0.5) * th;
 
-    double tx[kTPT], ty[kTPT], tz[kTPT];
-    double acc[kTPT][KD];
+    double tx[kTPT], ty[kTPT], tz[kTPT];   // absolute (FP64) or relative to the target centre (mixed)
+    double acc[kTPT][ND];
     for (int j = 0; j < kTPT; ++j) {
-        for (int c = 0; c < KD; ++c) acc[j][c] = 0.0;
-        int t = w.t0 + min(tid + j * kThreads, max(w.tcount - 1, 0));
-        double x, y, z;   // absolute (FP64) or relative to the target centre (mixed)
-        if (w.tkind == 0) {
-            if (MIXED) {   // hi + lo float pair, exact sum in double
-                x = (double)a.off[t] + (double)a.off[3 * n + t];
-                y = (double)a.off[n + t] + (double)a.off[4 * n + t];
-                z = (double)a.off[2 * n + t] + (double)a.off[5 * n + t];
-            } else {
-                x = a.xs[t]; y = a.xs[n + t]; z = a.xs[2 * n + t];
-            }
+        for (int c = 0; c < ND; ++c) acc[j][c] = 0.0;
+        const int t = w.t0 + min(tid + j * kThreads, max(w.tcount - 1, 0));
+        if (MIXED) {   // hi + lo float pair, exact sum in double
+            tx[j] = (double)a.off[t] + (double)a.off[3 * n + t];
+            ty[j] = (double)a.off[n + t] + (double)a.off[4 * n + t];
+            tz[j] = (double)a.off[2 * n + t] + (double)a.off[5 * n + t];
         } else {
-            double f = (w.tkind == 1 ? kInner : kOuter) * th;
-            x = f * c_usurf[3 * t]; y = f * c_usurf[3 * t + 1]; z = f * c_usurf[3 * t + 2];
-            if (!MIXED) { x += tcx; y += tcy; z += tcz; }
+            tx[j] = a.xs[t]; ty[j] = a.xs[n + t]; tz[j] = a.xs[2 * n + t];
         }
-        tx[j] = x; ty[j] = y; tz[j] = z;
     }
 
     for (int sg = w.seg0; sg < w.seg1; ++sg) {
@@ -121,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r) {
         const double scx = (a.box_ix[b] + 0.5) * sh + shx;
         const double scy = (a.box_iy[b] + 0.5) * sh + shy;
         const double scz = (a.box_iz[b] + 0.5) * sh + shz;
-        // source-centre minus target-centre: exact dyadic value (mixed mode origin shift)
+        // source-centre minus target-centre: an exact dyadic value (mixed-mode origin shift)
         const double dcx = scx - tcx, dcy = scy - tcy, dcz = scz - tcz;
         int count, base = 0;
         if (seg.kind == 0) {
@@ -130,22 +110,22 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r) {
         } else {
             count = a.n_surf;
         }
-        // per-segment target coordinates relative to the source frame; in the mixed
-        // mode a float hi + lo pair, so that only the final differences are rounded
+        const bool self_seg = seg.kind == 0 && b == w.tbox && seg.shift == 13;
+        // per-segment target coordinates in the source frame; mixed: float hi + lo pair
         T ux[kTPT], uy[kTPT], uz[kTPT];
         float lx[kTPT], ly[kTPT], lz[kTPT];
         for (int j = 0; j < kTPT; ++j) {
             if (MIXED) {
                 double vx = tx[j] - dcx, vy = ty[j] - dcy, vz = tz[j] - dcz;
                 ux[j] = (float)vx; uy[j] = (float)vy; uz[j] = (float)vz;
-                lx[j] = (float)(vx - (double)ux[j]); ly[j] = (float)(vy - (double)uy[j]);
+                lx[j] = (float)(vx - (double)ux[j]);
+                ly[j] = (float)(vy - (double)uy[j]);
                 lz[j] = (float)(vz - (double)uz[j]);
             } else {
                 ux[j] = (T)(tx[j] - shx); uy[j] = (T)(ty[j] - shy); uz[j] = (T)(tz[j] - shz);
                 lx[j] = ly[j] = lz[j] = 0.f;
             }
         }
-        const bool self_seg = seg.kind == 0 && b == w.tbox && seg.shift == 13;
         const double* phi = seg.kind == 1 ? a.phi_u : a.phi_d;
         const double sf = (seg.kind == 1 ? kInner : kOuter) * sh;
         for (int c0 = 0; c0 < count; c0 += kThreads) {
@@ -158,53 +138,55 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r) {
                     if (MIXED) {
                         s_x[tid] = a.off[q]; s_y[tid] = a.off[n + q]; s_z[tid] = a.off[2 * n + q];
                         s_lx[tid] = a.off[3 * n + q]; s_ly[tid] = a.off[4 * n + q]; s_lz[tid] = a.off[5 * n + q];
-                        for (int c = 0; c < KD; ++c) s_d[c][tid] = (T)a.ds32[((int64_t)r * KD + c) * n + q];
+                        for (int c = 0; c < ND; ++c) s_d[c][tid] = (T)a.ds32[((int64_t)r0 * KD + c) * n + q];
                     } else {
                         s_x[tid] = a.xs[q]; s_y[tid] = a.xs[n + q]; s_z[tid] = a.xs[2 * n + q];
-                        for (int c = 0; c < KD; ++c) s_d[c][tid] = (T)a.ds[((int64_t)r * KD + c) * n + q];
+                        for (int c = 0; c < ND; ++c) s_d[c][tid] = (T)a.ds[((int64_t)r0 * KD + c) * n + q];
                     }
-                } else {
-                    double px = sf * c_usurf[3 * s], py = sf * c_usurf[3 * s + 1], pz = sf * c_usurf[3 * s + 2];
-                    if (!MIXED) { px += scx - shx; py += scy - shy; pz += scz - shz; }
-                    s_x[tid] = (T)px; s_y[tid] = (T)py; s_z[tid] = (T)pz;
-                    const double* src = phi + ((int64_t)b * a.R + r) * kn + KD * s;
-                    for (int c = 0; c < KD; ++c) s_d[c][tid] = (T)src[c];
+                } else {   // surface sources exist only in the float64 passes
+                    s_x[tid] = (T)(sf * usurf[3 * s] + scx - shx);
+                    s_y[tid] = (T)(sf * usurf[3 * s + 1] + scy - shy);
+                    s_z[tid] = (T)(sf * usurf[3 * s + 2] + scz - shz);
+                    for (int q = 0; q < RB; ++q) {
+                        const double* src = phi + ((int64_t)b * a.R + r0 + q) * kn + KD * s;
+                        for (int c = 0; c < KD; ++c) s_d[KD * q + c][tid] = (T)src[c];
+                    }
                 }
             }
             __syncthreads();
             if constexpr (MIXED) {
                 for (int j0 = 0; j0 < cnt; j0 += 32) {
                     const int j1 = min(cnt, j0 + 32);
-                    T part[kTPT][KD];
+                    T part[kTPT][ND];
                     for (int j = 0; j < kTPT; ++j)
-                        for (int c = 0; c < KD; ++c) part[j][c] = T(0);
+                        for (int c = 0; c < ND; ++c) part[j][c] = T(0);
                     for (int q = j0; q < j1; ++q) {
-                        T d[KD];
-                        for (int c = 0; c < KD; ++c) d[c] = s_d[c][q];
+                        T d[ND];
+                        for (int c = 0; c < ND; ++c) d[c] = s_d[c][q];
                         const float sx = s_x[q], sy = s_y[q], sz = s_z[q];
                         const float slx = s_lx[q], sly = s_ly[q], slz = s_lz[q];
                         if (self_seg) {
                             for (int j = 0; j < kTPT; ++j)
-                                interact_d<KD, true>((ux[j] - sx) + (lx[j] - slx), (uy[j] - sy) + (ly[j] - sly),
-                                                     (uz[j] - sz) + (lz[j] - slz), d, part[j]);
+                                interact<KD, RB, true, T>((ux[j] - sx) + (lx[j] - slx), (uy[j] - sy) + (ly[j] - sly),
+                                                          (uz[j] - sz) + (lz[j] - slz), d, part[j]);
                         } else {
                             for (int j = 0; j < kTPT; ++j)
-                                interact_d<KD, false>((ux[j] - sx) + (lx[j] - slx), (uy[j] - sy) + (ly[j] - sly),
-                                                      (uz[j] - sz) + (lz[j] - slz), d, part[j]);
+                                interact<KD, RB, false, T>((ux[j] - sx) + (lx[j] - slx), (uy[j] - sy) + (ly[j] - sly),
+                                                           (uz[j] - sz) + (lz[j] - slz), d, part[j]);
                         }
                     }
                     for (int j = 0; j < kTPT; ++j)
-                        for (int c = 0; c < KD; ++c) acc[j][c] += (double)part[j][c];
+                        for (int c = 0; c < ND; ++c) acc[j][c] += (double)part[j][c];
                 }
             } else {
                 for (int q = 0; q < cnt; ++q) {
-                    T d[KD];
-                    for (int c = 0; c < KD; ++c) d[c] = s_d[c][q];
+                    T d[ND];
+                    for (int c = 0; c < ND; ++c) d[c] = s_d[c][q];
                     for (int j = 0; j < kTPT; ++j) {
-                        T part[KD];
-                        for (int c = 0; c < KD; ++c) part[c] = acc[j][c];
-                        interact<KD, T>(ux[j], uy[j], uz[j], s_x[q], s_y[q], s_z[q], d, part);
-                        for (int c = 0; c < KD; ++c) acc[j][c] = part[c];
+                        if (self_seg)
+                            interact<KD, RB, true, T>(ux[j] - s_x[q], uy[j] - s_y[q], uz[j] - s_z[q], d, acc[j]);
+                        else
+                            interact<KD, RB, false, T>(ux[j] - s_x[q], uy[j] - s_y[q], uz[j] - s_z[q], d, acc[j]);
                     }
                 }
             }
@@ -214,17 +196,11 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r) {
         const int lt = tid + j * kThreads;
         if (lt >= w.tcount) continue;
         const int t = w.t0 + lt;
-        if (w.tkind == 0) {
-            for (int c = 0; c < KD; ++c) {
-                double* o = a.out_pts + ((int64_t)r * KD + c) * n + t;
-                *o = a.accumulate_pts ? *o + acc[j][c] : acc[j][c];
-            }
-        } else {
-            double* q = a.out_surf + ((int64_t)w.tbox * a.R + r) * kn + KD * t;
-            for (int c = 0; c < KD; ++c) q[c] += acc[j][c];
+        for (int c = 0; c < ND; ++c) {
+            double* o = a.out_pts + ((int64_t)r0 * KD + c) * n + t;
+            *o = a.accumulate_pts ? *o + acc[j][c] : acc[j][c];
         }
     }
-    }   // work items
 }
 
 // Points to a surface (S2M: a leaf's own points to its upward check surface; X list:
@@ -268,7 +244,7 @@ __global__ __launch_bounds__(kThreads) void k_p2s(P2PArgs a, int r) {
             for (int q = grp; q < cnt; q += 4) {
                 double d[KD];
                 for (int c = 0; c < KD; ++c) d[c] = s_d[c][q];
-                interact<KD, double>(ux, uy, uz, s_x[q], s_y[q], s_z[q], d, acc);
+                interact<KD, 1, true, double>(ux - s_x[q], uy - s_y[q], uz - s_z[q], d, acc);
             }
         }
     }
@@ -277,6 +253,26 @@ __global__ __launch_bounds__(kThreads) void k_p2s(P2PArgs a, int r) {
     if (grp == 0 && lt < w.tcount) {
         double* q = a.out_surf + ((int64_t)w.tbox * a.R + r) * kn + KD * (w.t0 + lt);
         for (int c = 0; c < KD; ++c) q[c] += ((s_red[0][lt][c] + s_red[1][lt][c]) + s_red[2][lt][c]) + s_red[3][lt][c];
+    }
+}
+
+template <int KD, bool MIXED, int RB>
+void launch_block(const P2PArgs& a, int r0, hipStream_t s) {
+    hipLaunchKernelGGL((k_p2p<KD, MIXED, RB>), dim3(a.n_work), dim3(kThreads), 0, s, a, r0);
+    PK_HIP(hipGetLastError());
+}
+
+template <int KD, bool MIXED>
+void launch_rhs(const P2PArgs& a, hipStream_t s) {
+    // right-hand sides in blocks: up to 16 (Laplace) or 4 (Stokes) share one geometry pass
+    int r0 = 0;
+    while (r0 < a.R) {
+        const int left = a.R - r0;
+        if (KD == 1 && left >= 16) { launch_block<KD, MIXED, 16>(a, r0, s); r0 += 16; }
+        else if (KD == 1 && left >= 8) { launch_block<KD, MIXED, 8>(a, r0, s); r0 += 8; }
+        else if (left >= 4) { launch_block<KD, MIXED, 4>(a, r0, s); r0 += 4; }
+        else if (left >= 2) { launch_block<KD, MIXED, 2>(a, r0, s); r0 += 2; }
+        else { launch_block<KD, MIXED, 1>(a, r0, s); r0 += 1; }
     }
 }
 
@@ -291,18 +287,14 @@ void launch_p2s(const P2PArgs& a, hipStream_t s) {
     }
 }
 
-void launch_p2p(const P2PArgs& a, bool mixed, hipStream_t s, int max_groups) {
+void launch_p2p(const P2PArgs& a, bool mixed, hipStream_t s) {
     if (a.n_work == 0) return;
-    const int grid = max_groups > 0 ? std::min(a.n_work, max_groups) : a.n_work;
-    for (int r = 0; r < a.R; ++r) {
-        if (a.kernel == PKIFMM_LAPLACE) {
-            if (mixed) hipLaunchKernelGGL((k_p2p<1, true>), dim3(grid), dim3(kThreads), 0, s, a, r);
-            else hipLaunchKernelGGL((k_p2p<1, false>), dim3(grid), dim3(kThreads), 0, s, a, r);
-        } else {
-            if (mixed) hipLaunchKernelGGL((k_p2p<3, true>), dim3(grid), dim3(kThreads), 0, s, a, r);
-            else hipLaunchKernelGGL((k_p2p<3, false>), dim3(grid), dim3(kThreads), 0, s, a, r);
-        }
-        PK_HIP(hipGetLastError());
+    if (a.kernel == PKIFMM_LAPLACE) {
+        if (mixed) launch_rhs<1, true>(a, s);
+        else launch_rhs<1, false>(a, s);
+    } else {
+        if (mixed) launch_rhs<3, true>(a, s);
+        else launch_rhs<3, false>(a, s);
     }
 }
 

@@ -2,6 +2,7 @@
 // gathers and density permutations.  All are HBM-bound streaming kernels with
 // one point per thread and coalesced SoA accesses.
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include "launch.h"
 
@@ -100,19 +101,20 @@ __global__ void k_unpermute(const double* __restrict__ pot, const uint32_t* __re
             out[((int64_t)r * n + j) * k + c] = scale * pot[((int64_t)r * k + c) * n + i];
 }
 
-// one workgroup per (rhs, component); deterministic tree reduction in LDS
-__global__ void k_density_sums(const double* __restrict__ ds, int64_t n, double* __restrict__ out) {
+// one workgroup per (problem, rhs x component); deterministic tree reduction in LDS
+__global__ void k_density_sums(const double* __restrict__ ds, int64_t n, const int64_t* __restrict__ off,
+                               double* __restrict__ out) {
     __shared__ double sh[256];
-    const double* src = ds + (int64_t)blockIdx.x * n;
+    const double* src = ds + (int64_t)blockIdx.y * n;
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) acc += src[i];
+    for (int64_t i = off[blockIdx.x] + threadIdx.x; i < off[blockIdx.x + 1]; i += 256) acc += src[i];
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * gridDim.y + blockIdx.y] = sh[0];
 }
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -127,9 +129,17 @@ void launch_keys(const double* xyz, int64_t n, double L, unsigned mask, uint64_t
 }
 
 void radix_sort_pairs(uint64_t* kin, uint64_t* kout, uint32_t* vin, uint32_t* vout, int64_t n, DBuf<char>& temp,
-                      hipStream_t s) {
+                      hipStream_t s, int n_seg, const int64_t* off) {
     if (n == 0) return;
     size_t bytes = 0;
+    if (n_seg > 1) {
+        PK_HIP(rocprim::segmented_radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, (unsigned)n, (unsigned)n_seg,
+                                                   off, off + 1, 0, 63, s));
+        temp.ensure(bytes);
+        PK_HIP(rocprim::segmented_radix_sort_pairs(temp.p, bytes, kin, kout, vin, vout, (unsigned)n, (unsigned)n_seg,
+                                                   off, off + 1, 0, 63, s));
+        return;
+    }
     PK_HIP(rocprim::radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, (size_t)n, 0, 63, s));
     temp.ensure(bytes);
     PK_HIP(rocprim::radix_sort_pairs(temp.p, bytes, kin, kout, vin, vout, (size_t)n, 0, 63, s));
@@ -162,8 +172,9 @@ void launch_unpermute(const double* pot, const uint32_t* perm, int64_t n, int R,
     PK_HIP(hipGetLastError());
 }
 
-void launch_density_sums(const double* ds, int64_t n, int R, int k, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_density_sums, dim3(R * k), dim3(256), 0, s, ds, n, out);
+void launch_density_sums(const double* ds, int64_t n, int R, int k, const int64_t* off, int n_prob, double* out,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_density_sums, dim3(n_prob, R * k), dim3(256), 0, s, ds, n, off, out);
     PK_HIP(hipGetLastError());
 }
 

@@ -12,9 +12,10 @@ namespace pk {
 // set for a coordinate outside the box or not finite.
 void launch_keys(const double* xyz, int64_t n, double L, unsigned mask, uint64_t* keys,
                  uint32_t* vals, double* u, int* err, hipStream_t s);
-// Stable radix sort of (key, index) pairs; temp storage is grown as needed.
+// Stable radix sort of (key, index) pairs; temp storage is grown as needed.  With
+// n_seg > 1 each segment [off[i], off[i+1]) is sorted on its own (off: device, n_seg+1).
 void radix_sort_pairs(uint64_t* keys_in, uint64_t* keys_out, uint32_t* vals_in, uint32_t* vals_out,
-                      int64_t n, DBuf<char>& temp, hipStream_t s);
+                      int64_t n, DBuf<char>& temp, hipStream_t s, int n_seg = 1, const int64_t* off = nullptr);
 // Sorted SoA coordinates xs[3][n] = u[:, perm]; per-point float offsets from the
 // centre of the point's leaf (pt_box[sorted index] gives the leaf box).
 void launch_gather_points(const double* u, const uint32_t* perm, int64_t n, double* xs, hipStream_t s);
@@ -26,8 +27,10 @@ void launch_permute_density(const double* dens, const uint32_t* perm, int64_t n,
 // pot_sorted [R][k][n] -> out [R][n][k] input order, times scale
 void launch_unpermute(const double* pot, const uint32_t* perm, int64_t n, int R, int k, double scale,
                       double* out, hipStream_t s);
-// per-RHS, per-component sums of the sorted densities (neutrality check): out [R*k]
-void launch_density_sums(const double* ds, int64_t n, int R, int k, double* out, hipStream_t s);
+// per-problem, per-RHS, per-component sums of the sorted densities (neutrality check):
+// out [n_prob][R*k]; problem i owns sorted points [off[i], off[i+1]) (off: device)
+void launch_density_sums(const double* ds, int64_t n, int R, int k, const int64_t* off, int n_prob, double* out,
+                         hipStream_t s);
 
 // ---- direct interactions (kernels_p2p.hip)
 struct Seg {         // one source segment
@@ -66,8 +69,8 @@ struct P2PArgs {
     int accumulate_pts;  // add into out_pts instead of storing
     double* out_surf;    // [nbox*R][kn] check potentials (targets = surfaces), accumulated
 };
-// max_groups > 0: persistent launch with at most that many workgroups striding over the items
-void launch_p2p(const P2PArgs& a, bool mixed, hipStream_t s, int max_groups = 0);
+// right-hand sides are processed in blocks that share each pair's geometry
+void launch_p2p(const P2PArgs& a, bool mixed, hipStream_t s);
 // points to surfaces only (S2M, X), float64, up to 64 targets per work item
 void launch_p2s(const P2PArgs& a, hipStream_t s);
 

@@ -93,8 +93,12 @@ struct pkifmm_plan {
     DBuf<double> m2l;                   // [316][kn*kn]
     DBuf<double> mroot;                 // [kn*kn]
 
-    // points and tree
+    // points and tree (a forest: one tree per problem, boxes numbered level-major)
     int64_t n = 0;
+    int n_problems = 1;
+    std::vector<int64_t> prob_off_h;
+    DBuf<int64_t> prob_off;
+    std::vector<int> box_prob;
     bool have_points = false;
     HostTree tree;
     HostLists lists;
@@ -372,13 +376,14 @@ void build_work(pkifmm_plan* P, int R) {
                 }
             });
     }
-    P->g_root = range([&] {
+    P->g_root = range([&] {   // every problem's root
         std::vector<int> c;
         std::vector<double> one;
-        for (int r = 0; r < R; ++r) {
-            c.push_back(r);
-            one.push_back(1.0);
-        }
+        for (int b = t.level_start[0]; b < t.level_start[1]; ++b)
+            for (int r = 0; r < R; ++r) {
+                c.push_back(b * R + r);
+                one.push_back(1.0);
+            }
         add_gemm(g, 0, kn, c, c, one);
     });
     // M2L grouped by offset; output column = V-list entry (summed per target afterwards)
@@ -420,7 +425,7 @@ void build_work(pkifmm_plan* P, int R) {
     P->ds.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
     if (P->cfg.precision == PKIFMM_MIXED) P->ds32.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
     P->pot.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
-    P->sums.ensure((size_t)R * P->k);
+    P->sums.ensure((size_t)P->n_problems * R * P->k);
     {   // split-K partial tiles: the largest small launch of the tree passes
         int64_t need = 1;
         auto consider = [&](const GemmRange& gr, int K) {
@@ -464,7 +469,7 @@ void run_gemm(pkifmm_plan* P, const GemmRange& gr, const double* ops, int64_t op
 }
 
 void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_surf, int R, bool f32, bool acc_pts,
-             hipStream_t s, int max_groups = 0, bool to_surface = false) {
+             hipStream_t s, bool to_surface = false) {
     if (w.nwork == 0) return;
     P2PArgs a{};
     a.kernel = P->cfg.kernel;
@@ -491,7 +496,7 @@ void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_sur
     a.out_surf = out_surf;
     a.accumulate_pts = acc_pts ? 1 : 0;
     if (to_surface) launch_p2s(a, s);
-    else launch_p2p(a, f32, s, max_groups);
+    else launch_p2p(a, f32, s);
 }
 
 }  // namespace
@@ -602,14 +607,29 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
 }
 
 int pkifmm_set_points(pkifmm_plan* P, int64_t n, const double* xyz, void* stream) {
+    if (n < 0) return P ? fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n")) : PKIFMM_ERR_INVALID_ARG;
+    return pkifmm_set_points_batch(P, 1, &n, xyz, stream);
+}
+
+int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* counts, const double* xyz, void* stream) {
     if (!P) return PKIFMM_ERR_INVALID_ARG;
-    if (n < 0 || n > (int64_t)INT32_MAX || (n > 0 && !xyz)) return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n or xyz"));
+    if (n_problems < 1 || !counts) return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n_problems or counts"));
+    std::vector<int64_t> poff(n_problems + 1, 0);
+    for (int i = 0; i < n_problems; ++i) {
+        if (counts[i] < 0) return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "negative count"));
+        poff[i + 1] = poff[i] + counts[i];
+    }
+    const int64_t n = poff[n_problems];
+    if (n > (int64_t)INT32_MAX || (n > 0 && !xyz)) return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n or xyz"));
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
     try {
         P->have_points = false;
         P->R_built = -1;
         P->n = n;
+        P->n_problems = n_problems;
+        P->prob_off_h = poff;
+        P->prob_off.upload(poff, s);
         const size_t m = std::max<int64_t>(n, 1);
         P->keys_a.ensure(m);
         P->keys_b.ensure(m);
@@ -622,14 +642,28 @@ int pkifmm_set_points(pkifmm_plan* P, int64_t n, const double* xyz, void* stream
                     P->err_flag.p, s);
         int err = 0;
         PK_HIP(hipMemcpyAsync(&err, P->err_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
-        radix_sort_pairs(P->keys_a.p, P->keys_b.p, P->vals_a.p, P->perm.p, n, P->sort_temp, s);
+        // each problem's points are sorted on their own (segmented sort for a batch)
+        radix_sort_pairs(P->keys_a.p, P->keys_b.p, P->vals_a.p, P->perm.p, n, P->sort_temp, s, n_problems,
+                         P->prob_off.p);
         launch_gather_points(P->u_wrapped.p, P->perm.p, n, P->xs.p, s);
         std::vector<uint64_t> keys(n);
         if (n) PK_HIP(hipMemcpyAsync(keys.data(), P->keys_b.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
         PK_HIP(hipStreamSynchronize(s));
         if (err) throw Error(PKIFMM_ERR_OUT_OF_BOX, "coordinate outside the box on a non-periodic axis, or not finite");
-        build_tree_host(keys.data(), n, P->cfg.max_pts_per_leaf, P->tree);
-        build_lists_host(P->tree, P->cfg.periodic_mask, P->lists);
+        if (n_problems == 1) {
+            build_tree_host(keys.data(), n, P->cfg.max_pts_per_leaf, P->tree);
+            build_lists_host(P->tree, P->cfg.periodic_mask, P->lists);
+            P->box_prob.assign(P->tree.nbox(), 0);
+        } else {
+            std::vector<HostTree> trees(n_problems);
+            std::vector<HostLists> lists(n_problems);
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int q = 0; q < n_problems; ++q) {
+                build_tree_host(keys.data() + poff[q], poff[q + 1] - poff[q], P->cfg.max_pts_per_leaf, trees[q]);
+                build_lists_host(trees[q], P->cfg.periodic_mask, lists[q]);
+            }
+            merge_forest(trees, lists, poff, P->tree, P->lists, P->box_prob);
+        }
         const HostTree& t = P->tree;
         P->b_level.upload(t.level, s);
         P->b_ix.upload(t.ix, s);
@@ -655,6 +689,7 @@ int pkifmm_set_points(pkifmm_plan* P, int64_t n, const double* xyz, void* stream
         P->have_points = true;
         auto& st = P->stats;
         st.n_points = n;
+        st.n_problems = n_problems;
         st.n_boxes = t.nbox();
         st.n_leaves = (int)t.leaves.size();
         st.depth = t.depth;
@@ -703,13 +738,17 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
         auto mark = [&]() { mark_on(s); };
         launch_permute_density(density, P->perm.p, n, R, k, P->ds.p, mixed ? P->ds32.p : nullptr, s);
         if (__builtin_popcount(P->cfg.periodic_mask) == 1 && !(P->cfg.flags & PKIFMM_SKIP_CHECKS)) {
-            std::vector<double> sums(R * k);
-            launch_density_sums(P->ds.p, n, R, k, P->sums.p, s);
-            PK_HIP(hipMemcpyAsync(sums.data(), P->sums.p, sizeof(double) * R * k, hipMemcpyDeviceToHost, s));
+            const int np = P->n_problems;
+            std::vector<double> sums((size_t)np * R * k);
+            launch_density_sums(P->ds.p, n, R, k, P->prob_off.p, np, P->sums.p, s);
+            PK_HIP(hipMemcpyAsync(sums.data(), P->sums.p, sizeof(double) * sums.size(), hipMemcpyDeviceToHost, s));
             PK_HIP(hipStreamSynchronize(s));
-            for (int i = 0; i < R * k; ++i)
-                if (!(std::fabs(sums[i]) <= 1e-10 * std::max(1.0, (double)n)))
-                    throw Error(PKIFMM_ERR_INCOMPATIBLE, "singly periodic input needs a zero net density");
+            for (int q = 0; q < np; ++q) {
+                const double cnt = (double)(P->prob_off_h[q + 1] - P->prob_off_h[q]);
+                for (int i = 0; i < R * k; ++i)
+                    if (!(std::fabs(sums[(size_t)q * R * k + i]) <= 1e-10 * std::max(1.0, cnt)))
+                        throw Error(PKIFMM_ERR_INCOMPATIBLE, "singly periodic input needs a zero net density");
+            }
         }
         const size_t cols = (size_t)t.nbox() * R;
         const int64_t kk = (int64_t)kn * kn;
@@ -717,7 +756,7 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
         mark();
         PK_HIP(hipMemsetAsync(P->q_u.p, 0, sizeof(double) * cols * kn, s));
         PK_HIP(hipMemsetAsync(P->q_d.p, 0, sizeof(double) * cols * kn, s));
-        run_p2p(P, P->w_s2m, nullptr, P->q_u.p, R, false, false, s, 0, true);
+        run_p2p(P, P->w_s2m, nullptr, P->q_u.p, R, false, false, s, true);
         // 7a. U-list near field: depends only on the permuted densities, so it runs on a
         // second stream while the tree passes below run on the caller's stream
         hipStream_t sn = P->near_stream;
@@ -740,7 +779,7 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
         launch_segment_reduce(P->m2l_tmp.p, P->v_off.p, P->v_targets.p, P->n_v_targets, R, kn, P->q_d.p, s);
         mark();
         // 5-6. X list and the downward pass
-        run_p2p(P, P->w_x, nullptr, P->q_d.p, R, false, false, s, 0, true);
+        run_p2p(P, P->w_x, nullptr, P->q_d.p, R, false, false, s, true);
         for (int lv = 0; lv <= t.depth; ++lv) {
             if (lv >= 1) run_gemm(P, P->g_l2l[lv], P->l2l.p, kk, kn, kn, P->phi_d.p, kn, P->q_d.p, kn, true, s);
             run_gemm(P, P->g_dn1[lv], P->dn_Ut.p, 0, P->r_dn, kn, P->q_d.p, kn, P->tmp.p, kn, false, s);

@@ -287,3 +287,82 @@ extern "C" int pkifmm_host_topology(const uint64_t* keys, int64_t n, int s, unsi
     }
     return PKIFMM_OK;
 }
+
+namespace pk {
+
+// Several independent trees as one forest: boxes renumbered level-major (all
+// problems' level-0 boxes, then level 1, ...), problems in order within a
+// level, each problem's own (level, Morton) order kept; point ranges shifted by
+// the problem offsets.  Lists only ever connect boxes of one problem.
+void merge_forest(const std::vector<HostTree>& trees, const std::vector<HostLists>& lists,
+                  const std::vector<int64_t>& poff, HostTree& t, HostLists& L, std::vector<int>& box_prob) {
+    const int np = (int)trees.size();
+    int depth = 0;
+    for (const HostTree& q : trees) depth = std::max(depth, q.depth);
+    std::vector<std::vector<int>> gid(np);
+    for (int q = 0; q < np; ++q) gid[q].assign(trees[q].nbox(), -1);
+    t = HostTree();
+    box_prob.clear();
+    std::vector<std::pair<int, int>> src;   // global -> (problem, local)
+    for (int lv = 0; lv <= depth; ++lv) {
+        t.level_start.push_back((int)src.size());
+        for (int q = 0; q < np; ++q) {
+            const HostTree& a = trees[q];
+            if (lv > a.depth) continue;
+            for (int b = a.level_start[lv]; b < a.level_start[lv + 1]; ++b) {
+                gid[q][b] = (int)src.size();
+                src.push_back({q, b});
+            }
+        }
+    }
+    t.level_start.push_back((int)src.size());
+    t.depth = depth;
+    const int nb = (int)src.size();
+    t.level.resize(nb); t.ix.resize(nb); t.iy.resize(nb); t.iz.resize(nb);
+    t.begin.resize(nb); t.end.resize(nb); t.parent.resize(nb); t.child.assign(8 * (size_t)nb, -1);
+    box_prob.resize(nb);
+    for (int g = 0; g < nb; ++g) {
+        const int q = src[g].first, b = src[g].second;
+        const HostTree& a = trees[q];
+        t.level[g] = a.level[b]; t.ix[g] = a.ix[b]; t.iy[g] = a.iy[b]; t.iz[g] = a.iz[b];
+        t.begin[g] = (int)(a.begin[b] + poff[q]);
+        t.end[g] = (int)(a.end[b] + poff[q]);
+        t.parent[g] = a.parent[b] < 0 ? -1 : gid[q][a.parent[b]];
+        for (int o = 0; o < 8; ++o) {
+            int c = a.child[8 * b + o];
+            t.child[8 * g + o] = c < 0 ? -1 : gid[q][c];
+        }
+        box_prob[g] = q;
+    }
+    t.leaf_id.assign(nb, -1);
+    for (int g = 0; g < nb; ++g)
+        if (t.is_leaf(g)) {
+            t.leaf_id[g] = (int)t.leaves.size();
+            t.leaves.push_back(g);
+        }
+    auto merge = [&](auto off_of, auto ent_of, std::vector<int64_t>& off, std::vector<Entry>& ent) {
+        off.assign(nb + 1, 0);
+        ent.clear();
+        for (int g = 0; g < nb; ++g) {
+            const int q = src[g].first, b = src[g].second;
+            const std::vector<int64_t>& lo = off_of(lists[q]);
+            const std::vector<Entry>& le = ent_of(lists[q]);
+            for (int64_t e = lo[b]; e < lo[b + 1]; ++e) {
+                Entry x = le[e];
+                x.src = gid[q][x.src];
+                ent.push_back(x);
+            }
+            off[g + 1] = (int64_t)ent.size();
+        }
+    };
+    merge([](const HostLists& l) -> const std::vector<int64_t>& { return l.u_off; },
+          [](const HostLists& l) -> const std::vector<Entry>& { return l.u; }, L.u_off, L.u);
+    merge([](const HostLists& l) -> const std::vector<int64_t>& { return l.v_off; },
+          [](const HostLists& l) -> const std::vector<Entry>& { return l.v; }, L.v_off, L.v);
+    merge([](const HostLists& l) -> const std::vector<int64_t>& { return l.w_off; },
+          [](const HostLists& l) -> const std::vector<Entry>& { return l.w; }, L.w_off, L.w);
+    merge([](const HostLists& l) -> const std::vector<int64_t>& { return l.x_off; },
+          [](const HostLists& l) -> const std::vector<Entry>& { return l.x; }, L.x_off, L.x);
+}
+
+}  // namespace pk

@@ -191,3 +191,96 @@ def test_full_size_stokes_tp_sampled(precision, tol):
     err = np.sqrt(num / den)
     print(f"full-size precision={precision} sampled rel L2 {err:.3e} over {len(pick)} leaves", flush=True)
     assert err < tol
+
+
+def _batch(sizes, seed, n_rhs, s=40, p=6):
+    rng = np.random.default_rng(seed)
+    pts, dens = [], []
+    for n in sizes:
+        pts.append(rng.random((n, 3)))
+        q = rng.uniform(-1, 1, (n_rhs, n))
+        if n:
+            q -= q.mean(axis=1, keepdims=True)
+        dens.append(q[:, :, None])
+    return pts, dens
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6)])
+def test_batch_of_uneven_problems(precision, tol):
+    """Independent Laplace SP problems of uneven N (one empty, one tiny) in one plan, 3 RHS."""
+    pk = _pk()
+    sizes = [3000, 0, 7, 12000, 500]
+    pts, dens = _batch(sizes, 31, 3)
+    plan = pk.Plan(pk.LAPLACE, pk.PERIODIC_X, 6, 40, precision=precision)
+    plan.set_points_batch(sizes, _dev(np.concatenate(pts)))
+    out = plan.evaluate(_dev(np.concatenate(dens, axis=1))).cpu().numpy()
+    assert plan.stats()["n_problems"] == len(sizes)
+    _, boxes = plan.tree()
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    # problem of each box: the level-0 boxes are the problems' roots, in order
+    prob = np.zeros(boxes.shape[0], dtype=int)
+    for b in range(boxes.shape[0]):
+        prob[b] = b if boxes[b, 0] == 0 else prob[boxes[b, 6]]
+    assert np.sum(boxes[:, 0] == 0) == len(sizes)
+    for i, n in enumerate(sizes):
+        if n == 0:
+            assert boxes[i, 4] == boxes[i, 5] == off[i]
+            continue
+        f = okifmm.KIFMM(1, 1, 6, 40, pts[i])
+        # this problem's boxes, in global order, reproduce the oracle's tree
+        mine = [b for b in range(boxes.shape[0]) if prob[b] == i]
+        rows = boxes[mine].copy()
+        rows[:, 4:6] -= off[i]
+        assert rows.shape[0] == f.tree.nbox
+        for j, b in enumerate(range(f.tree.nbox)):
+            t = f.tree
+            assert list(rows[j][:6]) == [t.level[b], *t.coord[b], t.begin[b], t.end[b]]
+        for r in range(3):
+            ref = f.evaluate(dens[i][r])
+            got = out[r, off[i]:off[i + 1]]
+            assert _rel(got, ref) < tol, (i, r, _rel(got, ref))
+
+
+def test_batch_result_is_bitwise_independent_of_the_batch():
+    pk = _pk()
+    sizes = [5000, 800, 20000]
+    pts, dens = _batch(sizes, 32, 2, s=60)
+    plan = pk.Plan(pk.LAPLACE, pk.PERIODIC_X, 6, 60, precision=1)
+    plan.set_points_batch(sizes, _dev(np.concatenate(pts)))
+    out = plan.evaluate(_dev(np.concatenate(dens, axis=1))).cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    for i in (0, 2):
+        solo = pk.Plan(pk.LAPLACE, pk.PERIODIC_X, 6, 60, precision=1)
+        solo.set_points(_dev(pts[i]))
+        o = solo.evaluate(_dev(dens[i])).cpu().numpy()
+        assert np.array_equal(o, out[:, off[i]:off[i + 1]]), i
+
+
+def test_sixteen_rhs_laplace():
+    """16 right-hand sides share each pair's geometry in the near-field kernel."""
+    pb = W.laplace_sp_uniform(n=6000, seed=33, p=6, s=80, n_rhs=16)
+    for precision, tol in ((0, 1e-10), (1, 1e-6)):
+        _, out = _run(pb, precision)
+        f = okifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+        for r in (0, 7, 15):
+            assert _rel(out[r], f.evaluate(pb.density[r])) < tol
+
+
+def test_batched_config_sampled():
+    """64 Laplace SP problems, N log-uniform in [1e4, 1e6], 16 RHS, p = 8, s = 2000; the three
+    smallest problems checked against the oracle for all 16 right-hand sides."""
+    pk = _pk()
+    probs = W.laplace_sp_batch()
+    sizes = [pb.n for pb in probs]
+    plan = pk.Plan(pk.LAPLACE, pk.PERIODIC_X, 8, 2000, precision=1)
+    plan.set_points_batch(sizes, _dev(np.concatenate([pb.points for pb in probs])))
+    out = plan.evaluate(_dev(np.concatenate([pb.density for pb in probs], axis=1))).cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    print(f"batched: {len(sizes)} problems, {off[-1]} points, stats {plan.stats()}", flush=True)
+    for i in np.argsort(sizes)[:3]:
+        pb = probs[i]
+        f = okifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+        ref = np.stack([f.evaluate(pb.density[r]) for r in range(16)])
+        err = _rel(out[:, off[i]:off[i + 1]], ref)
+        print(f"problem {i} N={pb.n} mixed rel L2 {err:.3e}", flush=True)
+        assert err < 1e-6
