@@ -100,6 +100,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (a plain copy kernel of known size, "
+                         "to calibrate rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -108,6 +111,12 @@ def main():
     import torch
     import paper_1705_02043_amd as pk
     import workloads as W
+    if args.copy_calibration_mib:
+        src = torch.ones(args.copy_calibration_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     pb = W.stokes_tp_uniform()
     log(f"workload {pb.name}: N={pb.n} p={pb.p} s={pb.s}")
     r64, out64 = time_form(pk, torch, pb, pk.FP64, args.steps, args.warmup)

@@ -94,6 +94,9 @@ typedef struct {
 #define PKIFMM_SKIP_CHECKS 1u    /* skip the SP neutrality check (no device-to-host read) */
 #define PKIFMM_PHASE_TIMING 2u   /* record HIP events around the phases of every evaluate on its
                                     stream; pkifmm_get_stats waits for them and reports averages */
+#define PKIFMM_GRAPH 4u          /* pkifmm_evaluate captures its launch sequence into a HIP graph
+                                    (once per points/n_rhs/density/potential pointers) and replays
+                                    it on `stream`; implies no neutrality check and no phase timing */
 
 /* phases of one evaluation; the near field runs on a library-owned second stream,
  * concurrently with the other phases, which run in this order on the caller's stream */

@@ -27,6 +27,7 @@ struct Error : std::runtime_error {
 
 constexpr int kMaxLevel = 21;
 constexpr int kNumM2L = 316;   // offsets in [-3,3]^3 with |delta|_inf >= 2
+constexpr int kM2LGroups = 8;  // fixed groups of offsets per M2L launch (bounded temporary)
 
 // Device buffer owned by a plan.
 template <class T>

@@ -117,9 +117,20 @@ __global__ void k_density_sums(const double* __restrict__ ds, int64_t n, const i
     if (threadIdx.x == 0) out[(int64_t)blockIdx.x * gridDim.y + blockIdx.y] = sh[0];
 }
 
+__global__ void k_fill_zero(double* __restrict__ x, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = 0.0;
+}
+
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
+
+void launch_fill_zero(double* x, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<int64_t>(nblk(n, 256), 4096)), dim3(256), 0, s, x, n);
+    PK_HIP(hipGetLastError());
+}
 
 void launch_keys(const double* xyz, int64_t n, double L, unsigned mask, uint64_t* keys, uint32_t* vals, double* u,
                  int* err, hipStream_t s) {

@@ -84,6 +84,13 @@ struct pkifmm_plan {
     hipStream_t setup_stream = nullptr;
     hipStream_t near_stream = nullptr;          // U-list near field, concurrent with the tree passes
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t capture_stream = nullptr;      // PKIFMM_GRAPH: the evaluation is captured here
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int g_key_R = 0;
+    const double* g_key_in = nullptr;
+    double* g_key_out = nullptr;
+    uint64_t g_key_gen = 0, generation = 0;
     int n_cu = 256;
 
     // operators (device, float64, column-major kn x kn unless noted)
@@ -123,7 +130,12 @@ struct pkifmm_plan {
     DBuf<Work> work;
     std::vector<GemmRange> g_m2m;       // per level
     std::vector<GemmRange> g_up1, g_up2, g_dn1, g_dn2, g_l2l;   // per level
-    GemmRange g_root, g_m2l;
+    GemmRange g_root;
+    std::vector<GemmRange> g_m2l;                        // per offset group
+    std::vector<std::pair<int, int>> m2l_targets;        // per group: (first, count) in v_gtargets
+    DBuf<int64_t> v_goff;                                // per group: CSR over boxes of temp slots
+    DBuf<int> v_gtargets;
+    int m2l_slots = 1;
     DBuf<Tile> tiles;
     DBuf<int> col_in, col_out;
     DBuf<double> col_scale;
@@ -386,11 +398,18 @@ void build_work(pkifmm_plan* P, int R) {
             }
         add_gemm(g, 0, kn, c, c, one);
     });
-    // M2L grouped by offset; output column = V-list entry (summed per target afterwards)
-    P->g_m2l = range([&] {
+    // M2L grouped by offset; the 316 offsets are split into kM2LGroups fixed groups (by offset
+    // index, so the per-target summation order never depends on the batch).  Within a group,
+    // output column = the entry's slot in the group (a bounded temporary), summed per target
+    // afterwards in entry order; groups are added to q_d one after another.
+    {
         std::vector<std::vector<int>> in(kNumM2L), out(kNumM2L);
         std::vector<std::vector<double>> sc(kNumM2L);
-        for (int b = 0; b < nb; ++b)
+        std::vector<int64_t> goff((size_t)kM2LGroups * (nb + 1), 0);
+        std::vector<int> slot_count(kM2LGroups, 0);
+        std::vector<std::vector<int>> gtarg(kM2LGroups);
+        for (int b = 0; b < nb; ++b) {
+            for (int q = 0; q < kM2LGroups; ++q) goff[(size_t)q * (nb + 1) + b] = slot_count[q];
             for (int64_t e = L.v_off[b]; e < L.v_off[b + 1]; ++e) {
                 const Entry& v = L.v[e];
                 const int lv = t.level[b];
@@ -400,15 +419,35 @@ void build_work(pkifmm_plan* P, int R) {
                 int dz = t.iz[v.src] + v.sz * side - t.iz[b];
                 int idx = m2l_offset_index(dx, dy, dz);
                 if (idx < 0) throw Error(PKIFMM_ERR_NUMERICS, "V-list offset out of range");
+                const int q = idx * kM2LGroups / kNumM2L;
+                const int slot = slot_count[q]++;
                 for (int r = 0; r < R; ++r) {
                     in[idx].push_back(v.src * R + r);
-                    out[idx].push_back((int)(e * R + r));
+                    out[idx].push_back(slot * R + r);
                     sc[idx].push_back(std::ldexp(1.0, lv));
                 }
             }
-        for (int d = 0; d < kNumM2L; ++d)
-            if (!in[d].empty()) add_gemm(g, d, kn, in[d], out[d], sc[d]);
-    });
+            for (int q = 0; q < kM2LGroups; ++q)
+                if (slot_count[q] > goff[(size_t)q * (nb + 1) + b]) gtarg[q].push_back(b);
+        }
+        for (int q = 0; q < kM2LGroups; ++q) goff[(size_t)q * (nb + 1) + nb] = slot_count[q];
+        P->g_m2l.assign(kM2LGroups, GemmRange());
+        P->m2l_targets.assign(kM2LGroups, {});
+        int max_slots = 1;
+        std::vector<int> all_targets;
+        for (int q = 0; q < kM2LGroups; ++q) {
+            P->g_m2l[q] = range([&] {
+                for (int d = 0; d < kNumM2L; ++d)
+                    if (d * kM2LGroups / kNumM2L == q && !in[d].empty()) add_gemm(g, d, kn, in[d], out[d], sc[d]);
+            });
+            P->m2l_targets[q] = {(int)all_targets.size(), (int)gtarg[q].size()};
+            all_targets.insert(all_targets.end(), gtarg[q].begin(), gtarg[q].end());
+            max_slots = std::max(max_slots, slot_count[q]);
+        }
+        P->v_goff.upload(goff, s);
+        P->v_gtargets.upload(all_targets, s);
+        P->m2l_slots = max_slots;
+    }
     P->tiles.upload(g.tiles, s);
     P->col_in.upload(g.in, s);
     P->col_out.upload(g.out, s);
@@ -421,7 +460,7 @@ void build_work(pkifmm_plan* P, int R) {
     P->q_d.ensure(cols * kn);
     P->phi_d.ensure(cols * kn);
     P->tmp.ensure(cols * kn);
-    P->m2l_tmp.ensure(std::max<size_t>(1, (size_t)L.v.size() * R * kn));
+    P->m2l_tmp.ensure(std::max<size_t>(1, (size_t)P->m2l_slots * R * kn));
     P->ds.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
     if (P->cfg.precision == PKIFMM_MIXED) P->ds32.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
     P->pot.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
@@ -446,7 +485,8 @@ void build_work(pkifmm_plan* P, int R) {
 }
 
 void run_gemm(pkifmm_plan* P, const GemmRange& gr, const double* ops, int64_t op_stride, int M, int K,
-              const double* B, int64_t ldb, double* C, int64_t ldc, bool acc, hipStream_t s, int nkb = 1) {
+              const double* B, int64_t ldb, double* C, int64_t ldc, bool acc, hipStream_t s, int nkb = 1,
+              bool allow_split = true) {
     if (gr.ntile == 0) return;
     GemmArgs a{};
     a.ops = ops;
@@ -465,7 +505,9 @@ void run_gemm(pkifmm_plan* P, const GemmRange& gr, const double* ops, int64_t op
     a.out_col = P->col_out.p;
     a.scale = P->col_scale.p;
     a.accumulate = acc ? 1 : 0;
-    launch_gemm(a, s, P->split_tmp.p, (int64_t)P->split_tmp.n);
+    // the per-level launches split K (latency-bound, few tiles); M2L never does
+    if (allow_split) launch_gemm(a, s, P->split_tmp.p, (int64_t)P->split_tmp.n);
+    else launch_gemm(a, s);
 }
 
 void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_surf, int R, bool f32, bool acc_pts,
@@ -497,6 +539,99 @@ void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_sur
     a.accumulate_pts = acc_pts ? 1 : 0;
     if (to_surface) launch_p2s(a, s);
     else launch_p2p(a, f32, s);
+}
+
+}  // namespace
+
+namespace {
+
+void drop_graph(pkifmm_plan* P) {
+    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    P->gexec = nullptr;
+    P->graph = nullptr;
+}
+
+// Enqueue one evaluation on stream s (no host synchronisation unless `checks`).
+void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* potential, hipStream_t s, bool checks,
+                      bool allow_timing) {
+        const int64_t n = P->n;
+        const int k = P->k, kn = P->kn;
+        const HostTree& t = P->tree;
+        const bool mixed = P->cfg.precision == PKIFMM_MIXED;
+        const bool timing = allow_timing && (P->cfg.flags & PKIFMM_PHASE_TIMING) != 0;
+        std::vector<hipEvent_t> ev;
+        auto mark_on = [&](hipStream_t st) {
+            if (!timing) return;
+            hipEvent_t e;
+            PK_HIP(hipEventCreate(&e));
+            PK_HIP(hipEventRecord(e, st));
+            ev.push_back(e);
+        };
+        auto mark = [&]() { mark_on(s); };
+        launch_permute_density(density, P->perm.p, n, R, k, P->ds.p, mixed ? P->ds32.p : nullptr, s);
+        if (checks && __builtin_popcount(P->cfg.periodic_mask) == 1 && !(P->cfg.flags & PKIFMM_SKIP_CHECKS)) {
+            const int np = P->n_problems;
+            std::vector<double> sums((size_t)np * R * k);
+            launch_density_sums(P->ds.p, n, R, k, P->prob_off.p, np, P->sums.p, s);
+            PK_HIP(hipMemcpyAsync(sums.data(), P->sums.p, sizeof(double) * sums.size(), hipMemcpyDeviceToHost, s));
+            PK_HIP(hipStreamSynchronize(s));
+            for (int q = 0; q < np; ++q) {
+                const double cnt = (double)(P->prob_off_h[q + 1] - P->prob_off_h[q]);
+                for (int i = 0; i < R * k; ++i)
+                    if (!(std::fabs(sums[(size_t)q * R * k + i]) <= 1e-10 * std::max(1.0, cnt)))
+                        throw Error(PKIFMM_ERR_INCOMPATIBLE, "singly periodic input needs a zero net density");
+            }
+        }
+        const size_t cols = (size_t)t.nbox() * R;
+        const int64_t kk = (int64_t)kn * kn;
+        // 2. S2M first, with the whole chip (float64 direct sums feeding the upward solves)
+        mark();
+        launch_fill_zero(P->q_u.p, (int64_t)cols * kn, s);     // kernels, not memset nodes (graph-safe)
+        launch_fill_zero(P->q_d.p, (int64_t)cols * kn, s);
+        run_p2p(P, P->w_s2m, nullptr, P->q_u.p, R, false, false, s, true);
+        // 7a. U-list near field: depends only on the permuted densities, so it runs on a
+        // second stream while the tree passes below run on the caller's stream
+        hipStream_t sn = P->near_stream;
+        PK_HIP(hipEventRecord(P->ev_fork, s));
+        PK_HIP(hipStreamWaitEvent(sn, P->ev_fork, 0));
+        mark_on(sn);
+        run_p2p(P, P->w_leaf_u, P->pot.p, nullptr, R, mixed, false, sn);
+        mark_on(sn);
+        PK_HIP(hipEventRecord(P->ev_join, sn));
+        // 3. upward pass
+        for (int lv = t.depth; lv >= 0; --lv) {
+            run_gemm(P, P->g_m2m[lv], P->m2m.p, 0, kn, 8 * kn, P->phi_u.p, kn, P->q_u.p, kn, true, s, 8);
+            run_gemm(P, P->g_up1[lv], P->up_Ut.p, 0, P->r_up, kn, P->q_u.p, kn, P->tmp.p, kn, false, s);
+            run_gemm(P, P->g_up2[lv], P->up_VS.p, 0, kn, P->r_up, P->tmp.p, kn, P->phi_u.p, kn, false, s);
+        }
+        mark();
+        // 4-5. root far field and V-list M2L
+        run_gemm(P, P->g_root, P->mroot.p, 0, kn, kn, P->phi_u.p, kn, P->q_d.p, kn, true, s);
+        for (int q = 0; q < kM2LGroups; ++q) {
+            if (P->g_m2l[q].ntile == 0) continue;
+            run_gemm(P, P->g_m2l[q], P->m2l.p, kk, kn, kn, P->phi_u.p, kn, P->m2l_tmp.p, kn, false, s, 1, false);
+            launch_segment_reduce(P->m2l_tmp.p, P->v_goff.p + (size_t)q * (t.nbox() + 1),
+                                  P->v_gtargets.p + P->m2l_targets[q].first, P->m2l_targets[q].second, R, kn,
+                                  P->q_d.p, s);
+        }
+        mark();
+        // 5-6. X list and the downward pass
+        run_p2p(P, P->w_x, nullptr, P->q_d.p, R, false, false, s, true);
+        for (int lv = 0; lv <= t.depth; ++lv) {
+            if (lv >= 1) run_gemm(P, P->g_l2l[lv], P->l2l.p, kk, kn, kn, P->phi_d.p, kn, P->q_d.p, kn, true, s);
+            run_gemm(P, P->g_dn1[lv], P->dn_Ut.p, 0, P->r_dn, kn, P->q_d.p, kn, P->tmp.p, kn, false, s);
+            run_gemm(P, P->g_dn2[lv], P->dn_VS.p, 0, kn, P->r_dn, P->tmp.p, kn, P->phi_d.p, kn, false, s);
+        }
+        mark();
+        // 7b. W list and L2T (float64: they consume equivalent densities), after the near field
+        PK_HIP(hipStreamWaitEvent(s, P->ev_join, 0));
+        run_p2p(P, P->w_leaf_far, P->pot.p, nullptr, R, false, true, s);
+        // 8. output
+        const double c = (P->cfg.kernel == PKIFMM_LAPLACE ? 1.0 / (4.0 * M_PI) : 1.0 / (8.0 * M_PI)) / P->cfg.box_length;
+        launch_unpermute(P->pot.p, P->perm.p, n, R, k, c, potential, s);
+        mark();
+        if (timing) P->pending_events.push_back(ev);
 }
 
 }  // namespace
@@ -535,6 +670,7 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
         PK_HIP(hipStreamCreate(&P->setup_stream));
         // non-blocking: no implicit synchronisation with the legacy null stream; default priority
         PK_HIP(hipStreamCreateWithFlags(&P->near_stream, hipStreamNonBlocking));
+        PK_HIP(hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking));
         PK_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
         PK_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
         hipStream_t s = P->setup_stream;
@@ -595,6 +731,7 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
         if (h) rocblas_destroy_handle(h);
         if (P->setup_stream) (void)hipStreamDestroy(P->setup_stream);
         if (P->near_stream) (void)hipStreamDestroy(P->near_stream);
+        if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
         if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
         if (P->ev_join) (void)hipEventDestroy(P->ev_join);
         return e.code;
@@ -626,6 +763,8 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
     try {
         P->have_points = false;
         P->R_built = -1;
+        ++P->generation;
+        drop_graph(P);
         P->n = n;
         P->n_problems = n_problems;
         P->prob_off_h = poff;
@@ -720,80 +859,35 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
     try {
-        const int64_t n = P->n;
-        const int k = P->k, kn = P->kn;
-        if (n == 0) return PKIFMM_OK;
+        if (P->n == 0) return PKIFMM_OK;
         if (P->R_built != R) build_work(P, R);
-        const HostTree& t = P->tree;
-        const bool mixed = P->cfg.precision == PKIFMM_MIXED;
-        const bool timing = (P->cfg.flags & PKIFMM_PHASE_TIMING) != 0;
-        std::vector<hipEvent_t> ev;
-        auto mark_on = [&](hipStream_t st) {
-            if (!timing) return;
-            hipEvent_t e;
-            PK_HIP(hipEventCreate(&e));
-            PK_HIP(hipEventRecord(e, st));
-            ev.push_back(e);
-        };
-        auto mark = [&]() { mark_on(s); };
-        launch_permute_density(density, P->perm.p, n, R, k, P->ds.p, mixed ? P->ds32.p : nullptr, s);
-        if (__builtin_popcount(P->cfg.periodic_mask) == 1 && !(P->cfg.flags & PKIFMM_SKIP_CHECKS)) {
-            const int np = P->n_problems;
-            std::vector<double> sums((size_t)np * R * k);
-            launch_density_sums(P->ds.p, n, R, k, P->prob_off.p, np, P->sums.p, s);
-            PK_HIP(hipMemcpyAsync(sums.data(), P->sums.p, sizeof(double) * sums.size(), hipMemcpyDeviceToHost, s));
-            PK_HIP(hipStreamSynchronize(s));
-            for (int q = 0; q < np; ++q) {
-                const double cnt = (double)(P->prob_off_h[q + 1] - P->prob_off_h[q]);
-                for (int i = 0; i < R * k; ++i)
-                    if (!(std::fabs(sums[(size_t)q * R * k + i]) <= 1e-10 * std::max(1.0, cnt)))
-                        throw Error(PKIFMM_ERR_INCOMPATIBLE, "singly periodic input needs a zero net density");
+        if (!(P->cfg.flags & PKIFMM_GRAPH)) {
+            enqueue_evaluate(P, R, density, potential, s, true, true);
+        } else {
+            // captured once per (tree, R, buffers) on a library stream, replayed on the caller's
+            const bool same = P->gexec && P->g_key_R == R && P->g_key_in == density && P->g_key_out == potential &&
+                              P->g_key_gen == P->generation;
+            if (!same) {
+                drop_graph(P);
+                hipStream_t cs = P->capture_stream;
+                PK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+                try {
+                    enqueue_evaluate(P, R, density, potential, cs, false, false);
+                } catch (...) {
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(cs, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                PK_HIP(hipStreamEndCapture(cs, &P->graph));
+                PK_HIP(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+                P->g_key_R = R;
+                P->g_key_in = density;
+                P->g_key_out = potential;
+                P->g_key_gen = P->generation;
             }
+            PK_HIP(hipGraphLaunch(P->gexec, s));
         }
-        const size_t cols = (size_t)t.nbox() * R;
-        const int64_t kk = (int64_t)kn * kn;
-        // 2. S2M first, with the whole chip (float64 direct sums feeding the upward solves)
-        mark();
-        PK_HIP(hipMemsetAsync(P->q_u.p, 0, sizeof(double) * cols * kn, s));
-        PK_HIP(hipMemsetAsync(P->q_d.p, 0, sizeof(double) * cols * kn, s));
-        run_p2p(P, P->w_s2m, nullptr, P->q_u.p, R, false, false, s, true);
-        // 7a. U-list near field: depends only on the permuted densities, so it runs on a
-        // second stream while the tree passes below run on the caller's stream
-        hipStream_t sn = P->near_stream;
-        PK_HIP(hipEventRecord(P->ev_fork, s));
-        PK_HIP(hipStreamWaitEvent(sn, P->ev_fork, 0));
-        mark_on(sn);
-        run_p2p(P, P->w_leaf_u, P->pot.p, nullptr, R, mixed, false, sn);
-        mark_on(sn);
-        PK_HIP(hipEventRecord(P->ev_join, sn));
-        // 3. upward pass
-        for (int lv = t.depth; lv >= 0; --lv) {
-            run_gemm(P, P->g_m2m[lv], P->m2m.p, 0, kn, 8 * kn, P->phi_u.p, kn, P->q_u.p, kn, true, s, 8);
-            run_gemm(P, P->g_up1[lv], P->up_Ut.p, 0, P->r_up, kn, P->q_u.p, kn, P->tmp.p, kn, false, s);
-            run_gemm(P, P->g_up2[lv], P->up_VS.p, 0, kn, P->r_up, P->tmp.p, kn, P->phi_u.p, kn, false, s);
-        }
-        mark();
-        // 4-5. root far field and V-list M2L
-        run_gemm(P, P->g_root, P->mroot.p, 0, kn, kn, P->phi_u.p, kn, P->q_d.p, kn, true, s);
-        run_gemm(P, P->g_m2l, P->m2l.p, kk, kn, kn, P->phi_u.p, kn, P->m2l_tmp.p, kn, false, s);
-        launch_segment_reduce(P->m2l_tmp.p, P->v_off.p, P->v_targets.p, P->n_v_targets, R, kn, P->q_d.p, s);
-        mark();
-        // 5-6. X list and the downward pass
-        run_p2p(P, P->w_x, nullptr, P->q_d.p, R, false, false, s, true);
-        for (int lv = 0; lv <= t.depth; ++lv) {
-            if (lv >= 1) run_gemm(P, P->g_l2l[lv], P->l2l.p, kk, kn, kn, P->phi_d.p, kn, P->q_d.p, kn, true, s);
-            run_gemm(P, P->g_dn1[lv], P->dn_Ut.p, 0, P->r_dn, kn, P->q_d.p, kn, P->tmp.p, kn, false, s);
-            run_gemm(P, P->g_dn2[lv], P->dn_VS.p, 0, kn, P->r_dn, P->tmp.p, kn, P->phi_d.p, kn, false, s);
-        }
-        mark();
-        // 7b. W list and L2T (float64: they consume equivalent densities), after the near field
-        PK_HIP(hipStreamWaitEvent(s, P->ev_join, 0));
-        run_p2p(P, P->w_leaf_far, P->pot.p, nullptr, R, false, true, s);
-        // 8. output
-        const double c = (P->cfg.kernel == PKIFMM_LAPLACE ? 1.0 / (4.0 * M_PI) : 1.0 / (8.0 * M_PI)) / P->cfg.box_length;
-        launch_unpermute(P->pot.p, P->perm.p, n, R, k, c, potential, s);
-        mark();
-        if (timing) P->pending_events.push_back(ev);
     } catch (const Error& e) {
         return fail(P, e);
     } catch (const std::bad_alloc&) {
@@ -882,8 +976,10 @@ int pkifmm_plan_destroy(pkifmm_plan* P) {
     if (!P) return PKIFMM_OK;
     for (auto& ev : P->pending_events)
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    drop_graph(P);
     if (P->setup_stream) (void)hipStreamDestroy(P->setup_stream);
     if (P->near_stream) (void)hipStreamDestroy(P->near_stream);
+    if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
     if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
     if (P->ev_join) (void)hipEventDestroy(P->ev_join);
     delete P;

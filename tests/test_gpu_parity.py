@@ -284,3 +284,36 @@ def test_batched_config_sampled():
         err = _rel(out[:, off[i]:off[i + 1]], ref)
         print(f"problem {i} N={pb.n} mixed rel L2 {err:.3e}", flush=True)
         assert err < 1e-6
+
+
+def test_graph_replay_matches_eager():
+    """PKIFMM_GRAPH: captured once, replayed; each replay bitwise equal to the eager evaluation,
+    with unrelated eager GPU work between replays; new points trigger a new capture."""
+    pk = _pk()
+    pb = W.stokes_tp_uniform(n=20000, seed=34, p=6, s=300)
+    eager = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=1)
+    eager.set_points(_dev(pb.points))
+    ref = eager.evaluate(_dev(pb.density)).cpu().numpy()
+    g = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=1, flags=pk.GRAPH)
+    g.set_points(_dev(pb.points))
+    dens = _dev(pb.density)
+    out = torch.empty_like(dens)
+    for i in range(4):
+        g.evaluate(dens, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref), i
+        x = torch.randn(512, 512, device="cuda")
+        (x @ x).sum().item()                         # eager work between replays
+        out.zero_()
+    dens.mul_(2.0)                                   # in-place change of the captured input
+    g.evaluate(dens, out=out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), 2.0 * ref)
+    pts2 = np.mod(pb.points + 0.123, 1.0)
+    g.set_points(_dev(pts2))
+    eager.set_points(_dev(pts2))
+    ref2 = eager.evaluate(dens).cpu().numpy()
+    for _ in range(2):
+        g.evaluate(dens, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref2)
