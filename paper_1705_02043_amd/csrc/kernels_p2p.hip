@@ -32,7 +32,16 @@ constexpr double kInner = 0.525;        // half of 1.05
 constexpr double kOuter = 1.475;        // half of 2.95
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+// 1/sqrt(x) in float64 without branches: the hardware estimate v_rsq_f64 refined by two
+// Newton steps y <- y + y (1 - x y^2) / 2 (each roughly doubles the correct bits).  Valid for
+// the normal, positive x that occur here (separations >= ~1e-7); x = 0 is guarded by callers.
+__device__ __forceinline__ double rsq(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
 
 // K(d) applied to RB densities; GUARD drops a zero separation.  Only a leaf's own
 // segment can hold one (coincident points share a leaf; a point never meets its

@@ -317,3 +317,30 @@ def test_graph_replay_matches_eager():
         g.evaluate(dens, out=out)
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy(), ref2)
+
+
+@pytest.mark.timeout(1100)
+def test_clustered_stokes_p12_sampled():
+    """N = 16M Stokes TP points as 200 Gaussian clusters (sigma 0.02) + 20 % uniform, 4 force-free
+    RHS, p = 12, s = 2000 (deep adaptive tree with W/X lists), mixed form; every target of 3
+    random leaves checked against the oracle for all 4 RHS."""
+    pk = _pk()
+    pb = W.stokes_tp_clustered()
+    plan = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=1)
+    plan.set_points(_dev(pb.points))
+    out = plan.evaluate(_dev(pb.density)).cpu().numpy()
+    st = plan.stats()
+    print(f"clustered p=12: {st}", flush=True)
+    f = okifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+    leaves = f.tree.leaves()
+    pick = [leaves[i] for i in sorted(np.random.default_rng(3).choice(len(leaves), 3, replace=False))]
+    num = den = 0.0
+    for r in range(pb.density.shape[0]):
+        sub = f.evaluate(pb.density[r], target_leaves=pick)
+        for b, ref in sub.items():
+            idx = f.tree.perm[f.tree.begin[b]:f.tree.end[b]]
+            num += np.sum((out[r][idx] - ref) ** 2)
+            den += np.sum(ref ** 2)
+    err = np.sqrt(num / den)
+    print(f"clustered p=12 mixed sampled rel L2 {err:.3e} over {len(pick)} leaves x 4 RHS", flush=True)
+    assert err < 1e-6
