@@ -20,7 +20,14 @@ Conventions that the paper leaves to the cited Ewald literature:
         S^F(r) = S(r) - S^R(r),    c = 2 xi / sqrt(pi),   S^F(0) = 2c I
         K^P(r) = sum_p S^R(r - p)/(8 pi) + sum_{k != 0} (I - k k^T/k^2) / k^2 (1 + k^2/(4 xi^2)) e^{-k^2/(4 xi^2)} cos(k.r)
     with k in 2 pi Z^3 (unit cell, unit viscosity);
-  * triply periodic Laplace: standard Ewald with the k = 0 mode removed.
+  * triply periodic Laplace: standard Ewald with the k = 0 mode removed;
+  * doubly periodic (DP) Stokes and Laplace: the same real-space splits summed
+    over the in-plane lattice, and the Fourier part over in-plane wave vectors
+    k != 0 with the k_z integral done in closed form (below).  The k = 0 mode
+    and the additive constant follow the definition of the sum itself: the
+    limit of symmetric in-plane image sums, each image regularised by its
+    value at the lattice point, G(r) + sum_{p != 0} [G(r - p) - G(p)]; for a
+    net-force-free (or neutral) set of sources the subtracted terms cancel.
 A coincident pair contributes nothing from its own singular term, but every
 other image of it is kept.
 """
@@ -201,6 +208,162 @@ def tp_laplace_sum(r: np.ndarray, xi: float = 4.0, far_only: bool = False, exclu
     return out
 
 
+# ---------------------------------------------------------------- doubly periodic
+#
+# Frame: the two periodic axes first, the free axis last (z).  For an
+# in-plane wave vector k with kappa = |k| > 0 define, with
+# u+- = kappa/(2 xi) +- xi z,
+#     E = e^{kappa z} erfc(u+) + e^{-kappa z} erfc(u-),   D = e^{kappa z} erfc(u+) - e^{-kappa z} erfc(u-),
+#     g = exp(-kappa^2/(4 xi^2) - xi^2 z^2).
+# Then (1/2pi) int dk_z cos(k_z z) e^{-|k|^2/4xi^2}/|k|^2 = E/(4 kappa)           (the 2D Ewald kernel),
+#      A = (1/2pi) int cos(k_z z) H/|k|^2 = E/(4 kappa) + g/(4 xi sqrt(pi)),
+#      B = (1/2pi) int cos(k_z z) H/|k|^4 = -dA_0/d(kappa^2)
+#        = E/(8 kappa^3) - z D/(8 kappa^2) + g/(4 xi sqrt(pi) kappa^2),      dB/dz = -z E/(8 kappa),
+# with H = (1 + |k|^2/(4 xi^2)) e^{-|k|^2/(4 xi^2)} Hasimoto's screening.  The
+# Stokeslet's Fourier transform 8 pi (I/|k|^2 - k k^T/|k|^4) then gives, per k,
+# in-plane block 8 pi cos(k.r)(delta A - k_i k_j B), zz 8 pi cos(k.r) kappa^2 B,
+# and iz, zi -8 pi sin(k.r) k_i dB/dz.  The k = 0 mode (in-plane diagonal only;
+# its zz part vanishes) is T0(z) = -4 pi z erf(xi z) - (2 sqrt(pi)/xi)(e^{-xi^2 z^2} - 1)
+# for Stokes and -2 pi z erf(xi z) - (2 sqrt(pi)/xi)(e^{-xi^2 z^2} - 1) for
+# Laplace, i.e. the mode's divergent z-independent part removed.
+
+def _dp_frame(mask: int):
+    axes = periodic_axes(mask)
+    assert len(axes) == 2
+    free = [a for a in range(3) if a not in axes][0]
+    return axes + [free]                       # frame index i is original axis order[i]
+
+
+def _dp_kvectors(xi: float) -> np.ndarray:
+    """All in-plane k = 2 pi (m1, m2) != 0 with |k| <= 2 xi * 6.7 (both signs)."""
+    kmax = 2.0 * xi * 6.7
+    M = int(math.ceil(kmax / (2.0 * math.pi)))
+    m = np.array([(a, b) for a in range(-M, M + 1) for b in range(-M, M + 1) if (a, b) != (0, 0)], dtype=np.float64)
+    kv = 2.0 * np.pi * m
+    return kv[np.sqrt(np.sum(kv * kv, axis=1)) <= kmax]
+
+
+def _dp_fourier(r: np.ndarray, xi: float, stokes: bool) -> np.ndarray:
+    """Sum over in-plane k != 0 at separations r [M, 3] (frame order): [M, 3, 3] or [M]."""
+    kv = _dp_kvectors(xi)
+    kx, ky = kv[:, 0], kv[:, 1]
+    kap = np.sqrt(kx * kx + ky * ky)
+    M = r.shape[0]
+    assert M == 0 or np.max(np.abs(r[:, 2])) * np.max(kap) < 650.0
+    out = np.zeros((M, 3, 3)) if stokes else np.zeros(M)
+    sp = math.sqrt(math.pi)
+    chunk = max(1, 2_000_000 // max(1, kv.shape[0]))
+    for i0 in range(0, M, chunk):
+        rr = r[i0:i0 + chunk]
+        th = rr[:, :2] @ kv.T                                   # [m, K]
+        z = rr[:, 2:3]
+        ep = np.exp(kap * z) * erfc(kap / (2 * xi) + xi * z)
+        em = np.exp(-kap * z) * erfc(kap / (2 * xi) - xi * z)
+        E = ep + em
+        c = np.cos(th)
+        if not stokes:
+            out[i0:i0 + chunk] = FOUR_PI * np.sum(c * E / (4.0 * kap), axis=1)
+            continue
+        D = ep - em
+        g = np.exp(-kap ** 2 / (4 * xi * xi) - (xi * z) ** 2)
+        A = E / (4.0 * kap) + g / (4.0 * xi * sp)
+        B = E / (8.0 * kap ** 3) - z * D / (8.0 * kap ** 2) + g / (4.0 * xi * sp * kap ** 2)
+        dB = -z * E / (8.0 * kap)
+        s = np.sin(th)
+        o = out[i0:i0 + chunk]
+        o[:, 0, 0] = EIGHT_PI * np.sum(c * (A - kx * kx * B), axis=1)
+        o[:, 1, 1] = EIGHT_PI * np.sum(c * (A - ky * ky * B), axis=1)
+        o[:, 0, 1] = o[:, 1, 0] = -EIGHT_PI * np.sum(c * kx * ky * B, axis=1)
+        o[:, 2, 2] = EIGHT_PI * np.sum(c * kap * kap * B, axis=1)
+        o[:, 0, 2] = o[:, 2, 0] = -EIGHT_PI * np.sum(s * kx * dB, axis=1)
+        o[:, 1, 2] = o[:, 2, 1] = -EIGHT_PI * np.sum(s * ky * dB, axis=1)
+    return out
+
+
+def _dp_zero_mode(z: np.ndarray, xi: float, stokes: bool) -> np.ndarray:
+    lin = (EIGHT_PI if stokes else FOUR_PI) / 2.0
+    return -lin * z * erf(xi * z) - (2.0 * math.sqrt(math.pi) / xi) * (np.exp(-(xi * z) ** 2) - 1.0)
+
+
+def _dp_constant(xi: float, stokes: bool):
+    """C such that Ewald + C -> 0 as r -> 0 once the singular term G(r) is dropped,
+    which is the value of the per-image regularised symmetric sum at r = 0."""
+    rc, _ = _ewald_params(xi)
+    P = int(math.ceil(rc)) + 1
+    ps = np.array([(a, b, 0.0) for a in range(-P, P + 1) for b in range(-P, P + 1)
+                   if (a, b) != (0, 0) and a * a + b * b < rc * rc], dtype=np.float64)
+    c0 = 2.0 * xi / math.sqrt(math.pi)
+    zero = np.zeros((1, 3))
+    if stokes:
+        return 2.0 * c0 * np.eye(3) - np.sum(_hasimoto_real(ps, xi), axis=0) - _dp_fourier(zero, xi, True)[0]
+    pn = np.sqrt(np.sum(ps * ps, axis=1))
+    return c0 - np.sum(erfc(xi * pn) / pn) - _dp_fourier(zero, xi, False)[0]
+
+
+def _dp_sum(r: np.ndarray, mask: int, xi: float, far_only: bool, exclude_self: bool, near_layers: int,
+            stokes: bool) -> np.ndarray:
+    order = _dp_frame(mask)
+    r = np.asarray(r, dtype=np.float64).reshape(-1, 3)
+    rf = r[:, order]
+    M = rf.shape[0]
+    rc, _ = _ewald_params(xi)
+    c0 = 2.0 * xi / math.sqrt(math.pi)
+    out = np.zeros((M, 3, 3)) if stokes else np.zeros(M)
+    P = int(math.ceil((np.max(np.abs(rf[:, :2])) if M else 0.0) + rc)) + 1
+    for px, py in itertools.product(range(-P, P + 1), repeat=2):
+        p = np.array([px, py, 0.0])
+        near = max(abs(px), abs(py)) <= near_layers
+        d = rf - p
+        dn = np.sqrt(np.sum(d * d, axis=1))
+        zero = dn == 0.0
+        if stokes:
+            if far_only and near:
+                out -= _hasimoto_smooth(d, xi)
+                continue
+            sel = (dn < rc + 1e-12) & ~zero
+            if np.any(sel):
+                out[sel] += _hasimoto_real(d[sel], xi)
+            if np.any(zero) and exclude_self:
+                out[zero] -= _hasimoto_smooth(d[zero], xi)
+        else:
+            ds = np.where(zero, 1.0, dn)
+            smooth = np.where(zero, c0, erf(xi * ds) / ds)
+            if far_only and near:
+                out -= smooth
+                continue
+            sel = (dn < rc + 1e-12) & ~zero
+            out[sel] += erfc(xi * dn[sel]) / dn[sel]
+            if exclude_self:
+                out[zero] -= smooth[zero]
+    out += _dp_fourier(rf, xi, stokes)
+    t0 = _dp_zero_mode(rf[:, 2], xi, stokes)
+    C = _dp_constant(xi, stokes)
+    if stokes:
+        out[:, 0, 0] += t0
+        out[:, 1, 1] += t0
+        out += C
+        back = np.empty_like(out)
+        back[:, np.array(order)[:, None], np.array(order)[None, :]] = out
+        return back / EIGHT_PI
+    return (out + t0 + C) / FOUR_PI
+
+
+def dp_stokes_sum(r: np.ndarray, mask: int = 3, xi: float = 4.0, far_only: bool = False,
+                  exclude_self: bool = True, near_layers: int = 1) -> np.ndarray:
+    """Doubly periodic Stokeslet (per-image regularised, see above) at separations r: [M, 3, 3].
+
+    mask names the two periodic axes.  far_only: only in-plane images with
+    |p|_inf > near_layers (the near ones removed analytically through the smooth
+    part of the split).  exclude_self: r == 0 drops its own singular term."""
+    return _dp_sum(r, mask, xi, far_only, exclude_self, near_layers, True)
+
+
+def dp_laplace_sum(r: np.ndarray, mask: int = 3, xi: float = 4.0, far_only: bool = False,
+                   exclude_self: bool = True, near_layers: int = 1) -> np.ndarray:
+    """Doubly periodic 1/(4 pi r), per-image regularised: [M]."""
+    return _dp_sum(r, mask, xi, far_only, exclude_self, near_layers, False)
+
+
 # ---------------------------------------------------------------- dispatch
 
 def periodic_axes(mask: int):
@@ -213,7 +376,7 @@ def supported(kernel: int, mask: int) -> bool:
         return True
     if n == 1 and kernel == LAPLACE:
         return True
-    if n == 3:
+    if n >= 2:
         return True
     return False
 
@@ -234,6 +397,11 @@ def far_kernel_matrix(kernel: int, mask: int, X: np.ndarray, Y: np.ndarray, near
         return tp_laplace_sum(r, far_only=True, near_layers=near_layers).reshape(m, n)
     if kernel == STOKES and len(axes) == 3:
         G = tp_stokes_sum(r, far_only=True, near_layers=near_layers).reshape(m, n, 3, 3)
+        return G.transpose(0, 2, 1, 3).reshape(3 * m, 3 * n)
+    if kernel == LAPLACE and len(axes) == 2:
+        return dp_laplace_sum(r, mask, far_only=True, near_layers=near_layers).reshape(m, n)
+    if kernel == STOKES and len(axes) == 2:
+        G = dp_stokes_sum(r, mask, far_only=True, near_layers=near_layers).reshape(m, n, 3, 3)
         return G.transpose(0, 2, 1, 3).reshape(3 * m, 3 * n)
     raise NotImplementedError(f"no far-field operator for kernel {kernel}, mask {mask}")
 
@@ -256,6 +424,10 @@ def exact_potential(kernel: int, mask: int, targets: np.ndarray, sources: np.nda
         K = tp_laplace_sum(r)
     elif kernel == STOKES and len(axes) == 3:
         K = tp_stokes_sum(r)
+    elif kernel == LAPLACE and len(axes) == 2:
+        K = dp_laplace_sum(r, mask)
+    elif kernel == STOKES and len(axes) == 2:
+        K = dp_stokes_sum(r, mask)
     else:
         raise NotImplementedError
     if kernel == LAPLACE:

@@ -225,6 +225,106 @@ def test_tp_laplace_nacl_madelung():
     assert np.max(np.abs(a - b)) < 1e-13
 
 
+
+# ------------------------------------------------------------------ doubly periodic Ewald sums
+
+def _dp(kernel):
+    return periodic.dp_stokes_sum if kernel == K.STOKES else periodic.dp_laplace_sum
+
+
+def _regularised_lattice_sum(kernel, r, R):
+    """G(r) + sum_{0 < |p|_inf <= R} [G(r - p) - G(p)] over the in-plane lattice (x, y)."""
+    a = np.arange(-R, R + 1)
+    P = np.array([(x, y, 0.0) for x in a for y in a if (x, y) != (0, 0)])
+    s = np.sum(K.kernel_value(kernel, r[None, :] - P) - K.kernel_value(kernel, P), axis=0)
+    return s + K.kernel_value(kernel, r[None, :])[0]
+
+
+@pytest.mark.parametrize("kernel", [K.STOKES, K.LAPLACE])
+def test_dp_xi_independence(kernel):
+    rng = np.random.default_rng(31)
+    r = rng.uniform(-1.05, 1.05, (40, 3))
+    r[0] = 0.0
+    vals = [_dp(kernel)(r, 3, xi=xi) for xi in (3.0, 4.0, 5.5)]
+    scale = np.max(np.abs(vals[0]))
+    for v in vals[1:]:
+        assert np.max(np.abs(v - vals[0])) < 1e-13 * scale
+    far = [_dp(kernel)(r, 3, xi=xi, far_only=True) for xi in (3.0, 5.5)]
+    assert np.max(np.abs(far[1] - far[0])) < 1e-13 * np.max(np.abs(far[0]))
+
+
+@pytest.mark.parametrize("kernel", [K.STOKES, K.LAPLACE])
+def test_dp_against_regularised_lattice_sum(kernel):
+    """The DP sum is the limit of symmetric square image sums, each image regularised by
+    its value at the lattice point; the partial sums converge like 1/R, so five of them
+    (R = 16 .. 256) are Richardson-extrapolated in 1/R."""
+    rng = np.random.default_rng(32)
+    r = np.vstack([np.zeros(3), rng.uniform(-1.0, 1.0, (3, 3))])
+    ew = _dp(kernel)(r, 3)
+    for i, rv in enumerate(r):
+        T = [_regularised_lattice_sum(kernel, rv, R) for R in (16, 32, 64, 128, 256)]
+        for lvl in range(1, len(T)):
+            T = [(2 ** lvl * T[j + 1] - T[j]) / (2 ** lvl - 1) for j in range(len(T) - 1)]
+        assert np.max(np.abs(T[0] - ew[i])) < 2e-10 * max(1.0, np.max(np.abs(ew[i]))), i
+
+
+@pytest.mark.parametrize("kernel", [K.STOKES, K.LAPLACE])
+def test_dp_far_equals_full_minus_near_and_frames(kernel):
+    rng = np.random.default_rng(33)
+    r = rng.uniform(-0.9, 0.9, (20, 3))
+    f = _dp(kernel)
+    near = sum(K.kernel_value(kernel, r - np.array([a, b, 0.0])) for a in (-1, 0, 1) for b in (-1, 0, 1))
+    assert np.max(np.abs(f(r, 3) - near - f(r, 3, far_only=True))) < 1e-13
+    # periodic in x and y, even in r
+    assert np.max(np.abs(f(r + [1.0, -2.0, 0.0], 3) - f(r, 3))) < 1e-13
+    assert np.max(np.abs(f(-r, 3) - f(r, 3))) < 1e-13
+    # the free axis may be any of the three: periodic in (y, z) is (x, y) with axes relabelled
+    order = [1, 2, 0]                   # mask 6: periodic y, z then free x
+    rr = np.empty_like(r)
+    rr[:, order] = r                    # rr[:, order[i]] = r[:, i]
+    a = f(rr, 6)
+    b = f(r, 3)
+    if kernel == K.STOKES:
+        a = a[:, order][:, :, order]
+    assert np.max(np.abs(a - b)) < 1e-13
+
+
+def test_dp_stokes_zero_flux_and_shear_at_infinity():
+    """Net-force-free forces in a slab: no net flux of u_z through any plane z = const
+    (the k_par = 0 mode of u_z vanishes), and far from the slab the flow tends to a
+    uniform stream, u_par(+-inf) = +-(1/2) sum_s z_s f_s,par (with K = S/(8 pi), mu = 1:
+    a plane force density f gives a jump -f in du/dz)."""
+    rng = np.random.default_rng(34)
+    n = 7
+    src = np.column_stack([rng.random((n, 2)), rng.uniform(0.3, 0.7, n)])
+    f = rng.standard_normal((n, 3)); f -= f.mean(0)
+    m = 40
+    g = (np.arange(m) + 0.5) / m
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    for z0 in (0.95, 0.05):
+        plane = np.column_stack([X.ravel(), Y.ravel(), np.full(m * m, z0)])
+        u = periodic.exact_potential(K.STOKES, 3, plane, src, f)
+        assert abs(np.mean(u[:, 2])) < 1e-12 * np.max(np.abs(u))
+    mom = 0.5 * (src[:, 2:3] * f).sum(0)
+    for zs, sign in ((6.0, 1.0), (-5.0, -1.0)):
+        trg = np.column_stack([rng.random((5, 2)), np.full(5, zs)])
+        u = periodic.exact_potential(K.STOKES, 3, trg, src, f)
+        assert np.max(np.abs(u[:, :2] - sign * mom[:2])) < 1e-12
+        assert np.max(np.abs(u[:, 2])) < 1e-12
+
+
+def test_dp_laplace_dipole_layer_potential_jump():
+    """Neutral charges in a slab: far above and below, the potential tends to
+    +-(1/2) sum_s z_s q_s (the potential step of a dipole layer, 1/(4 pi r) units)."""
+    rng = np.random.default_rng(35)
+    src = np.column_stack([rng.random((6, 2)), rng.uniform(0.2, 0.8, 6)])
+    q = rng.uniform(-1, 1, 6); q -= q.mean()
+    mom = 0.5 * np.sum(src[:, 2] * q)
+    for zs, sign in ((6.0, 1.0), (-5.0, -1.0)):
+        trg = np.column_stack([rng.random((4, 2)), np.full(4, zs)])
+        u = periodic.exact_potential(K.LAPLACE, 3, trg, src, q[:, None])
+        assert np.max(np.abs(u[:, 0] - sign * mom)) < 1e-12
+
 # ------------------------------------------------------------------ tree and lists
 
 def _coverage_counts(t, lists, mask):
@@ -363,6 +463,20 @@ def test_kifmm_tp_stokes_random_against_ewald():
     # Stokes far field carries ~1e-4 at p = 8; it still converges with p
     assert errs[1] < errs[0] and errs[1] < 5e-4, errs
 
+
+
+@pytest.mark.parametrize("kernel,p,tol", [(K.STOKES, 6, 5e-4), (K.STOKES, 8, 3e-4), (K.LAPLACE, 8, 1e-6)])
+def test_kifmm_dp_against_ewald(kernel, p, tol):
+    """Doubly periodic slab (z ~ N(0.5, 0.1), clipped): the periodic KIFMM against the
+    pairwise DP sum."""
+    rng = np.random.default_rng(21)
+    n = 300
+    pts = np.column_stack([rng.random((n, 2)), np.clip(rng.normal(0.5, 0.1, n), 0, 1)])
+    k = 3 if kernel == K.STOKES else 1
+    d = rng.standard_normal((n, k)); d -= d.mean(0)
+    ex = periodic.exact_potential(kernel, 3, pts, pts, d)
+    q = kifmm.KIFMM(kernel, 3, p, 25, pts).evaluate(d)
+    assert np.linalg.norm(q - ex) / np.linalg.norm(ex) < tol
 
 def test_near_layer_independence():
     """Changing the near/far split layer l leaves the result unchanged to KIFMM accuracy
