@@ -8,8 +8,13 @@ discussion:
   Stage 1 (operators, unit box, scaled by 2^l at level l since the kernels
   are homogeneous of degree -1):
     * upward / downward check-to-equivalent solves from the SVD A = U S V^T,
-      applied as (V S_eps^+)(U^T q) with S_eps^+ dropping singular values
-      below eps * s_max (Appendix B, the backward-stable solver);
+      applied as (V S_eps^+)(U^T q) (Appendix B, the backward-stable solver),
+      with S_eps^+ dropping singular values below eps * s_max * dim(A): the
+      numerical-rank criterion under which Table 1 reports its ranks.
+      Appendix B's bare eps * s_max keeps directions whose singular values
+      sit at the rounding level of A itself; the solution along them is not
+      determined by the data (two SVD drivers disagree there) and the
+      equivalent densities then carry that noise to other points;
     * M2M, L2L for the eight octants and M2L for the 316 offsets in
       [-3,3]^3 \\ [-1,1]^3, from the free-space kernel between surfaces;
     * the periodic root operator M_root = K^{P,F}(x^{B0,d}, y^{B0,u}) over
@@ -58,9 +63,15 @@ class Pinv:
         return self.VS @ (self.Ut @ q)
 
 
-def pinv_factors(A: np.ndarray, rel_threshold: float = EPS) -> Pinv:
+def rank_threshold(A: np.ndarray) -> float:
+    """Relative singular-value cutoff eps * dim(A) (the rank criterion of Table 1)."""
+    return EPS * max(A.shape)
+
+
+def pinv_factors(A: np.ndarray, rel_threshold: Optional[float] = None) -> Pinv:
     U, s, Vt = np.linalg.svd(A)
-    keep = s > rel_threshold * s[0]
+    thr = rank_threshold(A) if rel_threshold is None else rel_threshold
+    keep = s > thr * s[0]
     return Pinv(Ut=U[:, keep].T.copy(), VS=(Vt[keep].T / s[keep][None, :]).copy())
 
 
@@ -74,7 +85,7 @@ M2L_OFFSETS = [d for d in itertools.product(range(-3, 4), repeat=3) if max(abs(c
 class Operators:
     """Unit-box operators for one (kernel, periodicity, p)."""
 
-    def __init__(self, kernel: int, mask: int, p: int, rel_threshold: float = EPS):
+    def __init__(self, kernel: int, mask: int, p: int, rel_threshold: Optional[float] = None):
         self.kernel, self.mask, self.p = kernel, mask, p
         self.k = kdim(kernel)
         u = unit_surface(p)
@@ -100,7 +111,7 @@ class Operators:
 _OPS_CACHE: Dict[tuple, Operators] = {}
 
 
-def operators(kernel: int, mask: int, p: int, rel_threshold: float = EPS) -> Operators:
+def operators(kernel: int, mask: int, p: int, rel_threshold: Optional[float] = None) -> Operators:
     key = (kernel, mask, p, rel_threshold)
     if key not in _OPS_CACHE:
         _OPS_CACHE[key] = Operators(kernel, mask, p, rel_threshold)
@@ -111,7 +122,7 @@ class KIFMM:
     """One problem: tree, lists and the evaluation pass."""
 
     def __init__(self, kernel: int, mask: int, p: int, s: int, points: np.ndarray,
-                 rel_threshold: float = EPS, box_length: float = 1.0):
+                 rel_threshold: Optional[float] = None, box_length: float = 1.0):
         if not periodic.supported(kernel, mask):
             raise NotImplementedError("unsupported kernel/periodicity")
         self.kernel, self.mask, self.p, self.s = kernel, mask, p, s
@@ -246,7 +257,7 @@ class KIFMM:
 
 
 def evaluate(kernel: int, mask: int, p: int, s: int, points: np.ndarray, density: np.ndarray,
-             rel_threshold: float = EPS) -> np.ndarray:
+             rel_threshold: Optional[float] = None) -> np.ndarray:
     """Convenience wrapper: [R, N, k] densities -> [R, N, k] potentials."""
     f = KIFMM(kernel, mask, p, s, points, rel_threshold)
     dens = np.asarray(density, dtype=np.float64)

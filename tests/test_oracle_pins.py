@@ -70,7 +70,7 @@ def test_backward_stable_solver_stokes_p8():
     """Appendix B: (V S^+)(U^T b) is backward stable; the explicit pseudo-inverse is not."""
     u = K.unit_surface(8)
     A = K.kernel_matrix(K.STOKES, 0.5 * K.INNER * u, 0.5 * K.OUTER * u)
-    f = kifmm.pinv_factors(A)
+    f = kifmm.pinv_factors(A, rel_threshold=kifmm.EPS)     # Appendix B's cutoff, as in Table 7
     one = np.ones(A.shape[0])
     x = f.apply(one)
     err = np.max(np.abs(A @ x - one))
@@ -86,7 +86,7 @@ def test_backward_stable_solver_stokes_p16():
     rows = {r[1]: float(r[2]) for r in golden("svd_backward_error.txt")}
     u = K.unit_surface(16)
     A = K.kernel_matrix(K.STOKES, 0.5 * K.INNER * u, 0.5 * K.OUTER * u)
-    f = kifmm.pinv_factors(A)
+    f = kifmm.pinv_factors(A, rel_threshold=kifmm.EPS)     # Appendix B's cutoff, as in Table 7
     one = np.ones(A.shape[0])
     err = np.max(np.abs(A @ f.apply(one) - one))
     assert err < 10 * rows["SVDpvfmm"]
@@ -427,7 +427,7 @@ def test_kifmm_free_space_converges_to_direct_sum():
             assert errs[0] > 10 * errs[1] > 100 * errs[2] and errs[2] < 1e-7, errs
         else:
             # the Stokeslet's surface representation converges more slowly with p
-            assert errs[2] < 5e-5 and errs[3] < 1e-5, errs
+            assert errs[2] < 5e-6 and errs[3] < 1e-7, errs
 
 
 def test_kifmm_sp_laplace_against_lattice_sum():
@@ -446,8 +446,8 @@ def test_kifmm_tp_stokes_point_forces(pts_f):
     allp = np.concatenate([pts, trg])
     dens = np.concatenate([f, np.zeros((60, 3))])
     ex = periodic.exact_potential(K.STOKES, 7, allp, pts, f)
-    # KIFMM accuracy for the Stokeslet at these p is ~1e-4 .. 1e-5 (surface representation)
-    for p, tol in ((6, 5e-4), (8, 2e-4)):
+    # KIFMM accuracy for the Stokeslet: ~1e-4 at p = 6, ~1e-6 at p = 8
+    for p, tol in ((6, 5e-4), (8, 2e-5)):
         q = kifmm.KIFMM(K.STOKES, 7, p, 8, allp).evaluate(dens)
         assert np.max(np.abs(q - ex)) / np.max(np.abs(ex)) < tol
 
@@ -459,13 +459,11 @@ def test_kifmm_tp_stokes_random_against_ewald():
     for p in (6, 8):
         q = kifmm.KIFMM(K.STOKES, 7, p, 25, pb.points).evaluate(pb.density[0])
         errs.append(np.linalg.norm(q - ex) / np.linalg.norm(ex))
-    # the root operator over |p|_inf >= 2 sits at the edge of the surfaces' validity, so the
-    # Stokes far field carries ~1e-4 at p = 8; it still converges with p
-    assert errs[1] < errs[0] and errs[1] < 5e-4, errs
+    assert errs[1] < errs[0] / 10 and errs[1] < 5e-5, errs
 
 
 
-@pytest.mark.parametrize("kernel,p,tol", [(K.STOKES, 6, 5e-4), (K.STOKES, 8, 3e-4), (K.LAPLACE, 8, 1e-6)])
+@pytest.mark.parametrize("kernel,p,tol", [(K.STOKES, 6, 5e-4), (K.STOKES, 8, 5e-5), (K.LAPLACE, 8, 1e-6)])
 def test_kifmm_dp_against_ewald(kernel, p, tol):
     """Doubly periodic slab (z ~ N(0.5, 0.1), clipped): the periodic KIFMM against the
     pairwise DP sum."""
@@ -499,10 +497,12 @@ def test_near_layer_independence():
         far = (K.kernel_matrix(K.STOKES, f.u, ops.outer + 0.5) @ phi_d).reshape(-1, 3)
         res[lay] = near + far
     err = {lay: np.linalg.norm(res[lay] - ex) / np.linalg.norm(ex) for lay in res}
-    assert err[2] < 1e-5 and err[3] < 1e-5 and err[1] < 3e-4, err
-    assert np.linalg.norm(res[2] - res[3]) / np.linalg.norm(ex) < 1e-5
+    # l = 1 (the tree's split) leaves the |p|_inf = 2 ring to the root's surfaces, at the edge
+    # of their separation: ~1e-5 at p = 8, against ~1e-7 once that ring is summed directly
+    assert err[2] < 1e-6 and err[3] < 1e-6 and err[1] < 2e-5, err
+    assert np.linalg.norm(res[2] - res[3]) / np.linalg.norm(ex) < 1e-6
     q1 = f.evaluate(d)
-    assert np.linalg.norm(q1 - res[2]) / np.linalg.norm(ex) < 5e-4
+    assert np.linalg.norm(q1 - res[2]) / np.linalg.norm(ex) < 3e-5
 
 
 def test_kifmm_linearity_and_periodic_relabel():
@@ -531,26 +531,38 @@ def test_kifmm_target_subset_matches_full():
         assert np.allclose(sub[b], full[f.tree.begin[b]:f.tree.end[b]], rtol=0, atol=1e-14)
 
 
-def test_solver_spread_stokes_p8():
-    """Two backward-stable SVD drivers (LAPACK gesdd, gesvd) give Stokes p = 8 potentials that differ
-    at the 1e-9 level (A has condition number 1.26e13, Table 1; the solution is not unique,
-    Appendix B); this spread sets the FP64 parity tolerance for that kernel and order."""
+def test_solver_threshold_and_spread_stokes_p8():
+    """Two backward-stable SVD drivers (LAPACK gesdd, gesvd) agree on the Stokes p = 8 potentials
+    to ~1e-10 when singular values below eps * s_max * dim(A) are dropped (Table 1's rank
+    criterion, the solver default), but differ at the 1e-9 level under Appendix B's bare
+    eps * s_max, which keeps directions at the rounding level of A (condition number 1.26e13,
+    Table 1); the dropped directions also cost accuracy against the exact periodic sum."""
     import scipy.linalg as sl
     pb = W.stokes_tp_uniform(n=4000, seed=21, p=8, s=300)
-    f = kifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
-    a = f.evaluate(pb.density[0])
-    ops = f.ops
-    keep_up, keep_dn = ops.up, ops.down
+    samp = np.random.default_rng(0).choice(pb.n, 60, replace=False)
+    ex = periodic.exact_potential(pb.kernel, pb.periodic_mask, pb.points[samp], pb.points, pb.density[0])
 
-    def gesvd(A):
-        U, s, Vt = sl.svd(A, lapack_driver="gesvd")
-        keep = s > kifmm.EPS * s[0]
-        return kifmm.Pinv(Ut=U[:, keep].T.copy(), VS=(Vt[keep].T / s[keep][None, :]).copy())
-    try:
-        ops.up = gesvd(K.kernel_matrix(K.STOKES, ops.outer, ops.inner))
-        ops.down = gesvd(K.kernel_matrix(K.STOKES, ops.inner, ops.outer))
-        b = f.evaluate(pb.density[0])
-    finally:
-        ops.up, ops.down = keep_up, keep_dn
-    spread = np.linalg.norm(a - b) / np.linalg.norm(a)
-    assert 1e-11 < spread < 2e-8, spread
+    def solve(thr, driver):
+        f = kifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+        ops = f.ops
+        keep_up, keep_dn = ops.up, ops.down
+
+        def pinv(A):
+            U, s, Vt = sl.svd(A, lapack_driver=driver)
+            keep = s > thr * s[0]
+            return kifmm.Pinv(Ut=U[:, keep].T.copy(), VS=(Vt[keep].T / s[keep][None, :]).copy())
+        try:
+            ops.up = pinv(K.kernel_matrix(K.STOKES, ops.outer, ops.inner))
+            ops.down = pinv(K.kernel_matrix(K.STOKES, ops.inner, ops.outer))
+            return f.evaluate(pb.density[0])
+        finally:
+            ops.up, ops.down = keep_up, keep_dn
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    f0 = kifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+    assert f0.ops.up.Ut.shape[0] == 881 and f0.ops.down.Ut.shape[0] == 881   # Table 1's rank
+    default = f0.evaluate(pb.density[0])
+    tight = [solve(kifmm.EPS * 888, d) for d in ("gesdd", "gesvd")]
+    bare = [solve(kifmm.EPS, d) for d in ("gesdd", "gesvd")]
+    assert rel(tight[0], default) < 5e-10 and rel(tight[1], tight[0]) < 5e-10
+    assert 1e-9 < rel(bare[1], bare[0]) < 2e-8
+    assert rel(tight[0][samp], ex) < 0.25 * rel(bare[0][samp], ex)
