@@ -15,11 +15,12 @@
  *     PKIFMM_STOKES      K(r) = (1/(8 pi)) (I/|r| + r r^T / |r|^3)       k = 3
  * A pair at exactly zero separation contributes nothing.  Sources are also the
  * targets.  Periodic sums that only converge conditionally are taken in the
- * following sense: singly periodic (SP) -- the limit of symmetric image
- * truncations, which requires zero net density (Section 2, Eq.
- * compatcondition, neutrality); triply periodic (TP) -- the Ewald sum with
- * the k = 0 Fourier mode removed (zero mean; Section 3, triply periodic
- * Stokes, which allows a net force).
+ * following sense: singly (SP) and doubly (DP) periodic -- the limit of
+ * symmetric image truncations, which requires zero net density (Section 2,
+ * Eq. compatcondition, neutrality); each image term is taken relative to the
+ * kernel's value at its lattice point, which fixes the additive constant;
+ * triply periodic (TP) -- the Ewald sum with the k = 0 Fourier mode removed
+ * (zero mean; Section 3, triply periodic Stokes, which allows a net force).
  *
  * The method is Algorithm 2 of the paper with its step d folded into the
  * tree: an octree covers the original box and its images with |p|_inf <= 1;
@@ -50,7 +51,8 @@ typedef struct pkifmm_plan pkifmm_plan;
 #define PKIFMM_LAPLACE 1
 #define PKIFMM_STOKES 2
 
-/* periodic axes (bit mask): 0 = free space, X = singly periodic, X|Y|Z = triply periodic */
+/* periodic axes (bit mask): 0 = free space, one axis = singly periodic (Laplace only),
+ * two axes = doubly periodic, X|Y|Z = triply periodic */
 #define PKIFMM_PERIODIC_X 1u
 #define PKIFMM_PERIODIC_Y 2u
 #define PKIFMM_PERIODIC_Z 4u
@@ -62,16 +64,11 @@ typedef struct pkifmm_plan pkifmm_plan;
                                 check-to-equivalent solve (S2M, X, M2M, M2L, L2L, the root far
                                 field) and every use of an equivalent density (W, L2T) in float64 */
 
-/* M2L arithmetic in the mixed mode */
-#define PKIFMM_M2L_FP32 0    /* float32 operands, float32 MFMA accumulation */
-#define PKIFMM_M2L_BF16X3 1  /* each float32 operand split into bf16 hi + lo; three bf16 MFMA
-                                products (hi*hi + hi*lo + lo*hi) with float32 accumulation */
-
 /* status codes */
 #define PKIFMM_OK 0
 #define PKIFMM_ERR_INVALID_ARG -1
 #define PKIFMM_ERR_OUT_OF_BOX -2     /* a coordinate on a non-periodic axis outside [0, L], or not finite */
-#define PKIFMM_ERR_INCOMPATIBLE -3   /* SP input with a non-zero net density */
+#define PKIFMM_ERR_INCOMPATIBLE -3   /* SP or DP input with a non-zero net density */
 #define PKIFMM_ERR_UNSUPPORTED -4    /* kernel x periodicity without a far-field operator */
 #define PKIFMM_ERR_OOM -5
 #define PKIFMM_ERR_HIP -6
@@ -80,18 +77,20 @@ typedef struct pkifmm_plan pkifmm_plan;
 
 typedef struct {
     int kernel;                  /* PKIFMM_LAPLACE or PKIFMM_STOKES */
-    unsigned periodic_mask;      /* 0, PKIFMM_PERIODIC_X (any single axis) or X|Y|Z */
+    unsigned periodic_mask;      /* 0, one axis (Laplace), two axes, or X|Y|Z */
     int p;                       /* surface points per cube edge, 4..16 */
     int max_pts_per_leaf;        /* s: a box holding more points is split */
     int precision;               /* PKIFMM_FP64 or PKIFMM_MIXED */
-    int m2l_mode;                /* PKIFMM_M2L_FP32 or PKIFMM_M2L_BF16X3 (mixed only) */
     double box_length;           /* L > 0 */
-    double svd_rel_threshold;    /* singular values <= this * s_max are dropped; 0 selects 2^-52
-                                    (Appendix B: epsilon_SVD = machine epsilon times s_max) */
+    double svd_rel_threshold;    /* singular values <= this * s_max are dropped from the
+                                    check-to-equivalent solves (Appendix B's (V S^+)(U^T q));
+                                    0 selects 2^-52 * dim(A), the numerical-rank criterion of
+                                    Table 1: a bare 2^-52 keeps directions at the rounding level
+                                    of A, along which the solution is noise */
     unsigned flags;              /* PKIFMM_SKIP_CHECKS */
 } pkifmm_config;
 
-#define PKIFMM_SKIP_CHECKS 1u    /* skip the SP neutrality check (no device-to-host read) */
+#define PKIFMM_SKIP_CHECKS 1u    /* skip the SP/DP neutrality check (no device-to-host read) */
 #define PKIFMM_PHASE_TIMING 2u   /* record HIP events around the phases of every evaluate on its
                                     stream; pkifmm_get_stats waits for them and reports averages */
 #define PKIFMM_GRAPH 4u          /* pkifmm_evaluate captures its launch sequence into a HIP graph
@@ -166,7 +165,7 @@ int pkifmm_set_points_batch(pkifmm_plan *plan, int n_problems, const int64_t *co
  *   potential: device, [n_rhs][n][k] float64, overwritten, input order
  * Work is enqueued on `stream` (the near field on a library-owned stream that
  * forks from and joins back into `stream`, so completion of `stream` covers
- * all of it); the call returns after enqueueing unless the SP neutrality
+ * all of it); the call returns after enqueueing unless the SP/DP neutrality
  * check runs (it reads one reduction back).  The output is float64 in every
  * precision mode.
  * Errors: NO_POINTS, INVALID_ARG, INCOMPATIBLE, OOM, HIP.

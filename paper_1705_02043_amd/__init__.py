@@ -18,7 +18,6 @@ LIB_PATH = os.path.join(HERE, "libpkifmm.so")
 LAPLACE, STOKES = 1, 2
 PERIODIC_X, PERIODIC_Y, PERIODIC_Z = 1, 2, 4
 FP64, MIXED = 0, 1
-M2L_FP32, M2L_BF16X3 = 0, 1
 SKIP_CHECKS = 1
 PHASE_TIMING = 2
 GRAPH = 4
@@ -35,7 +34,7 @@ EXPORTED = ["pkifmm_config_default", "pkifmm_plan_create", "pkifmm_set_points", 
 
 class pkifmm_config(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int), ("periodic_mask", ctypes.c_uint), ("p", ctypes.c_int),
-                ("max_pts_per_leaf", ctypes.c_int), ("precision", ctypes.c_int), ("m2l_mode", ctypes.c_int),
+                ("max_pts_per_leaf", ctypes.c_int), ("precision", ctypes.c_int),
                 ("box_length", ctypes.c_double), ("svd_rel_threshold", ctypes.c_double),
                 ("flags", ctypes.c_uint)]
 
@@ -118,13 +117,13 @@ class Plan:
     """One (kernel, periodicity, p, s, precision) set of operators, a point set and its tree."""
 
     def __init__(self, kernel: int, periodic_mask: int, p: int, max_pts_per_leaf: int,
-                 precision: int = FP64, m2l_mode: int = M2L_FP32, box_length: float = 1.0,
+                 precision: int = FP64, box_length: float = 1.0,
                  svd_rel_threshold: float = 0.0, flags: int = 0):
         L = lib()
         cfg = pkifmm_config()
         _check(L.pkifmm_config_default(ctypes.byref(cfg)))
         cfg.kernel, cfg.periodic_mask, cfg.p = kernel, periodic_mask, p
-        cfg.max_pts_per_leaf, cfg.precision, cfg.m2l_mode = max_pts_per_leaf, precision, m2l_mode
+        cfg.max_pts_per_leaf, cfg.precision = max_pts_per_leaf, precision
         cfg.box_length, cfg.svd_rel_threshold, cfg.flags = box_length, svd_rel_threshold, flags
         h = ctypes.c_void_p()
         _check(L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)))

@@ -16,7 +16,12 @@
 //     the near images |p|_inf <= 1 removed analytically by subtracting the
 //     smooth part S^F = S - S^R (finite at r = 0, where it equals 4 xi/sqrt(pi) I);
 //   * triply periodic Laplace: Ewald with the k = 0 mode removed, near images
-//     removed the same way.
+//     removed the same way;
+//   * doubly periodic Stokes and Laplace: the same splits over the in-plane
+//     lattice; each in-plane Fourier mode k != 0 has its k_z integral in closed
+//     form (erfc terms), the k = 0 mode keeps its z-dependent part, and a
+//     constant makes the sum equal the limit of symmetric image sums
+//     regularised per image by the kernel's value at the lattice point.
 #include <cmath>
 #include <vector>
 
@@ -181,6 +186,92 @@ __global__ void k_far_tp_laplace(const double* __restrict__ X, int m, const doub
     out[i + (int64_t)j * ld] = acc + fs;
 }
 
+// ---- doubly periodic.  Frame: periodic axes f0, f1, free axis f2.  For an in-plane
+// wave vector of length kap and u+- = kap/(2 xi) +- xi z:
+//   E = e^{kap z} erfc(u+) + e^{-kap z} erfc(u-),   D = e^{kap z} erfc(u+) - e^{-kap z} erfc(u-),
+//   g = exp(-kap^2/(4 xi^2) - xi^2 z^2),
+//   A = E/(4 kap) + g/(4 xi sqrt(pi)),  B = E/(8 kap^3) - z D/(8 kap^2) + g/(4 xi sqrt(pi) kap^2),
+//   dB/dz = -z E/(8 kap).
+// Stokes per mode: in-plane 8 pi cos(k.r)(delta_ij A - k_i k_j B), zz 8 pi cos(k.r) kap^2 B,
+// iz and zi -8 pi sin(k.r) k_i dB/dz.  Laplace per mode: 4 pi cos(k.r) E/(4 kap).
+// k = 0 mode on the in-plane diagonal (Stokes) or the scalar (Laplace):
+//   -c z erf(xi z) - (2 sqrt(pi)/xi)(e^{-xi^2 z^2} - 1),  c = 4 pi (Stokes), 2 pi (Laplace).
+__global__ void k_far_dp(int stokes, int f0, int f1, int f2, const double* __restrict__ X, int m,
+                         const double* __restrict__ Y, int n, double* __restrict__ out, int64_t ld,
+                         const double2* __restrict__ kv, int nk, double rc, int P, double c_par, double c_z) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    if (i >= m) return;
+    const double xi = kXi;
+    const double sp = sqrt(M_PI);
+    const double c0 = 2.0 * xi / sp;
+    const int fr[3] = {f0, f1, f2};
+    double r[3];
+    for (int a = 0; a < 3; ++a) r[a] = X[3 * i + fr[a]] - Y[3 * j + fr[a]];
+    double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double acc = 0.0;                  // Laplace
+    double S[3][3];
+    for (int px = -P; px <= P; ++px)
+        for (int py = -P; py <= P; ++py) {
+            double d[3] = {r[0] - px, r[1] - py, r[2]};
+            double rn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const bool near = max(abs(px), abs(py)) <= 1;
+            if (stokes) {
+                if (near) {
+                    hasimoto_smooth(d, rn, xi, S);
+                    for (int p = 0; p < 3; ++p)
+                        for (int q = 0; q < 3; ++q) A[p][q] -= S[p][q];
+                } else if (rn < rc) {
+                    hasimoto_real(d, rn, xi, S);
+                    for (int p = 0; p < 3; ++p)
+                        for (int q = 0; q < 3; ++q) A[p][q] += S[p][q];
+                }
+            } else {
+                if (near) acc -= rn > 0.0 ? erf(xi * rn) / rn : c0;
+                else if (rn < rc) acc += erfc(xi * rn) / rn;
+            }
+        }
+    // Fourier part: kv holds one of each +-k pair; both members contribute the same
+    const double z = r[2];
+    double fxx = 0, fyy = 0, fxy = 0, fzz = 0, fxz = 0, fyz = 0, fl = 0;
+    for (int t = nk - 1; t >= 0; --t) {      // small terms first
+        const double kx = kv[t].x, ky = kv[t].y;
+        const double kap = sqrt(kx * kx + ky * ky);
+        double sn, cs;
+        sincos(kx * r[0] + ky * r[1], &sn, &cs);
+        const double ep = exp(kap * z) * erfc(kap / (2.0 * xi) + xi * z);
+        const double em = exp(-kap * z) * erfc(kap / (2.0 * xi) - xi * z);
+        const double E = ep + em;
+        if (!stokes) {
+            fl += cs * E / kap;
+            continue;
+        }
+        const double D = ep - em;
+        const double g = exp(-kap * kap / (4.0 * xi * xi) - xi * xi * z * z);
+        const double Av = E / (4.0 * kap) + g / (4.0 * xi * sp);
+        const double Bv = E / (8.0 * kap * kap * kap) - z * D / (8.0 * kap * kap) + g / (4.0 * xi * sp * kap * kap);
+        const double dB = -z * E / (8.0 * kap);
+        fxx += cs * (Av - kx * kx * Bv);
+        fyy += cs * (Av - ky * ky * Bv);
+        fxy -= cs * kx * ky * Bv;
+        fzz += cs * kap * kap * Bv;
+        fxz -= sn * kx * dB;
+        fyz -= sn * ky * dB;
+    }
+    const double t0 = -(stokes ? 4.0 : 2.0) * M_PI * z * erf(xi * z) - (2.0 * sp / xi) * (exp(-xi * xi * z * z) - 1.0);
+    if (!stokes) {
+        out[i + (int64_t)j * ld] = acc + 2.0 * M_PI * fl + t0 + c_par;   // 2 x (4 pi / 4) per +-k pair
+        return;
+    }
+    const double w = 2.0 * 8.0 * M_PI;
+    const double F[3][3] = {{w * fxx + t0 + c_par, w * fxy, w * fxz},
+                            {w * fxy, w * fyy + t0 + c_par, w * fyz},
+                            {w * fxz, w * fyz, w * fzz + c_z}};
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q)
+            out[(3 * i + fr[p]) + (int64_t)(3 * j + fr[q]) * ld] = A[p][q] + F[p][q];
+}
+
 __global__ void k_pinv_factors(const double* __restrict__ U, const double* __restrict__ Vt,
                                const double* __restrict__ S, int kn, int r, double* __restrict__ Ut_r,
                                double* __restrict__ VS) {
@@ -232,6 +323,59 @@ std::vector<double> kvectors(double kmax, bool stokes) {
     return out;
 }
 
+// in-plane k = 2 pi (a, b), one of each +-k pair, |k| <= kmax
+std::vector<double> kvectors_2d(double kmax) {
+    std::vector<double> out;
+    int M = (int)std::ceil(kmax / (2.0 * M_PI));
+    for (int a = -M; a <= M; ++a)
+        for (int b = -M; b <= M; ++b) {
+            int first = a != 0 ? a : b;
+            if (first <= 0) continue;
+            double kx = 2 * M_PI * a, ky = 2 * M_PI * b;
+            if (kx * kx + ky * ky > kmax * kmax) continue;
+            out.insert(out.end(), {kx, ky});
+        }
+    return out;
+}
+
+// Constant of the doubly periodic sum (frame diagonal: in-plane c_par, free axis c_z):
+// the Ewald form plus this constant vanishes at r -> 0 once the singular term is dropped,
+// as the per-image regularised symmetric sum does there.
+void dp_constant(bool stokes, double rc, const std::vector<double>& kv, double& c_par, double& c_z) {
+    const double xi = kXi, sp = std::sqrt(M_PI), c0 = 2.0 * xi / sp;
+    double rs_par = 0.0, rs_z = 0.0;     // sum over in-plane p != 0 of the real-space split
+    int P = (int)std::ceil(rc) + 1;
+    for (int a = -P; a <= P; ++a)
+        for (int b = -P; b <= P; ++b) {
+            if ((a == 0 && b == 0) || a * a + b * b >= rc * rc) continue;
+            double rn = std::sqrt((double)(a * a + b * b));
+            double ec = std::erfc(xi * rn) / rn;
+            if (!stokes) { rs_par += ec; continue; }
+            double g = c0 * std::exp(-xi * xi * rn * rn);
+            rs_par += (ec - g) + (ec + g) * (double)(a * a) / (rn * rn);
+            rs_z += ec - g;
+        }
+    double f_par = 0.0, f_z = 0.0;       // Fourier part at r = 0 (both members of each pair)
+    for (size_t t = 0; t < kv.size() / 2; ++t) {
+        double kx = kv[2 * t], ky = kv[2 * t + 1];
+        double kap = std::sqrt(kx * kx + ky * ky);
+        double E = 2.0 * std::erfc(kap / (2.0 * xi));
+        if (!stokes) { f_par += 2.0 * M_PI * E / kap; continue; }
+        double g = std::exp(-kap * kap / (4.0 * xi * xi));
+        double Av = E / (4.0 * kap) + g / (4.0 * xi * sp);
+        double Bv = E / (8.0 * kap * kap * kap) + g / (4.0 * xi * sp * kap * kap);
+        f_par += 2.0 * 8.0 * M_PI * (Av - kx * kx * Bv);
+        f_z += 2.0 * 8.0 * M_PI * kap * kap * Bv;
+    }
+    if (!stokes) {
+        c_par = c0 - rs_par - f_par;
+        c_z = 0.0;
+        return;
+    }
+    c_par = 2.0 * c0 - rs_par - f_par;
+    c_z = 2.0 * c0 - rs_z - f_z;
+}
+
 }  // namespace
 
 void launch_kmat(int kernel, const double* X, int m, const double* Y, int n, double* out, int64_t ld,
@@ -281,6 +425,37 @@ void launch_far_kmat(int kernel, unsigned mask, const double* X, int m, const do
         else
             hipLaunchKernelGGL(k_far_tp_laplace, grid, dim3(128), 0, s, X, m, Y, n, out, ld, (const double4*)dk.p,
                                nk, rc, P);
+        PK_HIP(hipGetLastError());
+        PK_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    if (naxes == 2) {
+        int fr[3], nf = 0;
+        for (int a = 0; a < 3; ++a)
+            if (mask & (1u << a)) fr[nf++] = a;
+        for (int a = 0; a < 3; ++a)
+            if (!(mask & (1u << a))) fr[2] = a;
+        const double rc = 6.3 / kXi;
+        const double kmax = 2.0 * kXi * 6.7;
+        std::vector<double> hx(3 * (size_t)m), hy(3 * (size_t)n);
+        PK_HIP(hipMemcpyAsync(hx.data(), X, hx.size() * 8, hipMemcpyDeviceToHost, s));
+        PK_HIP(hipMemcpyAsync(hy.data(), Y, hy.size() * 8, hipMemcpyDeviceToHost, s));
+        PK_HIP(hipStreamSynchronize(s));
+        double rmax = 0.0;
+        for (int c = 0; c < 2; ++c) {
+            double xlo = 1e300, xhi = -1e300, ylo = 1e300, yhi = -1e300;
+            for (int i = 0; i < m; ++i) { xlo = std::min(xlo, hx[3 * i + fr[c]]); xhi = std::max(xhi, hx[3 * i + fr[c]]); }
+            for (int j = 0; j < n; ++j) { ylo = std::min(ylo, hy[3 * j + fr[c]]); yhi = std::max(yhi, hy[3 * j + fr[c]]); }
+            rmax = std::max(rmax, std::max(std::fabs(xhi - ylo), std::fabs(xlo - yhi)));
+        }
+        const int P = (int)std::ceil(rmax + rc) + 1;
+        std::vector<double> kv = kvectors_2d(kmax);
+        double c_par, c_z;
+        dp_constant(kernel == PKIFMM_STOKES, rc, kv, c_par, c_z);
+        DBuf<double> dk;
+        dk.upload(kv, s);
+        hipLaunchKernelGGL(k_far_dp, grid, dim3(128), 0, s, kernel == PKIFMM_STOKES ? 1 : 0, fr[0], fr[1], fr[2], X, m,
+                           Y, n, out, ld, (const double2*)dk.p, (int)(kv.size() / 2), rc, P, c_par, c_z);
         PK_HIP(hipGetLastError());
         PK_HIP(hipStreamSynchronize(s));
         return;

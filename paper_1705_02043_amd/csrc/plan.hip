@@ -164,7 +164,6 @@ void check_config(const pkifmm_config& c) {
     if (!(c.box_length > 0.0) || !std::isfinite(c.box_length)) throw Error(PKIFMM_ERR_INVALID_ARG, "box_length");
     if (c.svd_rel_threshold < 0.0 || c.svd_rel_threshold >= 1.0) throw Error(PKIFMM_ERR_INVALID_ARG, "svd_rel_threshold");
     int naxes = __builtin_popcount(c.periodic_mask);
-    if (naxes == 2) throw Error(PKIFMM_ERR_UNSUPPORTED, "doubly periodic far field not available");
     if (naxes == 1 && c.kernel == PKIFMM_STOKES) throw Error(PKIFMM_ERR_UNSUPPORTED, "singly periodic Stokes far field not available");
 }
 
@@ -570,7 +569,8 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
         };
         auto mark = [&]() { mark_on(s); };
         launch_permute_density(density, P->perm.p, n, R, k, P->ds.p, mixed ? P->ds32.p : nullptr, s);
-        if (checks && __builtin_popcount(P->cfg.periodic_mask) == 1 && !(P->cfg.flags & PKIFMM_SKIP_CHECKS)) {
+        const int naxes = __builtin_popcount(P->cfg.periodic_mask);
+        if (checks && (naxes == 1 || naxes == 2) && !(P->cfg.flags & PKIFMM_SKIP_CHECKS)) {
             const int np = P->n_problems;
             std::vector<double> sums((size_t)np * R * k);
             launch_density_sums(P->ds.p, n, R, k, P->prob_off.p, np, P->sums.p, s);
@@ -580,7 +580,7 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
                 const double cnt = (double)(P->prob_off_h[q + 1] - P->prob_off_h[q]);
                 for (int i = 0; i < R * k; ++i)
                     if (!(std::fabs(sums[(size_t)q * R * k + i]) <= 1e-10 * std::max(1.0, cnt)))
-                        throw Error(PKIFMM_ERR_INCOMPATIBLE, "singly periodic input needs a zero net density");
+                        throw Error(PKIFMM_ERR_INCOMPATIBLE, "singly and doubly periodic input needs a zero net density");
             }
         }
         const size_t cols = (size_t)t.nbox() * R;
@@ -646,7 +646,6 @@ int pkifmm_config_default(pkifmm_config* c) {
     c->p = 8;
     c->max_pts_per_leaf = 64;
     c->precision = PKIFMM_FP64;
-    c->m2l_mode = PKIFMM_M2L_FP32;
     c->box_length = 1.0;
     c->svd_rel_threshold = 0.0;
     c->flags = 0;
@@ -688,7 +687,7 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
         d_out.upload(outer, s);
         A.ensure((size_t)kn * kn);
         double thr = cfg->svd_rel_threshold;
-        if (thr == 0.0) thr = std::ldexp(1.0, -52);
+        if (thr == 0.0) thr = std::ldexp(1.0, -52) * kn;   // numerical-rank criterion of Table 1
         // upward: check = outer, equivalent = inner;  downward: check = inner, equivalent = outer
         launch_kmat(cfg->kernel, d_out.p, ns, d_in.p, ns, A.p, kn, s);
         P->r_up = pinv_build(h, s, A.p, kn, thr, P->up_Ut, P->up_VS);

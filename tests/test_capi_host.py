@@ -32,7 +32,7 @@ def test_status_strings_and_bad_config():
     h = ctypes.c_void_p()
     assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_INVALID_ARG
     cfg.p = 8
-    cfg.periodic_mask = 3   # doubly periodic far field is not provided
+    cfg.kernel, cfg.periodic_mask = pk.STOKES, 1   # singly periodic Stokes far field is not provided
     assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_UNSUPPORTED
     assert L.pkifmm_plan_destroy(None) == 0
 

@@ -94,6 +94,37 @@ def test_backward_stable_solver_stokes_p16():
     assert err_explicit > 100 * err
 
 
+
+class _NoisySolve:
+    """A check-to-equivalent solve whose input is perturbed by relative noise of 2^-53."""
+
+    def __init__(self, base, rng):
+        self.base, self.rng = base, rng
+
+    def apply(self, q):
+        return self.base.apply(q * (1.0 + 2.0 ** -53 * self.rng.standard_normal(q.shape)))
+
+
+@pytest.mark.parametrize("kernel,p,lo,hi", [(K.STOKES, 8, 1e-11, 1e-10), (K.LAPLACE, 8, 0.0, 2e-13)])
+def test_solve_amplification_of_rounding(kernel, p, lo, hi):
+    """How far rounding-level changes of every check potential move the final potentials: the
+    floor under FP64 agreement of two implementations that sum in different orders.  At Stokes
+    p = 8 the solve keeps two singular values just above the cutoff (2.18e-13 s_max against
+    1.97e-13), so it amplifies ~3e5 times; Laplace p = 8 is full rank and benign."""
+    pb = (W.stokes_tp_uniform(n=4000, seed=21, p=p, s=300) if kernel == K.STOKES
+          else W.laplace_sp_uniform(n=4000, seed=21, p=p, s=100))
+    f = kifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+    a = f.evaluate(pb.density[0])
+    up, dn = f.ops.up, f.ops.down
+    rng = np.random.default_rng(1)
+    try:
+        f.ops.up, f.ops.down = _NoisySolve(up, rng), _NoisySolve(dn, rng)
+        b = f.evaluate(pb.density[0])
+    finally:
+        f.ops.up, f.ops.down = up, dn
+    x = np.linalg.norm(a - b) / np.linalg.norm(a)
+    assert lo < x < hi, x
+
 # ------------------------------------------------------------------ singly periodic Laplace sums
 
 @pytest.mark.parametrize("axis", [0, 2])
