@@ -97,13 +97,14 @@ typedef struct {
                                     (once per points/n_rhs/density/potential pointers) and replays
                                     it on `stream`; implies no neutrality check and no phase timing */
 
-/* phases of one evaluation; the near field runs on a library-owned second stream,
- * concurrently with the other phases, which run in this order on the caller's stream */
-#define PKIFMM_PHASE_NEAR 0      /* U-list direct sums (leaf points to leaf points) */
+/* phases of one evaluation, on the caller's stream in this order except the near field,
+ * which runs on a library-owned second stream after the upward pass, concurrently with the
+ * M2L and downward phases */
+#define PKIFMM_PHASE_NEAR 0      /* U-list and direct W/X sums (leaf points to leaf points) */
 #define PKIFMM_PHASE_UP 1        /* density permutation, S2M, M2M, upward solves */
-#define PKIFMM_PHASE_M2L 2       /* root far field, V-list M2L and its per-target sums */
-#define PKIFMM_PHASE_DOWN 3      /* X list, L2L, downward solves */
-#define PKIFMM_PHASE_LEAF 4      /* W-list M2T, L2T, output permutation */
+#define PKIFMM_PHASE_M2L 2       /* root far field, X list, V-list M2L and its per-target sums */
+#define PKIFMM_PHASE_DOWN 3      /* L2L, downward solves */
+#define PKIFMM_PHASE_LEAF 4      /* W-list M2T, L2T, output permutation (after the near field) */
 #define PKIFMM_NUM_PHASES 5
 
 typedef struct {

@@ -15,6 +15,19 @@
 // every thread sweeps the tile; all lanes read the same LDS word (broadcast).
 // The geometry of a pair is computed once for a block of RB right-hand sides.
 //
+// U-list pairs evaluated once (segment kind 3, one right-hand side): the kernel is
+// symmetric, K(-d) = K(d), so a pair of adjacent leaves B, A (A in U(B) with shift p,
+// B in U(A) with -p) is swept by one workgroup holding B's targets.  Within a tile the
+// sources are taken in groups of 64 and rotated across the wave (lane i meets source
+// (i + j) mod 64 at step j), so at every step each lane adds its pair's reverse term
+// into a different per-wave float64 LDS accumulator with an LDS atomic add
+// (ds_add_f64; the float32 LDS atomic is an order of magnitude slower on this chip):
+// no two lanes touch one address in a step and the wave's LDS operations execute in
+// order, so each source's sum is formed in a fixed order.  After each group the four
+// waves are combined in a fixed order and each source's sum is written once to a
+// partial slot; a gather kernel adds the slots of every leaf in list order.  Results
+// are deterministic and do not depend on scheduling.
+//
 // Mixed precision (U lists and direct W/X): coordinates are float hi + lo
 // offsets from the leaf centres (source offsets plus the exact dyadic
 // difference of the box centres), so only the final differences are rounded;
@@ -66,6 +79,28 @@ __device__ __forceinline__ void interact(T dx, T dy, T dz, const T* d, T* acc) {
     }
 }
 
+// K(d) applied both ways: fs (the source's density) into acc_t, ft (the target's) into acc_s.
+// Only used between different leaves, where no separation is zero.
+template <int KD, typename T>
+__device__ __forceinline__ void interact_both(T dx, T dy, T dz, const T* fs, T* acc_t, const T* ft, T* acc_s) {
+    T r2 = dx * dx + dy * dy + dz * dz;
+    T ri = rsq(r2);
+    if constexpr (KD == 1) {
+        acc_t[0] += fs[0] * ri;
+        acc_s[0] += ft[0] * ri;
+    } else {
+        T ri2 = ri * ri;
+        T a = (fs[0] * dx + fs[1] * dy + fs[2] * dz) * ri2;
+        T b = (ft[0] * dx + ft[1] * dy + ft[2] * dz) * ri2;
+        acc_t[0] += ri * (fs[0] + dx * a);
+        acc_t[1] += ri * (fs[1] + dy * a);
+        acc_t[2] += ri * (fs[2] + dz * a);
+        acc_s[0] += ri * (ft[0] + dx * b);
+        acc_s[1] += ri * (ft[1] + dy * b);
+        acc_s[2] += ri * (ft[2] + dz * b);
+    }
+}
+
 __device__ __forceinline__ double box_h(const P2PArgs& a, int b) { return ldexp(1.0, -a.box_level[b]); }
 
 template <int KD, bool MIXED, int RB>
@@ -74,30 +109,45 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
     constexpr int ND = KD * RB;
     __shared__ T s_x[kThreads], s_y[kThreads], s_z[kThreads], s_d[ND][kThreads];
     __shared__ float s_lx[MIXED ? kThreads : 1], s_ly[MIXED ? kThreads : 1], s_lz[MIXED ? kThreads : 1];
+    // kind-3 segments: per-wave running sums of the reverse terms of a 64-source group
+    constexpr int NW = RB == 1 ? kThreads / 64 : 1;
+    __shared__ double s_dacc[NW][KD][64];
 
-    const Work w = a.work[blockIdx.x];
     const double* __restrict__ usurf = a.usurf;
     const int kn = KD * a.n_surf;
     const int64_t n = a.n;
     const int tid = threadIdx.x;
-
+    if constexpr (RB == 1) {
+        for (int i = tid; i < NW * KD * 64; i += kThreads) (&s_dacc[0][0][0])[i] = 0.0;
+    }
+    // the grid may be smaller than the item list (a capped residency leaves room on every
+    // compute unit for the concurrent tree passes): then workgroups take the next item from a
+    // counter, in list order; every workgroup leaves once the list is exhausted
+    __shared__ int s_item;
+    for (int wi = blockIdx.x;;) {
+    if (a.work_counter) {
+        __syncthreads();
+        if (tid == 0) s_item = (int)atomicAdd(a.work_counter, 1ull);
+        __syncthreads();
+        wi = s_item;
+    }
+    if (wi >= a.n_work) break;
+    const Work w = a.work[wi];
     // target box centre and edge (the origin of the mixed-precision offsets)
     const double th = box_h(a, w.tbox);
     const double tcx = (a.box_ix[w.tbox] + 0.5) * th;
     const double tcy = (a.box_iy[w.tbox] + 0.5) * th;
     const double tcz = (a.box_iz[w.tbox] + 0.5) * th;
 
-    double tx[kTPT], ty[kTPT], tz[kTPT];   // absolute (FP64) or relative to the target centre (mixed)
     double acc[kTPT][ND];
+    T dt[kTPT][KD];                        // the targets' own densities (kind-3 reverse terms); 0 for padding
     for (int j = 0; j < kTPT; ++j) {
         for (int c = 0; c < ND; ++c) acc[j][c] = 0.0;
         const int t = w.t0 + min(tid + j * kThreads, max(w.tcount - 1, 0));
-        if (MIXED) {   // hi + lo float pair, exact sum in double
-            tx[j] = (double)a.off[t] + (double)a.off[3 * n + t];
-            ty[j] = (double)a.off[n + t] + (double)a.off[4 * n + t];
-            tz[j] = (double)a.off[2 * n + t] + (double)a.off[5 * n + t];
-        } else {
-            tx[j] = a.xs[t]; ty[j] = a.xs[n + t]; tz[j] = a.xs[2 * n + t];
+        const bool real = tid + j * kThreads < w.tcount;
+        for (int c = 0; c < KD; ++c) {
+            const int64_t di = ((int64_t)r0 * KD + c) * n + t;
+            dt[j][c] = real ? (MIXED ? (T)a.ds32[di] : (T)a.ds[di]) : T(0);
         }
     }
 
@@ -112,8 +162,9 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
         const double scz = (a.box_iz[b] + 0.5) * sh + shz;
         // source-centre minus target-centre: an exact dyadic value (mixed-mode origin shift)
         const double dcx = scx - tcx, dcy = scy - tcy, dcz = scz - tcz;
+        const bool pts = seg.kind == 0 || seg.kind == 3;
         int count, base = 0;
-        if (seg.kind == 0) {
+        if (pts) {
             base = a.box_begin[b];
             count = a.box_end[b] - base;
         } else {
@@ -124,14 +175,20 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
         T ux[kTPT], uy[kTPT], uz[kTPT];
         float lx[kTPT], ly[kTPT], lz[kTPT];
         for (int j = 0; j < kTPT; ++j) {
+            // target coordinates: absolute (float64 form) or relative to the target centre, as
+            // an exact hi + lo sum (mixed form); reloaded per segment to keep registers free
+            const int t = w.t0 + min(tid + j * kThreads, max(w.tcount - 1, 0));
             if (MIXED) {
-                double vx = tx[j] - dcx, vy = ty[j] - dcy, vz = tz[j] - dcz;
+                const double tx = (double)a.off[t] + (double)a.off[3 * n + t];
+                const double ty = (double)a.off[n + t] + (double)a.off[4 * n + t];
+                const double tz = (double)a.off[2 * n + t] + (double)a.off[5 * n + t];
+                double vx = tx - dcx, vy = ty - dcy, vz = tz - dcz;
                 ux[j] = (float)vx; uy[j] = (float)vy; uz[j] = (float)vz;
                 lx[j] = (float)(vx - (double)ux[j]);
                 ly[j] = (float)(vy - (double)uy[j]);
                 lz[j] = (float)(vz - (double)uz[j]);
             } else {
-                ux[j] = (T)(tx[j] - shx); uy[j] = (T)(ty[j] - shy); uz[j] = (T)(tz[j] - shz);
+                ux[j] = (T)(a.xs[t] - shx); uy[j] = (T)(a.xs[n + t] - shy); uz[j] = (T)(a.xs[2 * n + t] - shz);
                 lx[j] = ly[j] = lz[j] = 0.f;
             }
         }
@@ -142,7 +199,7 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
             __syncthreads();
             if (tid < cnt) {
                 const int s = c0 + tid;
-                if (seg.kind == 0) {
+                if (pts) {
                     const int64_t q = base + s;
                     if (MIXED) {
                         s_x[tid] = a.off[q]; s_y[tid] = a.off[n + q]; s_z[tid] = a.off[2 * n + q];
@@ -161,8 +218,57 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
                         for (int c = 0; c < KD; ++c) s_d[KD * q + c][tid] = (T)src[c];
                     }
                 }
+            } else if (seg.kind == 3 && tid < ((cnt + 63) & ~63)) {
+                // padding of the last 64-source group: far away, zero density; its own
+                // reverse sums are computed and discarded
+                s_x[tid] = T(1.0e6); s_y[tid] = T(1.0e6); s_z[tid] = T(1.0e6);
+                if (MIXED) { s_lx[tid] = 0.f; s_ly[tid] = 0.f; s_lz[tid] = 0.f; }
+                for (int c = 0; c < ND; ++c) s_d[c][tid] = T(0);
             }
             __syncthreads();
+            if constexpr (RB == 1) {
+                if (seg.kind == 3) {
+                    const int lane = tid & 63, wv = tid >> 6;
+                    for (int g0 = 0; g0 < cnt; g0 += 64) {
+                        for (int h = 0; h < 64; h += 32) {
+                            T part[kTPT][KD];
+                            for (int j = 0; j < kTPT; ++j)
+                                for (int c = 0; c < KD; ++c) part[j][c] = T(0);
+                            for (int jj = 0; jj < 32; ++jj) {
+                                const int ql = (lane + h + jj) & 63;
+                                const int q = g0 + ql;
+                                T d[KD], cs[KD];
+                                for (int c = 0; c < KD; ++c) { d[c] = s_d[c][q]; cs[c] = T(0); }
+                                const T sx = s_x[q], sy = s_y[q], sz = s_z[q];
+                                if constexpr (MIXED) {
+                                    const float slx = s_lx[q], sly = s_ly[q], slz = s_lz[q];
+                                    for (int j = 0; j < kTPT; ++j)
+                                        interact_both<KD, T>((ux[j] - sx) + (lx[j] - slx), (uy[j] - sy) + (ly[j] - sly),
+                                                             (uz[j] - sz) + (lz[j] - slz), d, part[j], dt[j], cs);
+                                } else {
+                                    for (int j = 0; j < kTPT; ++j)
+                                        interact_both<KD, T>(ux[j] - sx, uy[j] - sy, uz[j] - sz, d, part[j], dt[j], cs);
+                                }
+                                for (int c = 0; c < KD; ++c)
+                                    __hip_atomic_fetch_add(&s_dacc[wv][c][ql], (double)cs[c], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+                            }
+                            for (int j = 0; j < kTPT; ++j)
+                                for (int c = 0; c < KD; ++c) acc[j][c] += (double)part[j][c];
+                        }
+                        __syncthreads();
+                        if (tid < min(64, cnt - g0))
+                            for (int c = 0; c < KD; ++c)
+                                a.mpart[(int64_t)c * a.n_slots + seg.slot + c0 + g0 + tid] =
+                                    ((s_dacc[0][c][tid] + s_dacc[1][c][tid]) + s_dacc[2][c][tid]) + s_dacc[3][c][tid];
+                        __syncthreads();
+                        // each lane clears its own slot; every add of the next group follows in program order
+                        for (int c = 0; c < KD; ++c) s_dacc[wv][c][lane] = 0.0;
+                        __asm__ volatile("" ::: "memory");
+                    }
+                    continue;
+                }
+            }
             if constexpr (MIXED) {
                 for (int j0 = 0; j0 < cnt; j0 += 32) {
                     const int j1 = min(cnt, j0 + 32);
@@ -210,6 +316,8 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
             *o = a.accumulate_pts ? *o + acc[j][c] : acc[j][c];
         }
     }
+    if (!a.work_counter) wi += gridDim.x;
+    }   // work items
 }
 
 // Points to a surface (S2M: a leaf's own points to its upward check surface; X list:
@@ -265,9 +373,36 @@ __global__ __launch_bounds__(kThreads) void k_p2s(P2PArgs a, int r) {
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_mutual_gather(const double* __restrict__ mpart, int64_t n_slots, int kd,
+                                                           const int* __restrict__ in_box,
+                                                           const int64_t* __restrict__ in_off,
+                                                           const int64_t* __restrict__ in_slot,
+                                                           const int* __restrict__ box_begin,
+                                                           const int* __restrict__ box_end, int64_t n,
+                                                           double* __restrict__ out) {
+    const int j = blockIdx.x, c = blockIdx.y;
+    const int b = in_box[j];
+    const int base = box_begin[b], cnt = box_end[b] - base;
+    const int64_t e0 = in_off[j], e1 = in_off[j + 1];
+    const double* __restrict__ pc = mpart + (int64_t)c * n_slots;
+    for (int i = threadIdx.x; i < cnt; i += kThreads) {
+        double s = 0.0;
+        for (int64_t e = e0; e < e1; e += 8) {      // eight loads in flight, added in list order
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = e + u < e1 ? pc[in_slot[e + u] + i] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (e + u < e1) s += v[u];
+        }
+        out[(int64_t)c * n + base + i] += s;
+    }
+}
+
 template <int KD, bool MIXED, int RB>
 void launch_block(const P2PArgs& a, int r0, hipStream_t s) {
-    hipLaunchKernelGGL((k_p2p<KD, MIXED, RB>), dim3(a.n_work), dim3(kThreads), 0, s, a, r0);
+    const int grid = a.work_counter ? std::min(a.n_work, a.grid_cap) : a.n_work;
+    hipLaunchKernelGGL((k_p2p<KD, MIXED, RB>), dim3(grid), dim3(kThreads), 0, s, a, r0);
     PK_HIP(hipGetLastError());
 }
 
@@ -294,6 +429,15 @@ void launch_p2s(const P2PArgs& a, hipStream_t s) {
         else hipLaunchKernelGGL((k_p2s<3>), dim3(a.n_work), dim3(kThreads), 0, s, a, r);
         PK_HIP(hipGetLastError());
     }
+}
+
+void launch_mutual_gather(const double* mpart, int64_t n_slots, int kd, const int* in_box, const int64_t* in_off,
+                          const int64_t* in_slot, int n_in, const int* box_begin, const int* box_end, int64_t n,
+                          double* out, hipStream_t s) {
+    if (n_in == 0) return;
+    hipLaunchKernelGGL(k_mutual_gather, dim3(n_in, kd), dim3(kThreads), 0, s, mpart, n_slots, kd, in_box, in_off,
+                       in_slot, box_begin, box_end, n, out);
+    PK_HIP(hipGetLastError());
 }
 
 void launch_p2p(const P2PArgs& a, bool mixed, hipStream_t s) {

@@ -36,9 +36,12 @@ void launch_density_sums(const double* ds, int64_t n, int R, int k, const int64_
 
 // ---- direct interactions (kernels_p2p.hip)
 struct Seg {         // one source segment
-    int kind;        // 0: points of box, 1: inner surface (phi_u), 2: outer surface (phi_d)
+    int kind;        // 0: points of box, 1: inner surface (phi_u), 2: outer surface (phi_d),
+                     // 3: points of box, both ways (a U-list pair evaluated once: the box's
+                     //    points also receive the item's targets, into partial slots)
     int box;
     int shift;       // (sx+1)*9 + (sy+1)*3 + (sz+1)
+    int64_t slot = 0;   // kind 3: first partial slot (one per point of box)
 };
 struct Work {        // one workgroup's targets and its segment range
     int tbox;        // target box
@@ -70,9 +73,19 @@ struct P2PArgs {
     double* out_pts;     // [R][k][n] sorted potentials (targets = points)
     int accumulate_pts;  // add into out_pts instead of storing
     double* out_surf;    // [nbox*R][kn] check potentials (targets = surfaces), accumulated
+    double* mpart;       // [k][n_slots] kind-3 partial sums (float64), written once each
+    int64_t n_slots;
+    int grid_cap;        // k_p2p with work_counter: this many workgroups take items from the counter
+    unsigned long long* work_counter;   // zero before the launch; NULL: one workgroup per item
 };
-// right-hand sides are processed in blocks that share each pair's geometry
+// right-hand sides are processed in blocks that share each pair's geometry; segments of
+// kind 3 require R == 1
 void launch_p2p(const P2PArgs& a, bool mixed, hipStream_t s);
+// out[c][begin(b) + i] += sum over e in [in_off[j], in_off[j+1]) of mpart[c][in_slot[e] + i]
+// for the leaves b = in_box[j], j < n_in (the other side of the kind-3 segments), in entry order
+void launch_mutual_gather(const double* mpart, int64_t n_slots, int kd, const int* in_box, const int64_t* in_off,
+                          const int64_t* in_slot, int n_in, const int* box_begin, const int* box_end, int64_t n,
+                          double* out, hipStream_t s);
 // points to surfaces only (S2M, X), float64, up to 64 targets per work item
 void launch_p2s(const P2PArgs& a, hipStream_t s);
 

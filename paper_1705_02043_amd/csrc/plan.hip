@@ -128,6 +128,16 @@ struct pkifmm_plan {
     SegRange w_s2m, w_x, w_leaf_u, w_leaf_far;
     DBuf<Seg> segs;
     DBuf<Work> work;
+    // U-list pairs evaluated once (one right-hand side): partial slots and, per leaf that is
+    // the other side of such pairs, its slots in a fixed order
+    int near_grid_cap = 0;              // near-field workgroups resident at once (0: one per item)
+    DBuf<double> counter;               // near-field work counter (one 64-bit word)
+    bool mutual = false;
+    int64_t n_slots = 0;
+    int n_in = 0;
+    DBuf<double> mpart;
+    DBuf<int> in_box;
+    DBuf<int64_t> in_off, in_slot;
     std::vector<GemmRange> g_m2m;       // per level
     std::vector<GemmRange> g_up1, g_up2, g_dn1, g_dn2, g_l2l;   // per level
     GemmRange g_root;
@@ -222,18 +232,22 @@ int pinv_build(rocblas_handle h, hipStream_t s, const double* A_dev, int kn, dou
     return r;
 }
 
-// in: nkb input columns per output column (K blocks), -1 for a zero block
-void add_gemm(Gemm& g, int op, int M, const std::vector<int>& in, const std::vector<int>& out,
-              const std::vector<double>& sc, int nkb = 1) {
-    for (size_t c0 = 0; c0 < out.size(); c0 += 64) {
-        int ncol = (int)std::min<size_t>(64, out.size() - c0);
+// in: nkb input columns per output column (K blocks), -1 for a zero block; ncols output columns
+void add_gemm(Gemm& g, int op, int M, const int* in, const int* out, const double* sc, size_t ncols, int nkb = 1) {
+    for (size_t c0 = 0; c0 < ncols; c0 += 64) {
+        int ncol = (int)std::min<size_t>(64, ncols - c0);
         int col0 = (int)g.out.size();
         for (int c = 0; c < ncol; ++c)
             for (int kb = 0; kb < 8; ++kb) g.in.push_back(kb < nkb ? in[(c0 + c) * nkb + kb] : -1);
-        g.out.insert(g.out.end(), out.begin() + c0, out.begin() + c0 + ncol);
-        g.scale.insert(g.scale.end(), sc.begin() + c0, sc.begin() + c0 + ncol);
+        g.out.insert(g.out.end(), out + c0, out + c0 + ncol);
+        g.scale.insert(g.scale.end(), sc + c0, sc + c0 + ncol);
         for (int r0 = 0; r0 < M; r0 += 64) g.tiles.push_back(Tile{op, col0, ncol, r0});
     }
+}
+
+void add_gemm(Gemm& g, int op, int M, const std::vector<int>& in, const std::vector<int>& out,
+              const std::vector<double>& sc, int nkb = 1) {
+    add_gemm(g, op, M, in.data(), out.data(), sc.data(), out.size(), nkb);
 }
 
 double box_edge(const HostTree& t, int b) { return std::ldexp(1.0, -t.level[b]); }
@@ -271,50 +285,125 @@ void build_work(pkifmm_plan* P, int R) {
         for (int c0 = 0; c0 < ns; c0 += 64) work.push_back(Work{b, 1, c0, std::min(64, ns - c0), s0, s1});
     }
     P->w_x.nwork = (int)work.size() - P->w_x.work0;
+    // Direct leaf-to-leaf pairs of different leaves are evaluated once when there is one
+    // right-hand side: the kernel is symmetric, A in U(B) with shift p exactly when B in U(A)
+    // with -p, and a small leaf A taken directly from W(B) is B taken directly from X(A) with
+    // -p.  The leaf with more points (then the lower box index) owns the pair and holds the
+    // targets; the other leaf's points get their sums through partial slots.
+    const bool mutual = R == 1;
+    auto pts_of = [&](int b) { return t.end[b] - t.begin[b]; };
+    // is (src, shift code c) in box a's list?  Lists are sorted by (source, shift code).
+    auto listed = [&](const std::vector<int64_t>& off, const std::vector<Entry>& v, int a, int s, int c) {
+        auto lo = v.begin() + off[a], hi = v.begin() + off[a + 1];
+        auto it = std::lower_bound(lo, hi, std::make_pair(s, c), [&](const Entry& e, const std::pair<int, int>& k) {
+            return e.src < k.first || (e.src == k.first && code(e) < k.second);
+        });
+        return it != hi && it->src == s && code(*it) == c;
+    };
+    // which: 0 U entry, 1 direct W entry, 2 direct X entry of leaf b.  Returns 0: evaluate one
+    // way, 1: own the pair, 2: the partner owns it
+    auto d_role = [&](int b, const Entry& e, int which) {
+        const int a = e.src;
+        if (!mutual || a == b) return 0;
+        const int mc = 26 - code(e);
+        const bool mirrored = which == 0 ? listed(L.u_off, L.u, a, b, mc)
+                              : which == 1 ? listed(L.x_off, L.x, a, b, mc)
+                                           : listed(L.w_off, L.w, a, b, mc);
+        if (!mirrored) return 0;
+        const bool own = pts_of(b) > pts_of(a) || (pts_of(b) == pts_of(a) && b < a);
+        return own ? 1 : 2;
+    };
+    int64_t n_slots = 0;
+    std::vector<std::vector<int64_t>> incoming(mutual ? nb : 0);
     // leaves: U (points), W (upward equivalent surfaces), L2T (own downward equivalent surface);
     // all three in one pass, or U alone and W + L2T alone
     auto leaf_pass = [&](SegRange& out, bool with_u, bool with_far) {
         out.work0 = (int)work.size();
         for (int b : t.leaves) {
-            int s0 = (int)segs.size();
-            if (with_u) {
-                for (int64_t e = L.u_off[b]; e < L.u_off[b + 1]; ++e) segs.push_back(Seg{0, L.u[e].src, code(L.u[e])});
-                for (int64_t e = L.w_off[b]; e < L.w_off[b + 1]; ++e)
-                    if (small_leaf(L.w[e].src)) segs.push_back(Seg{0, L.w[e].src, code(L.w[e])});
-                if (small_leaf(b))
-                    for (int64_t e = L.x_off[b]; e < L.x_off[b + 1]; ++e) segs.push_back(Seg{0, L.x[e].src, code(L.x[e])});
-            }
-            if (with_far) {
-                for (int64_t e = L.w_off[b]; e < L.w_off[b + 1]; ++e)
-                    if (!small_leaf(L.w[e].src)) segs.push_back(Seg{1, L.w[e].src, code(L.w[e])});
-                segs.push_back(Seg{2, b, kSelf});
-            }
-            int s1 = (int)segs.size();
-            int cnt = t.end[b] - t.begin[b];
-            for (int c0 = 0; c0 < cnt; c0 += 512)
+            const int cnt = t.end[b] - t.begin[b];
+            for (int c0 = 0; c0 < cnt; c0 += 512) {
+                // every target chunk has its own segment list (kind-3 segments own slots)
+                if (c0 > 0 && !(with_u && mutual)) {
+                    Work w0 = work.back();
+                    work.push_back(Work{b, 0, t.begin[b] + c0, std::min(512, cnt - c0), w0.seg0, w0.seg1});
+                    continue;
+                }
+                int s0 = (int)segs.size();
+                if (with_u) {
+                    auto direct = [&](const Entry& en, int which) {
+                        const int role = d_role(b, en, which);
+                        if (role == 2) return;
+                        Seg sg{role == 1 ? 3 : 0, en.src, code(en)};
+                        if (role == 1) {
+                            sg.slot = n_slots;
+                            incoming[en.src].push_back(n_slots);
+                            n_slots += pts_of(en.src);
+                        }
+                        segs.push_back(sg);
+                    };
+                    for (int64_t e = L.u_off[b]; e < L.u_off[b + 1]; ++e) direct(L.u[e], 0);
+                    for (int64_t e = L.w_off[b]; e < L.w_off[b + 1]; ++e)
+                        if (small_leaf(L.w[e].src)) direct(L.w[e], 1);
+                    if (small_leaf(b))
+                        for (int64_t e = L.x_off[b]; e < L.x_off[b + 1]; ++e) direct(L.x[e], 2);
+                }
+                if (with_far) {
+                    for (int64_t e = L.w_off[b]; e < L.w_off[b + 1]; ++e)
+                        if (!small_leaf(L.w[e].src)) segs.push_back(Seg{1, L.w[e].src, code(L.w[e])});
+                    segs.push_back(Seg{2, b, kSelf});
+                }
+                int s1 = (int)segs.size();
                 work.push_back(Work{b, 0, t.begin[b] + c0, std::min(512, cnt - c0), s0, s1});
+            }
         }
         out.nwork = (int)work.size() - out.work0;
     };
     leaf_pass(P->w_leaf_u, true, false);
-    {   // longest items first, so the persistent near-field kernel ends balanced
-        auto cost = [&](const Work& w) {
+    {   // longest items first, so the near-field kernel ends balanced
+        const int w0 = P->w_leaf_u.work0, nw = (int)work.size() - w0;
+        std::vector<int64_t> cost(nw);
+        for (int i = 0; i < nw; ++i) {
+            const Work& w = work[w0 + i];
             int64_t c = 0;
-            for (int sg = w.seg0; sg < w.seg1; ++sg) c += t.end[segs[sg].box] - t.begin[segs[sg].box];
-            return c * (int64_t)w.tcount;
-        };
-        std::stable_sort(work.begin() + P->w_leaf_u.work0, work.end(),
-                         [&](const Work& x, const Work& y) { return cost(x) > cost(y); });
+            for (int sg = w.seg0; sg < w.seg1; ++sg)   // a two-way segment costs about 4/3 of a one-way one
+                c += (int64_t)(t.end[segs[sg].box] - t.begin[segs[sg].box]) * (segs[sg].kind == 3 ? 4 : 3);
+            cost[i] = c * (int64_t)w.tcount;
+        }
+        std::vector<int> order(nw);
+        for (int i = 0; i < nw; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+        std::vector<Work> sorted(nw);
+        for (int i = 0; i < nw; ++i) sorted[i] = work[w0 + order[i]];
+        std::copy(sorted.begin(), sorted.end(), work.begin() + w0);
     }
     leaf_pass(P->w_leaf_far, false, true);
-    {
+    {   // ordered (target, source) pairs of the near field; a two-way segment counts both ways
         int64_t np = 0;
         for (int i = P->w_leaf_u.work0; i < P->w_leaf_u.work0 + P->w_leaf_u.nwork; ++i)
             for (int sg = work[i].seg0; sg < work[i].seg1; ++sg)
-                np += (int64_t)work[i].tcount * (t.end[segs[sg].box] - t.begin[segs[sg].box]);
+                np += (int64_t)work[i].tcount * (t.end[segs[sg].box] - t.begin[segs[sg].box]) *
+                      (segs[sg].kind == 3 ? 2 : 1);
         P->stats.near_pairs = np;
     }
     hipStream_t s = P->setup_stream;
+    P->mutual = mutual;
+    P->n_slots = n_slots;
+    P->n_in = 0;
+    if (mutual) {
+        std::vector<int> ib;
+        std::vector<int64_t> io{0}, is;
+        for (int b = 0; b < nb; ++b) {
+            if (incoming[b].empty()) continue;
+            ib.push_back(b);
+            is.insert(is.end(), incoming[b].begin(), incoming[b].end());
+            io.push_back((int64_t)is.size());
+        }
+        P->n_in = (int)ib.size();
+        P->in_box.upload(ib, s);
+        P->in_off.upload(io, s);
+        P->in_slot.upload(is, s);
+        P->mpart.ensure((size_t)P->k * std::max<int64_t>(n_slots, 1));
+    }
     P->segs.upload(segs, s);
     P->work.upload(work, s);
 
@@ -402,28 +491,41 @@ void build_work(pkifmm_plan* P, int R) {
     // output column = the entry's slot in the group (a bounded temporary), summed per target
     // afterwards in entry order; groups are added to q_d one after another.
     {
-        std::vector<std::vector<int>> in(kNumM2L), out(kNumM2L);
-        std::vector<std::vector<double>> sc(kNumM2L);
+        // one pass for the offsets, one for the per-group slots, one to lay the columns out by
+        // offset (entry order kept within an offset); flat arrays throughout
+        const int64_t nv = L.v_off[nb];
+        std::vector<int16_t> vidx(nv);
+        std::vector<int64_t> per_idx(kNumM2L + 1, 0);
+        for (int b = 0; b < nb; ++b) {
+            const int side = 1 << t.level[b];
+            for (int64_t e = L.v_off[b]; e < L.v_off[b + 1]; ++e) {
+                const Entry& v = L.v[e];
+                const int idx = m2l_offset_index(t.ix[v.src] + v.sx * side - t.ix[b], t.iy[v.src] + v.sy * side - t.iy[b],
+                                                 t.iz[v.src] + v.sz * side - t.iz[b]);
+                if (idx < 0) throw Error(PKIFMM_ERR_NUMERICS, "V-list offset out of range");
+                vidx[e] = (int16_t)idx;
+                ++per_idx[idx + 1];
+            }
+        }
+        for (int d = 0; d < kNumM2L; ++d) per_idx[d + 1] += per_idx[d];
         std::vector<int64_t> goff((size_t)kM2LGroups * (nb + 1), 0);
         std::vector<int> slot_count(kM2LGroups, 0);
         std::vector<std::vector<int>> gtarg(kM2LGroups);
+        std::vector<int64_t> pos(per_idx.begin(), per_idx.end() - 1);
+        std::vector<int> in_c((size_t)nv * R), out_c((size_t)nv * R);
+        std::vector<double> sc_c((size_t)nv * R);
         for (int b = 0; b < nb; ++b) {
             for (int q = 0; q < kM2LGroups; ++q) goff[(size_t)q * (nb + 1) + b] = slot_count[q];
+            const double sc = std::ldexp(1.0, t.level[b]);
             for (int64_t e = L.v_off[b]; e < L.v_off[b + 1]; ++e) {
-                const Entry& v = L.v[e];
-                const int lv = t.level[b];
-                const int side = 1 << lv;
-                int dx = t.ix[v.src] + v.sx * side - t.ix[b];
-                int dy = t.iy[v.src] + v.sy * side - t.iy[b];
-                int dz = t.iz[v.src] + v.sz * side - t.iz[b];
-                int idx = m2l_offset_index(dx, dy, dz);
-                if (idx < 0) throw Error(PKIFMM_ERR_NUMERICS, "V-list offset out of range");
+                const int idx = vidx[e];
                 const int q = idx * kM2LGroups / kNumM2L;
                 const int slot = slot_count[q]++;
+                const int64_t p0 = pos[idx]++ * R;
                 for (int r = 0; r < R; ++r) {
-                    in[idx].push_back(v.src * R + r);
-                    out[idx].push_back(slot * R + r);
-                    sc[idx].push_back(std::ldexp(1.0, lv));
+                    in_c[p0 + r] = L.v[e].src * R + r;
+                    out_c[p0 + r] = slot * R + r;
+                    sc_c[p0 + r] = sc;
                 }
             }
             for (int q = 0; q < kM2LGroups; ++q)
@@ -432,12 +534,18 @@ void build_work(pkifmm_plan* P, int R) {
         for (int q = 0; q < kM2LGroups; ++q) goff[(size_t)q * (nb + 1) + nb] = slot_count[q];
         P->g_m2l.assign(kM2LGroups, GemmRange());
         P->m2l_targets.assign(kM2LGroups, {});
+        g.in.reserve(g.in.size() + 8 * (size_t)nv * R);
+        g.out.reserve(g.out.size() + (size_t)nv * R);
+        g.scale.reserve(g.scale.size() + (size_t)nv * R);
         int max_slots = 1;
         std::vector<int> all_targets;
         for (int q = 0; q < kM2LGroups; ++q) {
             P->g_m2l[q] = range([&] {
-                for (int d = 0; d < kNumM2L; ++d)
-                    if (d * kM2LGroups / kNumM2L == q && !in[d].empty()) add_gemm(g, d, kn, in[d], out[d], sc[d]);
+                for (int d = 0; d < kNumM2L; ++d) {
+                    if (d * kM2LGroups / kNumM2L != q || per_idx[d + 1] == per_idx[d]) continue;
+                    const int64_t c0 = per_idx[d] * R, nc = (per_idx[d + 1] - per_idx[d]) * R;
+                    add_gemm(g, d, kn, in_c.data() + c0, out_c.data() + c0, sc_c.data() + c0, (size_t)nc);
+                }
             });
             P->m2l_targets[q] = {(int)all_targets.size(), (int)gtarg[q].size()};
             all_targets.insert(all_targets.end(), gtarg[q].begin(), gtarg[q].end());
@@ -510,7 +618,7 @@ void run_gemm(pkifmm_plan* P, const GemmRange& gr, const double* ops, int64_t op
 }
 
 void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_surf, int R, bool f32, bool acc_pts,
-             hipStream_t s, bool to_surface = false) {
+             hipStream_t s, bool to_surface = false, int grid_cap = 0) {
     if (w.nwork == 0) return;
     P2PArgs a{};
     a.kernel = P->cfg.kernel;
@@ -536,6 +644,14 @@ void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_sur
     a.out_pts = out_pts;
     a.out_surf = out_surf;
     a.accumulate_pts = acc_pts ? 1 : 0;
+    a.mpart = P->mpart.p;
+    a.n_slots = P->n_slots;
+    a.grid_cap = grid_cap;
+    a.work_counter = nullptr;
+    if (grid_cap > 0 && grid_cap < w.nwork) {   // the counter is cleared by a kernel (graph-safe)
+        a.work_counter = reinterpret_cast<unsigned long long*>(P->counter.p);
+        launch_fill_zero(P->counter.p, 1, s);
+    }
     if (to_surface) launch_p2s(a, s);
     else launch_p2p(a, f32, s);
 }
@@ -585,29 +701,34 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
         }
         const size_t cols = (size_t)t.nbox() * R;
         const int64_t kk = (int64_t)kn * kn;
-        // 2. S2M first, with the whole chip (float64 direct sums feeding the upward solves)
+        // 2. S2M and the upward pass first, with the whole chip: matrix-core GEMMs slow down
+        // many times over when they share compute units with the direct sums
         mark();
         launch_fill_zero(P->q_u.p, (int64_t)cols * kn, s);     // kernels, not memset nodes (graph-safe)
         launch_fill_zero(P->q_d.p, (int64_t)cols * kn, s);
         run_p2p(P, P->w_s2m, nullptr, P->q_u.p, R, false, false, s, true);
-        // 7a. U-list near field: depends only on the permuted densities, so it runs on a
-        // second stream while the tree passes below run on the caller's stream
-        hipStream_t sn = P->near_stream;
-        PK_HIP(hipEventRecord(P->ev_fork, s));
-        PK_HIP(hipStreamWaitEvent(sn, P->ev_fork, 0));
-        mark_on(sn);
-        run_p2p(P, P->w_leaf_u, P->pot.p, nullptr, R, mixed, false, sn);
-        mark_on(sn);
-        PK_HIP(hipEventRecord(P->ev_join, sn));
-        // 3. upward pass
         for (int lv = t.depth; lv >= 0; --lv) {
             run_gemm(P, P->g_m2m[lv], P->m2m.p, 0, kn, 8 * kn, P->phi_u.p, kn, P->q_u.p, kn, true, s, 8);
             run_gemm(P, P->g_up1[lv], P->up_Ut.p, 0, P->r_up, kn, P->q_u.p, kn, P->tmp.p, kn, false, s);
             run_gemm(P, P->g_up2[lv], P->up_VS.p, 0, kn, P->r_up, P->tmp.p, kn, P->phi_u.p, kn, false, s);
         }
         mark();
-        // 4-5. root far field and V-list M2L
+        // 3. near field (U lists and the direct W/X entries) on a second stream; it depends only
+        // on the permuted densities and is the longest part of the pass
+        hipStream_t sn = P->near_stream;
+        PK_HIP(hipEventRecord(P->ev_fork, s));
+        PK_HIP(hipStreamWaitEvent(sn, P->ev_fork, 0));
+        mark_on(sn);
+        run_p2p(P, P->w_leaf_u, P->pot.p, nullptr, R, mixed, false, sn, false, P->near_grid_cap);
+        if (P->mutual)
+            launch_mutual_gather(P->mpart.p, P->n_slots, k, P->in_box.p, P->in_off.p, P->in_slot.p, P->n_in,
+                                 P->b_begin.p, P->b_end.p, n, P->pot.p, sn);
+        mark_on(sn);
+        PK_HIP(hipEventRecord(P->ev_join, sn));
+        // 4-5. in the shadow of the near field: root far field, X list (points to downward check
+        // surfaces) and V-list M2L
         run_gemm(P, P->g_root, P->mroot.p, 0, kn, kn, P->phi_u.p, kn, P->q_d.p, kn, true, s);
+        run_p2p(P, P->w_x, nullptr, P->q_d.p, R, false, false, s, true);
         for (int q = 0; q < kM2LGroups; ++q) {
             if (P->g_m2l[q].ntile == 0) continue;
             run_gemm(P, P->g_m2l[q], P->m2l.p, kk, kn, kn, P->phi_u.p, kn, P->m2l_tmp.p, kn, false, s, 1, false);
@@ -616,8 +737,7 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
                                   P->q_d.p, s);
         }
         mark();
-        // 5-6. X list and the downward pass
-        run_p2p(P, P->w_x, nullptr, P->q_d.p, R, false, false, s, true);
+        // 6. the downward pass
         for (int lv = 0; lv <= t.depth; ++lv) {
             if (lv >= 1) run_gemm(P, P->g_l2l[lv], P->l2l.p, kk, kn, kn, P->phi_d.p, kn, P->q_d.p, kn, true, s);
             run_gemm(P, P->g_dn1[lv], P->dn_Ut.p, 0, P->r_dn, kn, P->q_d.p, kn, P->tmp.p, kn, false, s);
@@ -677,6 +797,10 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
             int dev = 0;
             PK_HIP(hipGetDevice(&dev));
             PK_HIP(hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+            // near field: four workgroups per compute unit take items from a counter in list
+            // (longest-first) order
+            P->near_grid_cap = 4 * P->n_cu;
+            P->counter.ensure(1);
         }
         if (rocblas_create_handle(&h) != rocblas_status_success) throw Error(PKIFMM_ERR_HIP, "rocblas handle");
         rocblas_set_stream(h, s);
@@ -905,9 +1029,9 @@ int pkifmm_get_stats(pkifmm_plan* P, pkifmm_stats* out) {
         for (auto& ev : P->pending_events) {
             if (ev.size() == PKIFMM_NUM_PHASES + 2) {
                 if (hipEventSynchronize(ev.back()) != hipSuccess) bad = hipErrorUnknown;
-                // ev[0]: start of the tree passes; ev[1], ev[2]: near field on its own stream;
-                // ev[3..6]: ends of the up, M2L, down and leaf phases
-                const int a[PKIFMM_NUM_PHASES] = {1, 0, 3, 4, 5}, b[PKIFMM_NUM_PHASES] = {2, 3, 4, 5, 6};
+                // ev[0]: start; ev[1]: end of the upward pass; ev[2], ev[3]: near field on its own
+                // stream; ev[4..6]: ends of the M2L, down and leaf phases
+                const int a[PKIFMM_NUM_PHASES] = {2, 0, 1, 4, 5}, b[PKIFMM_NUM_PHASES] = {3, 1, 4, 5, 6};
                 for (int i = 0; i < PKIFMM_NUM_PHASES && bad == hipSuccess; ++i) {
                     float ms = 0.f;
                     if (hipEventElapsedTime(&ms, ev[a[i]], ev[b[i]]) != hipSuccess) bad = hipErrorUnknown;
