@@ -59,6 +59,32 @@ struct DBuf {
     }
 };
 
+// Page-locked host buffer owned by a plan (device-to-host copies without a staging copy).
+template <class T>
+struct PinnedBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    PinnedBuf() = default;
+    PinnedBuf(const PinnedBuf&) = delete;
+    PinnedBuf& operator=(const PinnedBuf&) = delete;
+    ~PinnedBuf() { release(); }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void ensure(size_t count) {
+        if (count <= n && p) return;
+        release();
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        if (hipHostMalloc((void**)&p, bytes, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            throw Error(PKIFMM_ERR_OOM, "hipHostMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
+        n = std::max<size_t>(count, 1);
+    }
+};
+
 // ---------------------------------------------------------------- tree (host topology)
 
 struct HostTree {

@@ -17,10 +17,11 @@ void launch_keys(const double* xyz, int64_t n, double L, unsigned mask, uint64_t
 void radix_sort_pairs(uint64_t* keys_in, uint64_t* keys_out, uint32_t* vals_in, uint32_t* vals_out,
                       int64_t n, DBuf<char>& temp, hipStream_t s, int n_seg = 1, const int64_t* off = nullptr);
 // Sorted SoA coordinates xs[3][n] = u[:, perm]; per-point float offsets from the
-// centre of the point's leaf (pt_box[sorted index] gives the leaf box).
+// centre of the point's leaf (every leaf box listed once in leaves).
 void launch_gather_points(const double* u, const uint32_t* perm, int64_t n, double* xs, hipStream_t s);
-void launch_leaf_offsets(const double* xs, int64_t n, const int* pt_box, const int* box_level,
-                         const int* box_ix, const int* box_iy, const int* box_iz, float* off, hipStream_t s);
+void launch_leaf_offsets(const double* xs, int64_t n, const int* leaves, int n_leaves, const int* box_begin,
+                         const int* box_end, const int* box_level, const int* box_ix, const int* box_iy,
+                         const int* box_iz, float* off, hipStream_t s);
 // density [R][n][k] input order -> ds [R][k][n] sorted (double) and optionally float
 void launch_permute_density(const double* dens, const uint32_t* perm, int64_t n, int R, int k,
                             double* ds, float* ds32, hipStream_t s);

@@ -67,11 +67,19 @@ struct Gemm {      // host-side description of one grouped GEMM launch
 };
 
 struct GemmRange {
+    int set = 0;            // 0: tree-pass GEMMs (levels, root), 1: M2L
     int tile0 = 0, ntile = 0;
 };
 
 struct SegRange {
+    int set = 0;            // 0: S2M and X items, 1: leaf items (near field, W + L2T)
     int work0 = 0, nwork = 0;
+};
+
+struct GemmSet {            // device copy of one Gemm description
+    DBuf<Tile> tiles;
+    DBuf<int> col_in, col_out;
+    DBuf<double> col_scale;
 };
 
 }  // namespace
@@ -116,18 +124,17 @@ struct pkifmm_plan {
     DBuf<float> off;
     DBuf<char> sort_temp;
     DBuf<int> err_flag;
-    DBuf<int> b_level, b_ix, b_iy, b_iz, b_begin, b_end, pt_box;
+    DBuf<int> b_level, b_ix, b_iy, b_iz, b_begin, b_end, leaf_boxes;
+    PinnedBuf<uint64_t> keys_host;
     DBuf<int64_t> v_off;
     DBuf<int> v_targets;
     int n_v_targets = 0;
 
     // work lists for the current R
     int R_built = -1;
-    std::vector<Seg> segs_h;
-    std::vector<Work> work_h;
     SegRange w_s2m, w_x, w_leaf_u, w_leaf_far;
-    DBuf<Seg> segs;
-    DBuf<Work> work;
+    DBuf<Seg> segs[2];                  // per SegRange set
+    DBuf<Work> work[2];
     // U-list pairs evaluated once (one right-hand side): partial slots and, per leaf that is
     // the other side of such pairs, its slots in a fixed order
     int near_grid_cap = 0;              // near-field workgroups resident at once (0: one per item)
@@ -146,9 +153,7 @@ struct pkifmm_plan {
     DBuf<int64_t> v_goff;                                // per group: CSR over boxes of temp slots
     DBuf<int> v_gtargets;
     int m2l_slots = 1;
-    DBuf<Tile> tiles;
-    DBuf<int> col_in, col_out;
-    DBuf<double> col_scale;
+    GemmSet gsets[2];                   // per GemmRange set
 
     // workspace
     DBuf<double> ds, q_u, phi_u, q_d, phi_d, tmp, m2l_tmp, pot, sums, split_tmp;
@@ -252,19 +257,22 @@ void add_gemm(Gemm& g, int op, int M, const std::vector<int>& in, const std::vec
 
 double box_edge(const HostTree& t, int b) { return std::ldexp(1.0, -t.level[b]); }
 
-void build_work(pkifmm_plan* P, int R) {
+// Work lists of one (tree, R) are built in three stages, each uploaded on the setup stream
+// into its own buffers, so that an evaluation can launch the kernels of a stage while the
+// host builds the next one.
+
+// Stage 1: S2M and X items, per-level and root GEMMs, workspace.
+void build_stage_tree(pkifmm_plan* P, int R) {
     const HostTree& t = P->tree;
     const HostLists& L = P->lists;
     const int nb = t.nbox();
     const int ns = P->n_surf;
-    auto& segs = P->segs_h;
-    auto& work = P->work_h;
-    segs.clear();
-    work.clear();
+    std::vector<Seg> segs;
+    std::vector<Work> work;
     const int kSelf = 13;
     auto code = [](const Entry& e) { return (e.sx + 1) * 9 + (e.sy + 1) * 3 + (e.sz + 1); };
     // S2M: leaf points -> own upward check surface
-    P->w_s2m.work0 = (int)work.size();
+    P->w_s2m = SegRange{0, (int)work.size(), 0};
     for (int b : t.leaves) {
         int s0 = (int)segs.size();
         segs.push_back(Seg{0, b, kSelf});
@@ -276,7 +284,7 @@ void build_work(pkifmm_plan* P, int R) {
     // than a surface takes its X-list sources directly at its points
     auto small_leaf = [&](int b) { return t.is_leaf(b) && t.end[b] - t.begin[b] <= ns; };
     // X list: leaf points -> downward check surfaces
-    P->w_x.work0 = (int)work.size();
+    P->w_x = SegRange{0, (int)work.size(), 0};
     for (int b = 0; b < nb; ++b) {
         if (L.x_off[b + 1] == L.x_off[b] || small_leaf(b)) continue;
         int s0 = (int)segs.size();
@@ -285,6 +293,136 @@ void build_work(pkifmm_plan* P, int R) {
         for (int c0 = 0; c0 < ns; c0 += 64) work.push_back(Work{b, 1, c0, std::min(64, ns - c0), s0, s1});
     }
     P->w_x.nwork = (int)work.size() - P->w_x.work0;
+    hipStream_t s = P->setup_stream;
+    P->segs[0].upload(segs, s);
+    P->work[0].upload(work, s);
+
+    // GEMM launches
+    Gemm g;
+    const int kn = P->kn;
+    auto range = [&](auto&& fill) {
+        GemmRange r;
+        r.set = 0;
+        r.tile0 = (int)g.tiles.size();
+        fill();
+        r.ntile = (int)g.tiles.size() - r.tile0;
+        return r;
+    };
+    const int depth = t.depth;
+    P->g_m2m.assign(depth + 1, GemmRange());
+    P->g_up1.assign(depth + 1, GemmRange());
+    P->g_up2.assign(depth + 1, GemmRange());
+    P->g_dn1.assign(depth + 1, GemmRange());
+    P->g_dn2.assign(depth + 1, GemmRange());
+    P->g_l2l.assign(depth + 1, GemmRange());
+    for (int lv = 0; lv <= depth; ++lv) {
+        const int b0 = t.level_start[lv], b1 = t.level_start[lv + 1];
+        const double h = std::ldexp(1.0, -lv);
+        // M2M into the non-leaf boxes of this level: [M2M_0 | ... | M2M_7] times the stacked
+        // densities of the eight children (K blocked by octant), one launch
+        P->g_m2m[lv] = range([&] {
+            std::vector<int> in, out;
+            std::vector<double> sc;
+            for (int b = b0; b < b1; ++b) {
+                if (t.is_leaf(b)) continue;
+                for (int r = 0; r < R; ++r) {
+                    for (int o = 0; o < 8; ++o) {
+                        int c = t.child[8 * b + o];
+                        in.push_back(c < 0 ? -1 : c * R + r);
+                    }
+                    out.push_back(b * R + r);
+                    sc.push_back(1.0 / h);
+                }
+            }
+            add_gemm(g, 0, kn, in, out, sc, 8);
+        });
+        std::vector<int> cols;
+        std::vector<double> one, hs;
+        for (int b = b0; b < b1; ++b)
+            for (int r = 0; r < R; ++r) {
+                cols.push_back(b * R + r);
+                one.push_back(1.0);
+                hs.push_back(h);
+            }
+        P->g_up1[lv] = range([&] { add_gemm(g, 0, P->r_up, cols, cols, one); });
+        P->g_up2[lv] = range([&] { add_gemm(g, 0, kn, cols, cols, hs); });
+        P->g_dn1[lv] = range([&] { add_gemm(g, 0, P->r_dn, cols, cols, one); });
+        P->g_dn2[lv] = range([&] { add_gemm(g, 0, kn, cols, cols, hs); });
+        if (lv >= 1)
+            P->g_l2l[lv] = range([&] {
+                const double hp = 2.0 * h;
+                for (int o = 0; o < 8; ++o) {
+                    std::vector<int> in, out;
+                    std::vector<double> sc;
+                    for (int b = b0; b < b1; ++b) {
+                        int par = t.parent[b];
+                        if (t.child[8 * par + o] != b) continue;
+                        for (int r = 0; r < R; ++r) {
+                            in.push_back(par * R + r);
+                            out.push_back(b * R + r);
+                            sc.push_back(1.0 / hp);
+                        }
+                    }
+                    add_gemm(g, o, kn, in, out, sc);
+                }
+            });
+    }
+    P->g_root = range([&] {   // every problem's root
+        std::vector<int> c;
+        std::vector<double> one;
+        for (int b = t.level_start[0]; b < t.level_start[1]; ++b)
+            for (int r = 0; r < R; ++r) {
+                c.push_back(b * R + r);
+                one.push_back(1.0);
+            }
+        add_gemm(g, 0, kn, c, c, one);
+    });
+    GemmSet& G = P->gsets[0];
+    G.tiles.upload(g.tiles, s);
+    G.col_in.upload(g.in, s);
+    G.col_out.upload(g.out, s);
+    G.col_scale.upload(g.scale, s);
+
+    // workspace
+    const size_t cols = (size_t)nb * R;
+    P->q_u.ensure(cols * kn);
+    P->phi_u.ensure(cols * kn);
+    P->q_d.ensure(cols * kn);
+    P->phi_d.ensure(cols * kn);
+    P->tmp.ensure(cols * kn);
+    P->ds.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
+    if (P->cfg.precision == PKIFMM_MIXED) P->ds32.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
+    P->pot.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
+    P->sums.ensure((size_t)P->n_problems * R * P->k);
+    {   // split-K partial tiles: the largest small launch of the tree passes
+        int64_t need = 1;
+        auto consider = [&](const GemmRange& gr, int K) {
+            if (gr.ntile == 0) return;
+            need = std::max<int64_t>(need, (int64_t)gr.ntile * gemm_split_factor(gr.ntile, K) * 64 * 64);
+        };
+        for (int lv = 0; lv <= depth; ++lv) {
+            consider(P->g_m2m[lv], 8 * kn);
+            consider(P->g_up1[lv], kn); consider(P->g_up2[lv], P->r_up);
+            consider(P->g_dn1[lv], kn); consider(P->g_dn2[lv], P->r_dn);
+            consider(P->g_l2l[lv], kn);
+        }
+        consider(P->g_root, kn);
+        P->split_tmp.ensure(need);
+    }
+    PK_HIP(hipStreamSynchronize(s));
+}
+
+// Stage 2: the leaf items (near field; W + L2T) and the two-way pair bookkeeping.
+void build_stage_near(pkifmm_plan* P, int R) {
+    const HostTree& t = P->tree;
+    const HostLists& L = P->lists;
+    const int nb = t.nbox();
+    const int ns = P->n_surf;
+    std::vector<Seg> segs;
+    std::vector<Work> work;
+    const int kSelf = 13;
+    auto code = [](const Entry& e) { return (e.sx + 1) * 9 + (e.sy + 1) * 3 + (e.sz + 1); };
+    auto small_leaf = [&](int b) { return t.is_leaf(b) && t.end[b] - t.begin[b] <= ns; };
     // Direct leaf-to-leaf pairs of different leaves are evaluated once when there is one
     // right-hand side: the kernel is symmetric, A in U(B) with shift p exactly when B in U(A)
     // with -p, and a small leaf A taken directly from W(B) is B taken directly from X(A) with
@@ -318,6 +456,7 @@ void build_work(pkifmm_plan* P, int R) {
     // leaves: U (points), W (upward equivalent surfaces), L2T (own downward equivalent surface);
     // all three in one pass, or U alone and W + L2T alone
     auto leaf_pass = [&](SegRange& out, bool with_u, bool with_far) {
+        out.set = 1;
         out.work0 = (int)work.size();
         for (int b : t.leaves) {
             const int cnt = t.end[b] - t.begin[b];
@@ -404,88 +543,27 @@ void build_work(pkifmm_plan* P, int R) {
         P->in_slot.upload(is, s);
         P->mpart.ensure((size_t)P->k * std::max<int64_t>(n_slots, 1));
     }
-    P->segs.upload(segs, s);
-    P->work.upload(work, s);
+    P->segs[1].upload(segs, s);
+    P->work[1].upload(work, s);
+    PK_HIP(hipStreamSynchronize(s));
+}
 
-    // GEMM launches
-    Gemm g;
+// Stage 3: M2L GEMMs grouped by offset.
+void build_stage_m2l(pkifmm_plan* P, int R) {
+    const HostTree& t = P->tree;
+    const HostLists& L = P->lists;
+    const int nb = t.nbox();
     const int kn = P->kn;
+    hipStream_t s = P->setup_stream;
+    Gemm g;
     auto range = [&](auto&& fill) {
         GemmRange r;
+        r.set = 1;
         r.tile0 = (int)g.tiles.size();
         fill();
         r.ntile = (int)g.tiles.size() - r.tile0;
         return r;
     };
-    const int depth = t.depth;
-    P->g_m2m.assign(depth + 1, GemmRange());
-    P->g_up1.assign(depth + 1, GemmRange());
-    P->g_up2.assign(depth + 1, GemmRange());
-    P->g_dn1.assign(depth + 1, GemmRange());
-    P->g_dn2.assign(depth + 1, GemmRange());
-    P->g_l2l.assign(depth + 1, GemmRange());
-    for (int lv = 0; lv <= depth; ++lv) {
-        const int b0 = t.level_start[lv], b1 = t.level_start[lv + 1];
-        const double h = std::ldexp(1.0, -lv);
-        // M2M into the non-leaf boxes of this level: [M2M_0 | ... | M2M_7] times the stacked
-        // densities of the eight children (K blocked by octant), one launch
-        P->g_m2m[lv] = range([&] {
-            std::vector<int> in, out;
-            std::vector<double> sc;
-            for (int b = b0; b < b1; ++b) {
-                if (t.is_leaf(b)) continue;
-                for (int r = 0; r < R; ++r) {
-                    for (int o = 0; o < 8; ++o) {
-                        int c = t.child[8 * b + o];
-                        in.push_back(c < 0 ? -1 : c * R + r);
-                    }
-                    out.push_back(b * R + r);
-                    sc.push_back(1.0 / h);
-                }
-            }
-            add_gemm(g, 0, kn, in, out, sc, 8);
-        });
-        std::vector<int> cols;
-        std::vector<double> one, hs;
-        for (int b = b0; b < b1; ++b)
-            for (int r = 0; r < R; ++r) {
-                cols.push_back(b * R + r);
-                one.push_back(1.0);
-                hs.push_back(h);
-            }
-        P->g_up1[lv] = range([&] { add_gemm(g, 0, P->r_up, cols, cols, one); });
-        P->g_up2[lv] = range([&] { add_gemm(g, 0, kn, cols, cols, hs); });
-        P->g_dn1[lv] = range([&] { add_gemm(g, 0, P->r_dn, cols, cols, one); });
-        P->g_dn2[lv] = range([&] { add_gemm(g, 0, kn, cols, cols, hs); });
-        if (lv >= 1)
-            P->g_l2l[lv] = range([&] {
-                const double hp = 2.0 * h;
-                for (int o = 0; o < 8; ++o) {
-                    std::vector<int> in, out;
-                    std::vector<double> sc;
-                    for (int b = b0; b < b1; ++b) {
-                        int par = t.parent[b];
-                        if (t.child[8 * par + o] != b) continue;
-                        for (int r = 0; r < R; ++r) {
-                            in.push_back(par * R + r);
-                            out.push_back(b * R + r);
-                            sc.push_back(1.0 / hp);
-                        }
-                    }
-                    add_gemm(g, o, kn, in, out, sc);
-                }
-            });
-    }
-    P->g_root = range([&] {   // every problem's root
-        std::vector<int> c;
-        std::vector<double> one;
-        for (int b = t.level_start[0]; b < t.level_start[1]; ++b)
-            for (int r = 0; r < R; ++r) {
-                c.push_back(b * R + r);
-                one.push_back(1.0);
-            }
-        add_gemm(g, 0, kn, c, c, one);
-    });
     // M2L grouped by offset; the 316 offsets are split into kM2LGroups fixed groups (by offset
     // index, so the per-target summation order never depends on the batch).  Within a group,
     // output column = the entry's slot in the group (a bounded temporary), summed per target
@@ -555,39 +633,19 @@ void build_work(pkifmm_plan* P, int R) {
         P->v_gtargets.upload(all_targets, s);
         P->m2l_slots = max_slots;
     }
-    P->tiles.upload(g.tiles, s);
-    P->col_in.upload(g.in, s);
-    P->col_out.upload(g.out, s);
-    P->col_scale.upload(g.scale, s);
-
-    // workspace
-    const size_t cols = (size_t)nb * R;
-    P->q_u.ensure(cols * kn);
-    P->phi_u.ensure(cols * kn);
-    P->q_d.ensure(cols * kn);
-    P->phi_d.ensure(cols * kn);
-    P->tmp.ensure(cols * kn);
+    GemmSet& G = P->gsets[1];
+    G.tiles.upload(g.tiles, s);
+    G.col_in.upload(g.in, s);
+    G.col_out.upload(g.out, s);
+    G.col_scale.upload(g.scale, s);
     P->m2l_tmp.ensure(std::max<size_t>(1, (size_t)P->m2l_slots * R * kn));
-    P->ds.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
-    if (P->cfg.precision == PKIFMM_MIXED) P->ds32.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
-    P->pot.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
-    P->sums.ensure((size_t)P->n_problems * R * P->k);
-    {   // split-K partial tiles: the largest small launch of the tree passes
-        int64_t need = 1;
-        auto consider = [&](const GemmRange& gr, int K) {
-            if (gr.ntile == 0) return;
-            need = std::max<int64_t>(need, (int64_t)gr.ntile * gemm_split_factor(gr.ntile, K) * 64 * 64);
-        };
-        for (int lv = 0; lv <= depth; ++lv) {
-            consider(P->g_m2m[lv], 8 * kn);
-            consider(P->g_up1[lv], kn); consider(P->g_up2[lv], P->r_up);
-            consider(P->g_dn1[lv], kn); consider(P->g_dn2[lv], P->r_dn);
-            consider(P->g_l2l[lv], kn);
-        }
-        consider(P->g_root, kn);
-        P->split_tmp.ensure(need);
-    }
     PK_HIP(hipStreamSynchronize(s));
+}
+
+void build_work(pkifmm_plan* P, int R) {
+    build_stage_tree(P, R);
+    build_stage_near(P, R);
+    build_stage_m2l(P, R);
     P->R_built = R;
 }
 
@@ -604,13 +662,14 @@ void run_gemm(pkifmm_plan* P, const GemmRange& gr, const double* ops, int64_t op
     a.ldb = ldb;
     a.C = C;
     a.ldc = ldc;
-    a.tiles = P->tiles.p + gr.tile0;
+    const GemmSet& G = P->gsets[gr.set];
+    a.tiles = G.tiles.p + gr.tile0;
     a.n_tiles = gr.ntile;
-    a.in_col = P->col_in.p;
+    a.in_col = G.col_in.p;
     a.in_stride = nkb;
     a.kblock = K / nkb;
-    a.out_col = P->col_out.p;
-    a.scale = P->col_scale.p;
+    a.out_col = G.col_out.p;
+    a.scale = G.col_scale.p;
     a.accumulate = acc ? 1 : 0;
     // the per-level launches split K (latency-bound, few tiles); M2L never does
     if (allow_split) launch_gemm(a, s, P->split_tmp.p, (int64_t)P->split_tmp.n);
@@ -638,8 +697,8 @@ void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_sur
     a.box_begin = P->b_begin.p;
     a.box_end = P->b_end.p;
     a.usurf = P->usurf.p;
-    a.segs = P->segs.p;
-    a.work = P->work.p + w.work0;
+    a.segs = P->segs[w.set].p;
+    a.work = P->work[w.set].p + w.work0;
     a.n_work = w.nwork;
     a.out_pts = out_pts;
     a.out_surf = out_surf;
@@ -669,7 +728,7 @@ void drop_graph(pkifmm_plan* P) {
 
 // Enqueue one evaluation on stream s (no host synchronisation unless `checks`).
 void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* potential, hipStream_t s, bool checks,
-                      bool allow_timing) {
+                      bool allow_timing, bool build = false) {
         const int64_t n = P->n;
         const int k = P->k, kn = P->kn;
         const HostTree& t = P->tree;
@@ -684,6 +743,7 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
             ev.push_back(e);
         };
         auto mark = [&]() { mark_on(s); };
+        if (build) build_stage_tree(P, R);
         launch_permute_density(density, P->perm.p, n, R, k, P->ds.p, mixed ? P->ds32.p : nullptr, s);
         const int naxes = __builtin_popcount(P->cfg.periodic_mask);
         if (checks && (naxes == 1 || naxes == 2) && !(P->cfg.flags & PKIFMM_SKIP_CHECKS)) {
@@ -713,6 +773,7 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
             run_gemm(P, P->g_up2[lv], P->up_VS.p, 0, kn, P->r_up, P->tmp.p, kn, P->phi_u.p, kn, false, s);
         }
         mark();
+        if (build) build_stage_near(P, R);
         // 3. near field (U lists and the direct W/X entries) on a second stream; it depends only
         // on the permuted densities and is the longest part of the pass
         hipStream_t sn = P->near_stream;
@@ -725,6 +786,7 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
                                  P->b_begin.p, P->b_end.p, n, P->pot.p, sn);
         mark_on(sn);
         PK_HIP(hipEventRecord(P->ev_join, sn));
+        if (build) build_stage_m2l(P, R);
         // 4-5. in the shadow of the near field: root far field, X list (points to downward check
         // surfaces) and V-list M2L
         run_gemm(P, P->g_root, P->mroot.p, 0, kn, kn, P->phi_u.p, kn, P->q_d.p, kn, true, s);
@@ -752,6 +814,7 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
         launch_unpermute(P->pot.p, P->perm.p, n, R, k, c, potential, s);
         mark();
         if (timing) P->pending_events.push_back(ev);
+        if (build) P->R_built = R;
 }
 
 }  // namespace
@@ -908,12 +971,13 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
         radix_sort_pairs(P->keys_a.p, P->keys_b.p, P->vals_a.p, P->perm.p, n, P->sort_temp, s, n_problems,
                          P->prob_off.p);
         launch_gather_points(P->u_wrapped.p, P->perm.p, n, P->xs.p, s);
-        std::vector<uint64_t> keys(n);
-        if (n) PK_HIP(hipMemcpyAsync(keys.data(), P->keys_b.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
+        P->keys_host.ensure(m);
+        const uint64_t* keys = P->keys_host.p;
+        if (n) PK_HIP(hipMemcpyAsync(P->keys_host.p, P->keys_b.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
         PK_HIP(hipStreamSynchronize(s));
         if (err) throw Error(PKIFMM_ERR_OUT_OF_BOX, "coordinate outside the box on a non-periodic axis, or not finite");
         if (n_problems == 1) {
-            build_tree_host(keys.data(), n, P->cfg.max_pts_per_leaf, P->tree);
+            build_tree_host(keys, n, P->cfg.max_pts_per_leaf, P->tree);
             build_lists_host(P->tree, P->cfg.periodic_mask, P->lists);
             P->box_prob.assign(P->tree.nbox(), 0);
         } else {
@@ -921,7 +985,7 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
             std::vector<HostLists> lists(n_problems);
 #pragma omp parallel for schedule(dynamic, 1)
             for (int q = 0; q < n_problems; ++q) {
-                build_tree_host(keys.data() + poff[q], poff[q + 1] - poff[q], P->cfg.max_pts_per_leaf, trees[q]);
+                build_tree_host(keys + poff[q], poff[q + 1] - poff[q], P->cfg.max_pts_per_leaf, trees[q]);
                 build_lists_host(trees[q], P->cfg.periodic_mask, lists[q]);
             }
             merge_forest(trees, lists, poff, P->tree, P->lists, P->box_prob);
@@ -933,13 +997,11 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
         P->b_iz.upload(t.iz, s);
         P->b_begin.upload(t.begin, s);
         P->b_end.upload(t.end, s);
-        std::vector<int> pb(m, 0);
-        for (int b : t.leaves)
-            for (int i = t.begin[b]; i < t.end[b]; ++i) pb[i] = b;
-        P->pt_box.upload(pb, s);
+        P->leaf_boxes.upload(t.leaves, s);
         if (P->cfg.precision == PKIFMM_MIXED) {
             P->off.ensure(6 * m);
-            launch_leaf_offsets(P->xs.p, n, P->pt_box.p, P->b_level.p, P->b_ix.p, P->b_iy.p, P->b_iz.p, P->off.p, s);
+            launch_leaf_offsets(P->xs.p, n, P->leaf_boxes.p, (int)t.leaves.size(), P->b_begin.p, P->b_end.p, P->b_level.p,
+                                P->b_ix.p, P->b_iy.p, P->b_iz.p, P->off.p, s);
         }
         std::vector<int> vt;
         for (int b = 0; b < t.nbox(); ++b)
@@ -983,10 +1045,12 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
     hipStream_t s = (hipStream_t)stream;
     try {
         if (P->n == 0) return PKIFMM_OK;
-        if (P->R_built != R) build_work(P, R);
         if (!(P->cfg.flags & PKIFMM_GRAPH)) {
-            enqueue_evaluate(P, R, density, potential, s, true, true);
+            // a first evaluation on new points builds its work lists stage by stage, each
+            // while the kernels of the previous stage run
+            enqueue_evaluate(P, R, density, potential, s, true, true, P->R_built != R);
         } else {
+            if (P->R_built != R) build_work(P, R);
             // captured once per (tree, R, buffers) on a library stream, replayed on the caller's
             const bool same = P->gexec && P->g_key_R == R && P->g_key_in == density && P->g_key_out == potential &&
                               P->g_key_gen == P->generation;
