@@ -97,14 +97,16 @@ typedef struct {
                                     (once per points/n_rhs/density/potential pointers) and replays
                                     it on `stream`; implies no neutrality check and no phase timing */
 
-/* phases of one evaluation, on the caller's stream in this order except the near field,
- * which runs on a library-owned second stream after the upward pass, concurrently with the
- * M2L and downward phases */
+/* phases of one evaluation: up and M2L on the caller's stream; the near field on a
+ * library-owned stream, starting during M2L; then down and leaf on the caller's stream.
+ * The X list runs on a third stream beside the upward pass and M2L (its time counts in
+ * neither phase) */
 #define PKIFMM_PHASE_NEAR 0      /* U-list and direct W/X sums (leaf points to leaf points) */
-#define PKIFMM_PHASE_UP 1        /* density permutation, S2M, M2M, upward solves */
-#define PKIFMM_PHASE_M2L 2       /* root far field, X list, V-list M2L and its per-target sums */
-#define PKIFMM_PHASE_DOWN 3      /* L2L, downward solves */
-#define PKIFMM_PHASE_LEAF 4      /* W-list M2T, L2T, output permutation (after the near field) */
+#define PKIFMM_PHASE_UP 1        /* S2M, M2M, upward solves */
+#define PKIFMM_PHASE_M2L 2       /* root far field, V-list M2L and its per-target sums */
+#define PKIFMM_PHASE_DOWN 3      /* after M2L: waits for the near field and the X list, then L2L
+                                    and the downward solves */
+#define PKIFMM_PHASE_LEAF 4      /* W-list M2T, L2T, output permutation */
 #define PKIFMM_NUM_PHASES 5
 
 typedef struct {
@@ -164,10 +166,12 @@ int pkifmm_set_points_batch(pkifmm_plan *plan, int n_problems, const int64_t *co
  * Evaluate the periodic sum for n_rhs densities on the current points.
  *   density:   device, [n_rhs][n][k] float64 (k = 1 Laplace, 3 Stokes), input order
  *   potential: device, [n_rhs][n][k] float64, overwritten, input order
- * Work is enqueued on `stream` (the near field on a library-owned stream that
- * forks from and joins back into `stream`, so completion of `stream` covers
- * all of it); the call returns after enqueueing unless the SP/DP neutrality
- * check runs (it reads one reduction back).  The output is float64 in every
+ * Work is enqueued on `stream` (the near field and the X list on two
+ * library-owned streams that fork from and join back into `stream`, so
+ * completion of `stream` covers all of it); the call returns after enqueueing
+ * unless the SP/DP neutrality check runs (it reads one reduction back).  The
+ * first evaluation after set_points also builds the work lists on the host,
+ * stage by stage while the previous stage's kernels run.  The output is float64 in every
  * precision mode.
  * Errors: NO_POINTS, INVALID_ARG, INCOMPATIBLE, OOM, HIP.
  */

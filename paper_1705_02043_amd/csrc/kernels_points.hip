@@ -125,6 +125,11 @@ __global__ void k_fill_zero(double* __restrict__ x, int64_t n) {
         x[i] = 0.0;
 }
 
+__global__ void k_add_into(double* __restrict__ y, const double* __restrict__ x, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += x[i];
+}
+
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -132,6 +137,12 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 void launch_fill_zero(double* x, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<int64_t>(nblk(n, 256), 4096)), dim3(256), 0, s, x, n);
+    PK_HIP(hipGetLastError());
+}
+
+void launch_add_into(double* y, const double* x, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_add_into, dim3((unsigned)std::min<int64_t>(nblk(n, 256), 4096)), dim3(256), 0, s, y, x, n);
     PK_HIP(hipGetLastError());
 }
 

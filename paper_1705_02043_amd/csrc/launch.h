@@ -30,6 +30,8 @@ void launch_unpermute(const double* pot, const uint32_t* perm, int64_t n, int R,
                       double* out, hipStream_t s);
 // x[0..n) = 0 with a kernel (no memset node under graph capture)
 void launch_fill_zero(double* x, int64_t n, hipStream_t s);
+// y[0..n) += x[0..n)
+void launch_add_into(double* y, const double* x, int64_t n, hipStream_t s);
 // per-problem, per-RHS, per-component sums of the sorted densities (neutrality check):
 // out [n_prob][R*k]; problem i owns sorted points [off[i], off[i+1]) (off: device)
 void launch_density_sums(const double* ds, int64_t n, int R, int k, const int64_t* off, int n_prob, double* out,

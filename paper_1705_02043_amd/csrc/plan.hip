@@ -25,7 +25,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <memory>
+#include <thread>
 
 #include "launch.h"
 
@@ -90,8 +92,10 @@ struct pkifmm_plan {
     int r_up = 0, r_dn = 0;
     std::string last_error;
     hipStream_t setup_stream = nullptr;
-    hipStream_t near_stream = nullptr;          // U-list near field, concurrent with the tree passes
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t setup_stream2 = nullptr;        // uploads of the M2L work lists (built on a second host thread)
+    hipStream_t near_stream = nullptr;          // near field, concurrent with the end of M2L
+    hipStream_t x_stream = nullptr;             // X list, beside the upward pass and M2L
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_xjoin = nullptr;
     hipStream_t capture_stream = nullptr;      // PKIFMM_GRAPH: the evaluation is captured here
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -156,7 +160,7 @@ struct pkifmm_plan {
     GemmSet gsets[2];                   // per GemmRange set
 
     // workspace
-    DBuf<double> ds, q_u, phi_u, q_d, phi_d, tmp, m2l_tmp, pot, sums, split_tmp;
+    DBuf<double> ds, q_u, phi_u, q_d, q_x, phi_d, tmp, m2l_tmp, pot, sums, split_tmp;
     DBuf<float> ds32;
 
     pkifmm_stats stats{};
@@ -388,6 +392,7 @@ void build_stage_tree(pkifmm_plan* P, int R) {
     P->q_u.ensure(cols * kn);
     P->phi_u.ensure(cols * kn);
     P->q_d.ensure(cols * kn);
+    P->q_x.ensure(cols * kn);
     P->phi_d.ensure(cols * kn);
     P->tmp.ensure(cols * kn);
     P->ds.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
@@ -453,51 +458,105 @@ void build_stage_near(pkifmm_plan* P, int R) {
     };
     int64_t n_slots = 0;
     std::vector<std::vector<int64_t>> incoming(mutual ? nb : 0);
-    // leaves: U (points), W (upward equivalent surfaces), L2T (own downward equivalent surface);
-    // all three in one pass, or U alone and W + L2T alone
-    auto leaf_pass = [&](SegRange& out, bool with_u, bool with_far) {
+    // near-field items (U lists and the direct W/X entries), one per chunk of up to 512 target
+    // points: the leaves are split into contiguous ranges built on separate host threads and
+    // concatenated in leaf order, so segments, slots and incoming lists come out exactly as one
+    // sequential pass over the leaves would produce them
+    auto near_pass = [&](SegRange& out) {
         out.set = 1;
         out.work0 = (int)work.size();
-        for (int b : t.leaves) {
-            const int cnt = t.end[b] - t.begin[b];
-            for (int c0 = 0; c0 < cnt; c0 += 512) {
-                // every target chunk has its own segment list (kind-3 segments own slots)
-                if (c0 > 0 && !(with_u && mutual)) {
-                    Work w0 = work.back();
-                    work.push_back(Work{b, 0, t.begin[b] + c0, std::min(512, cnt - c0), w0.seg0, w0.seg1});
-                    continue;
-                }
-                int s0 = (int)segs.size();
-                if (with_u) {
+        const int nl = (int)t.leaves.size();
+        const int nth = std::max(1, std::min(8, nl / 64));
+        struct Part {
+            std::vector<Seg> segs;
+            std::vector<Work> work;
+            std::vector<std::pair<int, int64_t>> inc;   // (other leaf, local slot)
+            int64_t slots = 0;
+            std::exception_ptr err;
+        };
+        std::vector<Part> parts(nth);
+        auto run = [&](int th) {
+            Part& pt = parts[th];
+            try {
+                const int l0 = (int)((int64_t)nl * th / nth), l1 = (int)((int64_t)nl * (th + 1) / nth);
+                std::vector<Seg> near;     // one leaf's direct segments (roles decided once per leaf)
+                for (int li = l0; li < l1; ++li) {
+                    const int b = t.leaves[li];
+                    const int cnt = pts_of(b);
+                    if (cnt == 0) continue;
+                    near.clear();
                     auto direct = [&](const Entry& en, int which) {
                         const int role = d_role(b, en, which);
-                        if (role == 2) return;
-                        Seg sg{role == 1 ? 3 : 0, en.src, code(en)};
-                        if (role == 1) {
-                            sg.slot = n_slots;
-                            incoming[en.src].push_back(n_slots);
-                            n_slots += pts_of(en.src);
-                        }
-                        segs.push_back(sg);
+                        if (role != 2) near.push_back(Seg{role == 1 ? 3 : 0, en.src, code(en)});
                     };
                     for (int64_t e = L.u_off[b]; e < L.u_off[b + 1]; ++e) direct(L.u[e], 0);
                     for (int64_t e = L.w_off[b]; e < L.w_off[b + 1]; ++e)
                         if (small_leaf(L.w[e].src)) direct(L.w[e], 1);
                     if (small_leaf(b))
                         for (int64_t e = L.x_off[b]; e < L.x_off[b + 1]; ++e) direct(L.x[e], 2);
+                    for (int c0 = 0; c0 < cnt; c0 += 512) {
+                        const int tc = std::min(512, cnt - c0);
+                        if (c0 > 0 && !mutual) {   // without two-way segments the chunks share one list
+                            const Work w0 = pt.work.back();
+                            pt.work.push_back(Work{b, 0, t.begin[b] + c0, tc, w0.seg0, w0.seg1});
+                            continue;
+                        }
+                        const int s0 = (int)pt.segs.size();
+                        for (Seg sg : near) {   // every chunk's two-way segments own their slots
+                            if (sg.kind == 3) {
+                                sg.slot = pt.slots;
+                                pt.inc.push_back({sg.box, pt.slots});
+                                pt.slots += pts_of(sg.box);
+                            }
+                            pt.segs.push_back(sg);
+                        }
+                        pt.work.push_back(Work{b, 0, t.begin[b] + c0, tc, s0, (int)pt.segs.size()});
+                    }
                 }
-                if (with_far) {
-                    for (int64_t e = L.w_off[b]; e < L.w_off[b + 1]; ++e)
-                        if (!small_leaf(L.w[e].src)) segs.push_back(Seg{1, L.w[e].src, code(L.w[e])});
-                    segs.push_back(Seg{2, b, kSelf});
-                }
-                int s1 = (int)segs.size();
-                work.push_back(Work{b, 0, t.begin[b] + c0, std::min(512, cnt - c0), s0, s1});
+            } catch (...) {
+                pt.err = std::current_exception();
             }
+        };
+        std::vector<std::thread> pool;
+        for (int i = 1; i < nth; ++i) pool.emplace_back(run, i);
+        run(0);
+        for (auto& x : pool) x.join();
+        for (Part& pt : parts) {
+            if (pt.err) std::rethrow_exception(pt.err);
+            const int sb = (int)segs.size();
+            const int64_t slb = n_slots;
+            for (Seg sg : pt.segs) {
+                if (sg.kind == 3) sg.slot += slb;
+                segs.push_back(sg);
+            }
+            for (Work w : pt.work) {
+                w.seg0 += sb;
+                w.seg1 += sb;
+                work.push_back(w);
+            }
+            for (const auto& pr : pt.inc) incoming[pr.first].push_back(pr.second + slb);
+            n_slots += pt.slots;
         }
         out.nwork = (int)work.size() - out.work0;
     };
-    leaf_pass(P->w_leaf_u, true, false);
+    // W-list M2T (boxes that are not small leaves) and L2T, in float64 after the near field
+    auto far_pass = [&](SegRange& out) {
+        out.set = 1;
+        out.work0 = (int)work.size();
+        for (int b : t.leaves) {
+            const int cnt = t.end[b] - t.begin[b];
+            if (cnt == 0) continue;
+            const int s0 = (int)segs.size();
+            for (int64_t e = L.w_off[b]; e < L.w_off[b + 1]; ++e)
+                if (!small_leaf(L.w[e].src)) segs.push_back(Seg{1, L.w[e].src, code(L.w[e])});
+            segs.push_back(Seg{2, b, kSelf});
+            const int s1 = (int)segs.size();
+            for (int c0 = 0; c0 < cnt; c0 += 512)
+                work.push_back(Work{b, 0, t.begin[b] + c0, std::min(512, cnt - c0), s0, s1});
+        }
+        out.nwork = (int)work.size() - out.work0;
+    };
+    near_pass(P->w_leaf_u);
     {   // longest items first, so the near-field kernel ends balanced
         const int w0 = P->w_leaf_u.work0, nw = (int)work.size() - w0;
         std::vector<int64_t> cost(nw);
@@ -515,7 +574,7 @@ void build_stage_near(pkifmm_plan* P, int R) {
         for (int i = 0; i < nw; ++i) sorted[i] = work[w0 + order[i]];
         std::copy(sorted.begin(), sorted.end(), work.begin() + w0);
     }
-    leaf_pass(P->w_leaf_far, false, true);
+    far_pass(P->w_leaf_far);
     {   // ordered (target, source) pairs of the near field; a two-way segment counts both ways
         int64_t np = 0;
         for (int i = P->w_leaf_u.work0; i < P->w_leaf_u.work0 + P->w_leaf_u.nwork; ++i)
@@ -554,7 +613,7 @@ void build_stage_m2l(pkifmm_plan* P, int R) {
     const HostLists& L = P->lists;
     const int nb = t.nbox();
     const int kn = P->kn;
-    hipStream_t s = P->setup_stream;
+    hipStream_t s = P->setup_stream2;
     Gemm g;
     auto range = [&](auto&& fill) {
         GemmRange r;
@@ -761,36 +820,32 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
         }
         const size_t cols = (size_t)t.nbox() * R;
         const int64_t kk = (int64_t)kn * kn;
-        // 2. S2M and the upward pass first, with the whole chip: matrix-core GEMMs slow down
-        // many times over when they share compute units with the direct sums
+        // Schedule.  Matrix-core GEMMs slow down many times over when they share compute units
+        // with the direct sums, so the GEMM passes are placed where the chip is otherwise idle:
+        // the upward pass and M2L run first (while the host builds the near-field lists), the
+        // near field then starts on a second stream and M2L finishes in its tail, and the
+        // downward pass runs after both.  The X list (a few long, latency-bound work items) runs
+        // on a third stream into its own buffer.
+        // 2. S2M and the upward pass; X list beside them
         mark();
         launch_fill_zero(P->q_u.p, (int64_t)cols * kn, s);     // kernels, not memset nodes (graph-safe)
         launch_fill_zero(P->q_d.p, (int64_t)cols * kn, s);
+        launch_fill_zero(P->q_x.p, (int64_t)cols * kn, s);
         run_p2p(P, P->w_s2m, nullptr, P->q_u.p, R, false, false, s, true);
+        hipStream_t sx = P->x_stream, sn = P->near_stream;
+        PK_HIP(hipEventRecord(P->ev_fork, s));
+        PK_HIP(hipStreamWaitEvent(sx, P->ev_fork, 0));
+        run_p2p(P, P->w_x, nullptr, P->q_x.p, R, false, false, sx, true);
+        PK_HIP(hipEventRecord(P->ev_xjoin, sx));
         for (int lv = t.depth; lv >= 0; --lv) {
             run_gemm(P, P->g_m2m[lv], P->m2m.p, 0, kn, 8 * kn, P->phi_u.p, kn, P->q_u.p, kn, true, s, 8);
             run_gemm(P, P->g_up1[lv], P->up_Ut.p, 0, P->r_up, kn, P->q_u.p, kn, P->tmp.p, kn, false, s);
             run_gemm(P, P->g_up2[lv], P->up_VS.p, 0, kn, P->r_up, P->tmp.p, kn, P->phi_u.p, kn, false, s);
         }
         mark();
-        if (build) build_stage_near(P, R);
-        // 3. near field (U lists and the direct W/X entries) on a second stream; it depends only
-        // on the permuted densities and is the longest part of the pass
-        hipStream_t sn = P->near_stream;
-        PK_HIP(hipEventRecord(P->ev_fork, s));
-        PK_HIP(hipStreamWaitEvent(sn, P->ev_fork, 0));
-        mark_on(sn);
-        run_p2p(P, P->w_leaf_u, P->pot.p, nullptr, R, mixed, false, sn, false, P->near_grid_cap);
-        if (P->mutual)
-            launch_mutual_gather(P->mpart.p, P->n_slots, k, P->in_box.p, P->in_off.p, P->in_slot.p, P->n_in,
-                                 P->b_begin.p, P->b_end.p, n, P->pot.p, sn);
-        mark_on(sn);
-        PK_HIP(hipEventRecord(P->ev_join, sn));
-        if (build) build_stage_m2l(P, R);
-        // 4-5. in the shadow of the near field: root far field, X list (points to downward check
-        // surfaces) and V-list M2L
+        // 3. root far field and V-list M2L into the downward check potentials
+        if (build) build_stage_m2l(P, R);       // host work while the upward pass runs
         run_gemm(P, P->g_root, P->mroot.p, 0, kn, kn, P->phi_u.p, kn, P->q_d.p, kn, true, s);
-        run_p2p(P, P->w_x, nullptr, P->q_d.p, R, false, false, s, true);
         for (int q = 0; q < kM2LGroups; ++q) {
             if (P->g_m2l[q].ntile == 0) continue;
             run_gemm(P, P->g_m2l[q], P->m2l.p, kk, kn, kn, P->phi_u.p, kn, P->m2l_tmp.p, kn, false, s, 1, false);
@@ -799,17 +854,31 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
                                   P->q_d.p, s);
         }
         mark();
-        // 6. the downward pass
+        // 4. near field (U lists and the direct W/X entries) on the second stream; it needs only
+        // the permuted densities
+        if (build) build_stage_near(P, R);      // host work while M2L runs
+        PK_HIP(hipStreamWaitEvent(sn, P->ev_fork, 0));
+        mark_on(sn);
+        run_p2p(P, P->w_leaf_u, P->pot.p, nullptr, R, mixed, false, sn, false, P->near_grid_cap);
+        if (P->mutual)
+            launch_mutual_gather(P->mpart.p, P->n_slots, k, P->in_box.p, P->in_off.p, P->in_slot.p, P->n_in,
+                                 P->b_begin.p, P->b_end.p, n, P->pot.p, sn);
+        mark_on(sn);
+        PK_HIP(hipEventRecord(P->ev_join, sn));
+        // 5. after the near field and the X list: X-list check potentials join, then the
+        // downward pass with the whole chip
+        PK_HIP(hipStreamWaitEvent(s, P->ev_join, 0));
+        PK_HIP(hipStreamWaitEvent(s, P->ev_xjoin, 0));
+        launch_add_into(P->q_d.p, P->q_x.p, (int64_t)cols * kn, s);
         for (int lv = 0; lv <= t.depth; ++lv) {
             if (lv >= 1) run_gemm(P, P->g_l2l[lv], P->l2l.p, kk, kn, kn, P->phi_d.p, kn, P->q_d.p, kn, true, s);
             run_gemm(P, P->g_dn1[lv], P->dn_Ut.p, 0, P->r_dn, kn, P->q_d.p, kn, P->tmp.p, kn, false, s);
             run_gemm(P, P->g_dn2[lv], P->dn_VS.p, 0, kn, P->r_dn, P->tmp.p, kn, P->phi_d.p, kn, false, s);
         }
         mark();
-        // 7b. W list and L2T (float64: they consume equivalent densities), after the near field
-        PK_HIP(hipStreamWaitEvent(s, P->ev_join, 0));
+        // 6. W list and L2T (float64: they consume equivalent densities)
         run_p2p(P, P->w_leaf_far, P->pot.p, nullptr, R, false, true, s);
-        // 8. output
+        // 7. output
         const double c = (P->cfg.kernel == PKIFMM_LAPLACE ? 1.0 / (4.0 * M_PI) : 1.0 / (8.0 * M_PI)) / P->cfg.box_length;
         launch_unpermute(P->pot.p, P->perm.p, n, R, k, c, potential, s);
         mark();
@@ -849,12 +918,17 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
         P->n_surf = (int)u.size() / 3;
         P->kn = P->k * P->n_surf;
         const int kn = P->kn, ns = P->n_surf;
-        PK_HIP(hipStreamCreate(&P->setup_stream));
+        // non-blocking: the uploads of one stage must not wait for the kernels of the previous
+        // stage on the caller's stream (a legacy default stream would otherwise order them)
+        PK_HIP(hipStreamCreateWithFlags(&P->setup_stream, hipStreamNonBlocking));
+        PK_HIP(hipStreamCreateWithFlags(&P->setup_stream2, hipStreamNonBlocking));
         // non-blocking: no implicit synchronisation with the legacy null stream; default priority
         PK_HIP(hipStreamCreateWithFlags(&P->near_stream, hipStreamNonBlocking));
+        PK_HIP(hipStreamCreateWithFlags(&P->x_stream, hipStreamNonBlocking));
         PK_HIP(hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking));
         PK_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
         PK_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+        PK_HIP(hipEventCreateWithFlags(&P->ev_xjoin, hipEventDisableTiming));
         hipStream_t s = P->setup_stream;
         {
             int dev = 0;
@@ -916,10 +990,13 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
     } catch (const Error& e) {
         if (h) rocblas_destroy_handle(h);
         if (P->setup_stream) (void)hipStreamDestroy(P->setup_stream);
+        if (P->setup_stream2) (void)hipStreamDestroy(P->setup_stream2);
         if (P->near_stream) (void)hipStreamDestroy(P->near_stream);
+        if (P->x_stream) (void)hipStreamDestroy(P->x_stream);
         if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
         if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
         if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+        if (P->ev_xjoin) (void)hipEventDestroy(P->ev_xjoin);
         return e.code;
     } catch (const std::bad_alloc&) {
         if (h) rocblas_destroy_handle(h);
@@ -1093,9 +1170,9 @@ int pkifmm_get_stats(pkifmm_plan* P, pkifmm_stats* out) {
         for (auto& ev : P->pending_events) {
             if (ev.size() == PKIFMM_NUM_PHASES + 2) {
                 if (hipEventSynchronize(ev.back()) != hipSuccess) bad = hipErrorUnknown;
-                // ev[0]: start; ev[1]: end of the upward pass; ev[2], ev[3]: near field on its own
-                // stream; ev[4..6]: ends of the M2L, down and leaf phases
-                const int a[PKIFMM_NUM_PHASES] = {2, 0, 1, 4, 5}, b[PKIFMM_NUM_PHASES] = {3, 1, 4, 5, 6};
+                // ev[0]: start; ev[1], ev[2]: ends of the up and M2L phases; ev[3], ev[4]: near field
+                // on its own stream; ev[5], ev[6]: ends of the down and leaf phases
+                const int a[PKIFMM_NUM_PHASES] = {3, 0, 1, 2, 5}, b[PKIFMM_NUM_PHASES] = {4, 1, 2, 5, 6};
                 for (int i = 0; i < PKIFMM_NUM_PHASES && bad == hipSuccess; ++i) {
                     float ms = 0.f;
                     if (hipEventElapsedTime(&ms, ev[a[i]], ev[b[i]]) != hipSuccess) bad = hipErrorUnknown;
@@ -1165,10 +1242,13 @@ int pkifmm_plan_destroy(pkifmm_plan* P) {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     drop_graph(P);
     if (P->setup_stream) (void)hipStreamDestroy(P->setup_stream);
+    if (P->setup_stream2) (void)hipStreamDestroy(P->setup_stream2);
     if (P->near_stream) (void)hipStreamDestroy(P->near_stream);
+    if (P->x_stream) (void)hipStreamDestroy(P->x_stream);
     if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
     if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
     if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+    if (P->ev_xjoin) (void)hipEventDestroy(P->ev_xjoin);
     delete P;
     return PKIFMM_OK;
 }
