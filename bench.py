@@ -125,13 +125,16 @@ def main():
     log(f"mixed: {rmx['s_total'] / args.steps * 1e3:.2f} ms/step")
     ms_step = rmx["s_total"] / args.steps * 1e3
     st = rmx["stats"]
-    # dominant kernel: the float32 U-list direct sums (phase "near"), timed with HIP events
+    # dominant kernel: the float32 near-field direct sums (phase "near": k_p2p plus the gather of
+    # the reverse-direction sums), timed with HIP events on the stream they run on
     t_near = st["ms_phase"]["near"] * 1e-3
     achieved = FLOPS_PER_STOKES_PAIR * st["near_pairs"] / t_near / 1e12
-    roofline = {"bound": "alu", "kernel": "k_p2p<3,true> (near field: U lists + direct W/X, float32)",
+    roofline = {"bound": "alu",
+                "kernel": "k_p2p<3,true,1> + k_mutual_gather (near field: U lists + direct W/X, float32)",
                 "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
-                "algorithmic": f"{FLOPS_PER_STOKES_PAIR} flop/pair x {st['near_pairs']} pairs per launch",
+                "algorithmic": f"{FLOPS_PER_STOKES_PAIR} flop/pair x {st['near_pairs']} ordered (target, source) "
+                               f"pairs per launch (a pair of different leaves is evaluated once, both ways)",
                 "ms_per_launch": t_near * 1e3}
     rel_mx_vs_64 = float(np.linalg.norm(outmx - out64) / np.linalg.norm(out64))
     rec = {
