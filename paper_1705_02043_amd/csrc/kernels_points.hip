@@ -125,6 +125,37 @@ __global__ void k_fill_zero(double* __restrict__ x, int64_t n) {
         x[i] = 0.0;
 }
 
+// Children of split boxes: for split box i (level child_level - 1, sorted-key range
+// [begin, end), integer coordinates ix, iy, iz) and octant o, the key range of the child cell,
+// found by two binary searches over the box's keys.  box: [n_split][5] = begin, end, ix, iy, iz;
+// out: [n_split][8][2] = first, end (empty when equal).
+__global__ void k_tree_children(const uint64_t* __restrict__ keys, const int* __restrict__ box, int n_split,
+                                int child_level, int* __restrict__ out) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= 8 * n_split) return;
+    const int i = g >> 3, o = g & 7;
+    const int* bx = box + 5 * i;
+    const uint32_t cx = 2 * bx[2] + ((o >> 2) & 1), cy = 2 * bx[3] + ((o >> 1) & 1), cz = 2 * bx[4] + (o & 1);
+    const int sh = 3 * (21 - child_level);
+    const uint64_t prefix = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
+    const uint64_t klo = prefix << sh, khi = ((prefix + 1) << sh) - 1;
+    int lo = bx[0], hi = bx[1];
+    while (lo < hi) {          // first key >= klo
+        const int mid = lo + ((hi - lo) >> 1);
+        if (keys[mid] < klo) lo = mid + 1;
+        else hi = mid;
+    }
+    const int a = lo;
+    hi = bx[1];
+    while (lo < hi) {          // first key > khi
+        const int mid = lo + ((hi - lo) >> 1);
+        if (keys[mid] <= khi) lo = mid + 1;
+        else hi = mid;
+    }
+    out[2 * g] = a;
+    out[2 * g + 1] = lo;
+}
+
 __global__ void k_add_into(double* __restrict__ y, const double* __restrict__ x, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         y[i] += x[i];
@@ -137,6 +168,14 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 void launch_fill_zero(double* x, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<int64_t>(nblk(n, 256), 4096)), dim3(256), 0, s, x, n);
+    PK_HIP(hipGetLastError());
+}
+
+void launch_tree_children(const uint64_t* keys, const int* box, int n_split, int child_level, int* out,
+                          hipStream_t s) {
+    if (n_split == 0) return;
+    hipLaunchKernelGGL(k_tree_children, dim3(nblk(8 * (int64_t)n_split, 256)), dim3(256), 0, s, keys, box, n_split,
+                       child_level, out);
     PK_HIP(hipGetLastError());
 }
 

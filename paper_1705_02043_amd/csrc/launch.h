@@ -30,6 +30,10 @@ void launch_unpermute(const double* pot, const uint32_t* perm, int64_t n, int R,
                       double* out, hipStream_t s);
 // x[0..n) = 0 with a kernel (no memset node under graph capture)
 void launch_fill_zero(double* x, int64_t n, hipStream_t s);
+// children key ranges of split boxes (box: [n_split][5] = begin, end, ix, iy, iz at level
+// child_level - 1; out: [n_split][8][2] = first, end); keys sorted, device
+void launch_tree_children(const uint64_t* keys, const int* box, int n_split, int child_level, int* out,
+                          hipStream_t s);
 // y[0..n) += x[0..n)
 void launch_add_into(double* y, const double* x, int64_t n, hipStream_t s);
 // per-problem, per-RHS, per-component sums of the sorted densities (neutrality check):

@@ -130,6 +130,8 @@ struct pkifmm_plan {
     DBuf<int> err_flag;
     DBuf<int> b_level, b_ix, b_iy, b_iz, b_begin, b_end, leaf_boxes;
     PinnedBuf<uint64_t> keys_host;
+    DBuf<int> tree_box, tree_out;       // per-level split boxes and their children (device tree build)
+    PinnedBuf<int> tree_out_host;
     DBuf<int64_t> v_off;
     DBuf<int> v_targets;
     int n_v_targets = 0;
@@ -260,6 +262,66 @@ void add_gemm(Gemm& g, int op, int M, const std::vector<int>& in, const std::vec
 }
 
 double box_edge(const HostTree& t, int b) { return std::ldexp(1.0, -t.level[b]); }
+
+// Octree of one problem from its device-sorted keys, level by level on the device: the host
+// keeps the box table and decides which boxes split (more than s points); the children's key
+// ranges come from two binary searches per (split box, octant) on the device.  Boxes are
+// numbered exactly as a sequential pass over each level's boxes and octants would number them.
+void build_tree_device(pkifmm_plan* P, const uint64_t* keys, int64_t n, int s_max, HostTree& t, hipStream_t s) {
+    t = HostTree();
+    auto add = [&](int lv, int x, int y, int z, int b0, int b1, int par) {
+        t.level.push_back(lv); t.ix.push_back(x); t.iy.push_back(y); t.iz.push_back(z);
+        t.begin.push_back(b0); t.end.push_back(b1); t.parent.push_back(par);
+        for (int o = 0; o < 8; ++o) t.child.push_back(-1);
+        return (int)t.level.size() - 1;
+    };
+    add(0, 0, 0, 0, 0, (int)n, -1);
+    t.level_start.push_back(0);
+    int lv = 0;
+    std::vector<int> frontier{0}, split, box;
+    while (!frontier.empty() && lv < kMaxLevel) {
+        split.clear();
+        box.clear();
+        for (int b : frontier)
+            if (t.end[b] - t.begin[b] > s_max) {
+                split.push_back(b);
+                box.insert(box.end(), {t.begin[b], t.end[b], t.ix[b], t.iy[b], t.iz[b]});
+            }
+        if (split.empty()) break;
+        const int ns = (int)split.size();
+        P->tree_box.upload(box, s);
+        P->tree_out.ensure((size_t)16 * ns);
+        P->tree_out_host.ensure((size_t)16 * ns);
+        launch_tree_children(keys, P->tree_box.p, ns, lv + 1, P->tree_out.p, s);
+        PK_HIP(hipMemcpyAsync(P->tree_out_host.p, P->tree_out.p, sizeof(int) * 16 * ns, hipMemcpyDeviceToHost, s));
+        PK_HIP(hipStreamSynchronize(s));
+        const int* r = P->tree_out_host.p;
+        std::vector<int> next;
+        for (int i = 0; i < ns; ++i) {
+            const int b = split[i];
+            for (int o = 0; o < 8; ++o) {
+                const int a = r[16 * i + 2 * o], e = r[16 * i + 2 * o + 1];
+                if (e <= a) continue;
+                const int c = add(lv + 1, 2 * t.ix[b] + ((o >> 2) & 1), 2 * t.iy[b] + ((o >> 1) & 1),
+                                  2 * t.iz[b] + (o & 1), a, e, b);
+                t.child[8 * b + o] = c;
+                next.push_back(c);
+            }
+        }
+        if (next.empty()) break;
+        ++lv;
+        t.level_start.push_back(next.front());
+        frontier.swap(next);
+    }
+    t.depth = lv;
+    t.level_start.push_back(t.nbox());
+    t.leaf_id.assign(t.nbox(), -1);
+    for (int b = 0; b < t.nbox(); ++b)
+        if (t.is_leaf(b)) {
+            t.leaf_id[b] = (int)t.leaves.size();
+            t.leaves.push_back(b);
+        }
+}
 
 // Work lists of one (tree, R) are built in three stages, each uploaded on the setup stream
 // into its own buffers, so that an evaluation can launch the kernels of a stage while the
@@ -1048,13 +1110,16 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
         radix_sort_pairs(P->keys_a.p, P->keys_b.p, P->vals_a.p, P->perm.p, n, P->sort_temp, s, n_problems,
                          P->prob_off.p);
         launch_gather_points(P->u_wrapped.p, P->perm.p, n, P->xs.p, s);
-        P->keys_host.ensure(m);
-        const uint64_t* keys = P->keys_host.p;
-        if (n) PK_HIP(hipMemcpyAsync(P->keys_host.p, P->keys_b.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
+        const uint64_t* keys = nullptr;
+        if (n_problems > 1) {   // the forest is built on the host, one problem per thread
+            P->keys_host.ensure(m);
+            keys = P->keys_host.p;
+            if (n) PK_HIP(hipMemcpyAsync(P->keys_host.p, P->keys_b.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
+        }
         PK_HIP(hipStreamSynchronize(s));
         if (err) throw Error(PKIFMM_ERR_OUT_OF_BOX, "coordinate outside the box on a non-periodic axis, or not finite");
         if (n_problems == 1) {
-            build_tree_host(keys, n, P->cfg.max_pts_per_leaf, P->tree);
+            build_tree_device(P, P->keys_b.p, n, P->cfg.max_pts_per_leaf, P->tree, s);
             build_lists_host(P->tree, P->cfg.periodic_mask, P->lists);
             P->box_prob.assign(P->tree.nbox(), 0);
         } else {

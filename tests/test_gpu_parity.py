@@ -118,6 +118,24 @@ def test_multiple_rhs_and_linearity():
         assert _rel(out[r], f.evaluate(pb.density[r])) < 1e-10
 
 
+@pytest.mark.parametrize("name", ["stokes_free_graded", "laplace_sp_n2000", "stokes_dp_slab_n20000"])
+def test_pairs_once_matches_one_way_near_field(name):
+    """One right-hand side evaluates each pair of different leaves once, both ways; two
+    right-hand sides take the one-way near field with the right-hand sides blocked.  In float64
+    the two agree to rounding, and the pair count reported is the same."""
+    pk = _pk()
+    pb = CASES[name][0]()
+    plan = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=0)
+    plan.set_points(_dev(pb.points))
+    one = plan.evaluate(_dev(pb.density[:1])).cpu().numpy()
+    pairs_one = plan.stats()["near_pairs"]
+    two = plan.evaluate(_dev(np.concatenate([pb.density[:1], pb.density[:1]]))).cpu().numpy()
+    pairs_two = plan.stats()["near_pairs"]
+    assert pairs_one == pairs_two
+    for r in range(2):
+        assert _rel(two[r], one[0]) < 1e-13
+
+
 def test_root_leaf_and_tiny_inputs():
     pk = _pk()
     pts, q = W.madelung_chain(0)
