@@ -6,7 +6,7 @@ What is computed (Section 2, the problem statement and the near/far split):
              (the tree covers exactly those), so K^{P,F} sums |p|_inf >= 2.
 
 Conventions that the paper leaves to the cited Ewald literature:
-  * singly periodic (SP) Laplace: the image sum diverges like log n for one
+  * singly periodic (SP) Laplace and Stokes: the image sum diverges like log n for one
     pair, so each image term is regularised by its monopole value,
     K(r - k e) - K(k e); for a neutral system the subtracted terms cancel.
     The paper's own route for this geometry is a direct image sum that
@@ -73,6 +73,49 @@ def sp_laplace_sum(r: np.ndarray, axis: int, kmin: int = 0, n: int = 64, mterms:
         out += 2.0 * eval_legendre(2 * m, cos_t) * rn ** (2 * m) * zeta(2 * m + 1, n + 1)
     return out / FOUR_PI
 
+
+
+def sp_stokes_sum(r: np.ndarray, axis: int, kmin: int = 0, n: int = 64, mterms: int = 10) -> np.ndarray:
+    """Regularised singly periodic Stokeslet sum over images |k| >= kmin: [M, 3, 3].
+
+    Returns (1/8pi) * ( [kmin == 0] S(r) + sum_{|k|>=max(kmin,1)} (S(r - k e) - S(k e)) ) with
+    S(x) = I/|x| + x x^T/|x|^3 (S(0) = 0): the limit of symmetric image sums, each image term
+    regularised by its value at the lattice point; for a net-force-free set of sources the
+    subtracted terms cancel.  Images with |k| <= n are summed directly.  Beyond, with
+    x = k e -+ r, 1/|x| = sum_l P_l(u) rho^l / k^(l+1) and 1/|x|^3 = sum_l C_l(u) rho^l / k^(l+3)
+    (Legendre P, Gegenbauer C of index 3/2; rho = |r|, u = r.e/rho), so that
+        S(ke - r) + S(ke + r) - 2 S(ke) = sum_{m even >= 2} 2 k^-(m+1) Q_m(r),
+        Q_m = I P_m rho^m + e e^T C_m rho^m - (e r^T + r e^T) C_{m-1} rho^(m-1) + r r^T C_{m-2} rho^(m-2),
+    and the tail is sum_m 2 Q_m(r) zeta(m+1, n+1).  Requires |r| < n + 1."""
+    r = np.asarray(r, dtype=np.float64).reshape(-1, 3)
+    M = r.shape[0]
+    e = np.zeros(3); e[axis] = 1.0
+    out = np.zeros((M, 3, 3))
+    if kmin == 0:
+        out += kernel_value(STOKES, r) * EIGHT_PI
+    for k in range(max(kmin, 1), n + 1):
+        ke = k * e
+        g0 = kernel_value(STOKES, ke[None, :])[0] * EIGHT_PI
+        for sgn in (1.0, -1.0):
+            out += kernel_value(STOKES, r - sgn * ke) * EIGHT_PI - g0
+    rho = np.sqrt(np.sum(r * r, axis=1))
+    assert np.all(rho < n + 1)
+    u = np.where(rho > 0, (r @ e) / np.where(rho > 0, rho, 1.0), 0.0)
+    L = 2 * mterms + 1
+    P = [np.ones(M), u.copy()]
+    C = [np.ones(M), 3.0 * u]
+    for l in range(1, L):
+        P.append(((2 * l + 1) * u * P[l] - l * P[l - 1]) / (l + 1))
+        C.append((2.0 * u * (l + 1.5) * C[l] - (l + 2) * C[l - 1]) / (l + 1))
+    ee = np.outer(e, e)
+    er = e[None, :, None] * r[:, None, :] + r[:, :, None] * e[None, None, :]
+    rr = r[:, :, None] * r[:, None, :]
+    for mm in range(1, mterms + 1):
+        m = 2 * mm
+        q = (P[m] * rho ** m)[:, None, None] * np.eye(3) + (C[m] * rho ** m)[:, None, None] * ee \
+            - (C[m - 1] * rho ** (m - 1))[:, None, None] * er + (C[m - 2] * rho ** (m - 2))[:, None, None] * rr
+        out += 2.0 * q * zeta(m + 1, n + 1)
+    return out / EIGHT_PI
 
 # ---------------------------------------------------------------- triply periodic Stokes
 
@@ -371,14 +414,8 @@ def periodic_axes(mask: int):
 
 
 def supported(kernel: int, mask: int) -> bool:
-    n = len(periodic_axes(mask))
-    if n == 0:
-        return True
-    if n == 1 and kernel == LAPLACE:
-        return True
-    if n >= 2:
-        return True
-    return False
+    """Every kernel with free space or one, two or three periodic axes has a far-field sum."""
+    return kernel in (LAPLACE, STOKES) and 0 <= mask <= 7
 
 
 def far_kernel_matrix(kernel: int, mask: int, X: np.ndarray, Y: np.ndarray, near_layers: int = 1) -> np.ndarray:
@@ -393,6 +430,9 @@ def far_kernel_matrix(kernel: int, mask: int, X: np.ndarray, Y: np.ndarray, near
         return np.zeros((k * m, k * n))
     if kernel == LAPLACE and len(axes) == 1:
         return sp_laplace_sum(r, axes[0], kmin=near_layers + 1).reshape(m, n)
+    if kernel == STOKES and len(axes) == 1:
+        G = sp_stokes_sum(r, axes[0], kmin=near_layers + 1).reshape(m, n, 3, 3)
+        return G.transpose(0, 2, 1, 3).reshape(3 * m, 3 * n)
     if kernel == LAPLACE and len(axes) == 3:
         return tp_laplace_sum(r, far_only=True, near_layers=near_layers).reshape(m, n)
     if kernel == STOKES and len(axes) == 3:
@@ -420,6 +460,8 @@ def exact_potential(kernel: int, mask: int, targets: np.ndarray, sources: np.nda
         K = kernel_value(kernel, r)
     elif kernel == LAPLACE and len(axes) == 1:
         K = sp_laplace_sum(r, axes[0], kmin=0, n=max(64, int(np.max(np.abs(r))) + 2))
+    elif kernel == STOKES and len(axes) == 1:
+        K = sp_stokes_sum(r, axes[0], kmin=0, n=max(64, int(np.max(np.abs(r))) + 2))
     elif kernel == LAPLACE and len(axes) == 3:
         K = tp_laplace_sum(r)
     elif kernel == STOKES and len(axes) == 3:

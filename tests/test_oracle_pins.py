@@ -182,6 +182,38 @@ def test_sp_periodicity_and_neutral_shift_invariance():
     assert np.max(np.abs(a - b)) < 1e-13
 
 
+
+def test_sp_stokes_tail_closed_form_and_relations():
+    """SP Stokeslet sum: the closed-form tail (Legendre and index-3/2 Gegenbauer expansions)
+    against a long direct image sum; the trace is four times the raw Laplace sum
+    (tr(I/|x| + x x^T/|x|^3) = 4/|x|); periodic along the axis; far = full - near."""
+    rng = np.random.default_rng(41)
+    r = rng.uniform(-1.0, 1.0, (8, 3))
+    r[0] = 0.0
+    for axis in (0, 2):
+        a = periodic.sp_stokes_sum(r, axis, n=64)
+        b = periodic.sp_stokes_sum(r, axis, n=3000, mterms=3)
+        assert np.max(np.abs(a - b)) < 1e-14
+        lap = periodic.sp_laplace_sum(r, axis)
+        assert np.max(np.abs(np.trace(a, axis1=1, axis2=2) - 2.0 * lap)) < 1e-14   # (4/8pi) = 2 (1/4pi)
+        e = np.zeros(3); e[axis] = 1.0
+        c = periodic.sp_stokes_sum(r + 2.0 * e, axis)
+        assert np.max(np.abs(c[1:] - a[1:])) < 1e-14
+        # the tree sums the images |k| <= 1 unregularised: full = near + far - 2 S(e)
+        near = sum(K.kernel_value(K.STOKES, r[1:] - k * e) for k in (-1, 0, 1))
+        far = periodic.sp_stokes_sum(r[1:], axis, kmin=2)
+        two_s_e = 2.0 * K.kernel_value(K.STOKES, e[None, :])[0]
+        assert np.max(np.abs(a[1:] - (near + far - two_s_e))) < 1e-14
+
+
+@pytest.mark.parametrize("p,tol", [(6, 5e-4), (8, 5e-5)])
+def test_kifmm_sp_stokes_against_lattice_sum(p, tol):
+    """Singly periodic Stokes (axis x): the periodic KIFMM against the regularised image sum."""
+    pb = W.stokes_tp_uniform(n=300, seed=42, p=p, s=25, mask=1)
+    ex = periodic.exact_potential(K.STOKES, 1, pb.points, pb.points, pb.density[0])
+    q = kifmm.KIFMM(K.STOKES, 1, p, 25, pb.points).evaluate(pb.density[0])
+    assert np.linalg.norm(q - ex) / np.linalg.norm(ex) < tol
+
 # ------------------------------------------------------------------ triply periodic Ewald sums
 
 def test_tp_stokes_xi_independence():
