@@ -51,8 +51,8 @@ typedef struct pkifmm_plan pkifmm_plan;
 #define PKIFMM_LAPLACE 1
 #define PKIFMM_STOKES 2
 
-/* periodic axes (bit mask): 0 = free space, one axis = singly periodic (Laplace only),
- * two axes = doubly periodic, X|Y|Z = triply periodic */
+/* periodic axes (bit mask): 0 = free space, one axis = singly periodic, two axes = doubly
+ * periodic, X|Y|Z = triply periodic (every combination, both kernels) */
 #define PKIFMM_PERIODIC_X 1u
 #define PKIFMM_PERIODIC_Y 2u
 #define PKIFMM_PERIODIC_Z 4u
@@ -69,7 +69,7 @@ typedef struct pkifmm_plan pkifmm_plan;
 #define PKIFMM_ERR_INVALID_ARG -1
 #define PKIFMM_ERR_OUT_OF_BOX -2     /* a coordinate on a non-periodic axis outside [0, L], or not finite */
 #define PKIFMM_ERR_INCOMPATIBLE -3   /* SP or DP input with a non-zero net density */
-#define PKIFMM_ERR_UNSUPPORTED -4    /* kernel x periodicity without a far-field operator */
+#define PKIFMM_ERR_UNSUPPORTED -4    /* kernel x periodicity without a far-field operator (none at present) */
 #define PKIFMM_ERR_OOM -5
 #define PKIFMM_ERR_HIP -6
 #define PKIFMM_ERR_NO_POINTS -7      /* evaluate before set_points */
@@ -77,7 +77,7 @@ typedef struct pkifmm_plan pkifmm_plan;
 
 typedef struct {
     int kernel;                  /* PKIFMM_LAPLACE or PKIFMM_STOKES */
-    unsigned periodic_mask;      /* 0, one axis (Laplace), two axes, or X|Y|Z */
+    unsigned periodic_mask;      /* 0, one axis, two axes, or X|Y|Z */
     int p;                       /* surface points per cube edge, 4..16 */
     int max_pts_per_leaf;        /* s: a box holding more points is split */
     int precision;               /* PKIFMM_FP64 or PKIFMM_MIXED */

@@ -7,10 +7,10 @@
 //
 // Periodic far-field kernels (the paper leaves the periodic sums to the
 // Ewald literature; the conventions used here):
-//   * singly periodic Laplace along axis e: each image term is regularised by
-//     its monopole value, sum_{|k|>=2} 1/|r - k e| - 1/|k|; images up to
+//   * singly periodic Laplace and Stokes along axis e: each image term is regularised by
+//     its value at the lattice point, sum_{|k|>=2} K(r - k e) - K(k e); images up to
 //     |k| = kNear are summed directly and the rest in closed form from the
-//     Legendre expansion, 2 sum_m P_2m(cos t) |r|^2m zeta(2m+1, kNear+1);
+//     Legendre (and for Stokes also Gegenbauer) expansions with Hurwitz zeta sums;
 //   * triply periodic Stokes: Hasimoto's split with the k = 0 mode removed;
 //     real-space part S^R over the far images, Fourier part over k != 0, and
 //     the near images |p|_inf <= 1 removed analytically by subtracting the
@@ -86,6 +86,59 @@ __global__ void k_far_sp_laplace(int axis, const double* __restrict__ X, int m, 
         }
     }
     out[i + (int64_t)j * ld] = acc + tail;
+}
+
+// ---- singly periodic Stokes, same regularisation; tail from the Legendre (1/|x|) and index-3/2
+// Gegenbauer (1/|x|^3) expansions: for x = k e -+ r,
+//   S(ke - r) + S(ke + r) - 2 S(ke) = sum_{m even >= 2} 2 k^-(m+1) Q_m(r),
+//   Q_m = I P_m rho^m + e e^T C_m rho^m - (e r^T + r e^T) C_{m-1} rho^(m-1) + r r^T C_{m-2} rho^(m-2)
+// (rho = |r|, u = r.e/rho), summed against zeta(m+1, kNear+1).
+__global__ void k_far_sp_stokes(int axis, const double* __restrict__ X, int m, const double* __restrict__ Y, int n,
+                                double* __restrict__ out, int64_t ld, const double* __restrict__ zeta) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    if (i >= m) return;
+    const double r[3] = {X[3 * i] - Y[3 * j], X[3 * i + 1] - Y[3 * j + 1], X[3 * i + 2] - Y[3 * j + 2]};
+    double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int k = kNear; k >= 2; --k) {   // small terms first
+        for (int sg = -1; sg <= 1; sg += 2) {
+            double d[3] = {r[0], r[1], r[2]};
+            d[axis] -= sg * k;
+            const double ri = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const double ri3 = ri * ri * ri;
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q) {
+                    // S(d) - S(k e): S(k e) = (I + e e^T) / k
+                    const double s0 = ((p == q ? 1.0 : 0.0) + (p == axis && q == axis ? 1.0 : 0.0)) / k;
+                    A[p][q] += ((p == q ? ri : 0.0) + d[p] * d[q] * ri3) - s0;
+                }
+        }
+    }
+    const double rho2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double rho = sqrt(rho2);
+    const double u = rho > 0.0 ? r[axis] / rho : 0.0;
+    // P_l and C_l (index 3/2) by their three-term recurrences, with the powers of rho folded in:
+    // pl[l] = P_l(u) rho^l, cl[l] = C_l(u) rho^l
+    double pl[2 * kLegendre + 1], cl[2 * kLegendre + 1];
+    pl[0] = 1.0; pl[1] = u * rho;
+    cl[0] = 1.0; cl[1] = 3.0 * u * rho;
+    for (int l = 1; l < 2 * kLegendre; ++l) {
+        pl[l + 1] = ((2 * l + 1) * u * rho * pl[l] - l * rho2 * pl[l - 1]) / (l + 1);
+        cl[l + 1] = (2.0 * u * rho * (l + 1.5) * cl[l] - (l + 2) * rho2 * cl[l - 1]) / (l + 1);
+    }
+    for (int mm = 1; mm <= kLegendre; ++mm) {
+        const int mo = 2 * mm;
+        const double z = 2.0 * zeta[mm - 1];
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) {
+                const double e_p = p == axis ? 1.0 : 0.0, e_q = q == axis ? 1.0 : 0.0;
+                double qv = (p == q ? pl[mo] : 0.0) + e_p * e_q * cl[mo] - (e_p * r[q] + r[p] * e_q) * cl[mo - 1] +
+                            r[p] * r[q] * cl[mo - 2];
+                A[p][q] += z * qv;
+            }
+    }
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) out[(3 * i + p) + (int64_t)(3 * j + q) * ld] = A[p][q];
 }
 
 // ---- triply periodic Stokes (Hasimoto)
@@ -388,13 +441,16 @@ void launch_far_kmat(int kernel, unsigned mask, const double* X, int m, const do
                      int64_t ld, const double*, hipStream_t s) {
     int naxes = __builtin_popcount(mask & 7u);
     dim3 grid((m + 127) / 128, n);
-    if (naxes == 1 && kernel == PKIFMM_LAPLACE) {
+    if (naxes == 1) {
         int axis = mask & 1u ? 0 : (mask & 2u ? 1 : 2);
         std::vector<double> z(kLegendre);
         for (int mm = 1; mm <= kLegendre; ++mm) z[mm - 1] = hurwitz_zeta(2.0 * mm + 1.0, kNear + 1.0);
         DBuf<double> dz;
         dz.upload(z, s);
-        hipLaunchKernelGGL(k_far_sp_laplace, grid, dim3(128), 0, s, axis, X, m, Y, n, out, ld, dz.p);
+        if (kernel == PKIFMM_LAPLACE)
+            hipLaunchKernelGGL(k_far_sp_laplace, grid, dim3(128), 0, s, axis, X, m, Y, n, out, ld, dz.p);
+        else
+            hipLaunchKernelGGL(k_far_sp_stokes, grid, dim3(128), 0, s, axis, X, m, Y, n, out, ld, dz.p);
         PK_HIP(hipGetLastError());
         PK_HIP(hipStreamSynchronize(s));
         return;

@@ -184,8 +184,6 @@ void check_config(const pkifmm_config& c) {
     if (c.precision != PKIFMM_FP64 && c.precision != PKIFMM_MIXED) throw Error(PKIFMM_ERR_INVALID_ARG, "precision");
     if (!(c.box_length > 0.0) || !std::isfinite(c.box_length)) throw Error(PKIFMM_ERR_INVALID_ARG, "box_length");
     if (c.svd_rel_threshold < 0.0 || c.svd_rel_threshold >= 1.0) throw Error(PKIFMM_ERR_INVALID_ARG, "svd_rel_threshold");
-    int naxes = __builtin_popcount(c.periodic_mask);
-    if (naxes == 1 && c.kernel == PKIFMM_STOKES) throw Error(PKIFMM_ERR_UNSUPPORTED, "singly periodic Stokes far field not available");
 }
 
 // SVD of a kn x kn matrix on the device (rocSOLVER, one-sided bidiagonal QR);

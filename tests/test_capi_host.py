@@ -32,8 +32,10 @@ def test_status_strings_and_bad_config():
     h = ctypes.c_void_p()
     assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_INVALID_ARG
     cfg.p = 8
-    cfg.kernel, cfg.periodic_mask = pk.STOKES, 1   # singly periodic Stokes far field is not provided
-    assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_UNSUPPORTED
+    cfg.kernel = 3                 # no such kernel
+    assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_INVALID_ARG
+    cfg.kernel, cfg.periodic_mask = pk.STOKES, 8   # no such axis
+    assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_INVALID_ARG
     assert L.pkifmm_plan_destroy(None) == 0
 
 

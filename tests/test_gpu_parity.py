@@ -50,6 +50,8 @@ CASES = {
     "laplace_tp_n3000": (lambda: W.laplace_sp_uniform(n=3000, seed=23, p=6, s=60, mask=7), 1e-10, 1e-6),
     "stokes_dp_slab_n20000": (lambda: W.stokes_dp_slab(n=20000, seed=28, p=8, s=600), STOKES_P8_FP64_TOL, 1e-6),
     "laplace_dp_yz_n3000": (lambda: W.laplace_sp_uniform(n=3000, seed=29, p=6, s=60, mask=6), 1e-10, 1e-6),
+    "stokes_sp_x_n8000": (lambda: W.stokes_tp_uniform(n=8000, seed=30, p=6, s=200, mask=1), 1e-10, 1e-6),
+    "stokes_sp_z_n20000": (lambda: W.stokes_tp_uniform(n=20000, seed=31, p=8, s=600, mask=4), STOKES_P8_FP64_TOL, 1e-6),
 }
 
 
