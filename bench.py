@@ -33,7 +33,10 @@ def log(msg):
 
 
 def time_form(pk, torch, pb, precision, steps, warmup):
+    t_plan = time.perf_counter()
     plan = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=precision, flags=pk.PHASE_TIMING)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t_plan
     xyz = torch.as_tensor(pb.points, device="cuda")
     dens = torch.as_tensor(pb.density, device="cuda")
     out = torch.empty_like(dens)
@@ -59,7 +62,64 @@ def time_form(pk, torch, pb, precision, steps, warmup):
     st = plan.stats()
     res = out.cpu().numpy()
     plan.close()
-    return {"s_total": total, "s_set_points": t_sp / steps, "s_evaluate": t_ev / steps, "stats": st}, res
+    return {"s_total": total, "s_set_points": t_sp / steps, "s_evaluate": t_ev / steps, "stats": st,
+            "s_plan": t_plan}, res
+
+
+def other_configs(pk, torch, W, steps=3, warmup=1):
+    """Throughput of the other configurations (mixed form): SP Laplace N=2000; DP Stokes slab
+    N=4M p=10; 64 SP Laplace problems x 16 RHS in one batched forest; clustered TP Stokes
+    N=16M p=12 x 4 RHS.  One step = set_points (or set_points_batch) + evaluate."""
+    res = {}
+
+    def run(name, kernel, mask, p, s, set_pts, dens, n_total):
+        t0 = time.perf_counter()
+        plan = pk.Plan(kernel, mask, p, s, precision=pk.MIXED, flags=pk.PHASE_TIMING)
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter() - t0
+        out = torch.empty_like(dens)
+        for _ in range(warmup):
+            set_pts(plan)
+            plan.evaluate(dens, out=out)
+        torch.cuda.synchronize()
+        plan.stats()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            set_pts(plan)
+            plan.evaluate(dens, out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        st = plan.stats()
+        R = dens.shape[0]
+        res[name] = {"ms_per_step": ms, "targets_per_s": n_total / (ms * 1e-3),
+                     "target_rhs_per_s": n_total * R / (ms * 1e-3), "n": n_total, "n_rhs": R, "p": p, "s": s,
+                     "plan_create_s": t_plan, "ms_phase": st["ms_phase"], "boxes": st["n_boxes"],
+                     "depth": st["depth"], "near_pairs": st["near_pairs"]}
+        log(f"{name}: {ms:.2f} ms/step, {n_total / (ms * 1e-3):.3e} targets/s")
+        plan.close()
+        del out
+
+    pb = W.laplace_sp_uniform()
+    xyz = torch.as_tensor(pb.points, device="cuda")
+    run("laplace_sp_n2000_p8_s50", pb.kernel, pb.periodic_mask, pb.p, pb.s, lambda pl: pl.set_points(xyz),
+        torch.as_tensor(pb.density, device="cuda"), pb.n)
+    pb = W.stokes_dp_slab()
+    xyz = torch.as_tensor(pb.points, device="cuda")
+    run("stokes_dp_slab_n4000000_p10_s2000", pb.kernel, pb.periodic_mask, pb.p, pb.s,
+        lambda pl: pl.set_points(xyz), torch.as_tensor(pb.density, device="cuda"), pb.n)
+    del pb, xyz
+    probs = W.laplace_sp_batch()
+    counts = [q.n for q in probs]
+    xyz = torch.as_tensor(np.concatenate([q.points for q in probs]), device="cuda")
+    dens = torch.as_tensor(np.concatenate([q.density for q in probs], axis=1), device="cuda")
+    run("laplace_sp_batch64_rhs16_p8_s2000", probs[0].kernel, probs[0].periodic_mask, probs[0].p, probs[0].s,
+        lambda pl: pl.set_points_batch(counts, xyz), dens, int(sum(counts)))
+    del probs, xyz, dens
+    pb = W.stokes_tp_clustered()
+    xyz = torch.as_tensor(pb.points, device="cuda")
+    run("stokes_tp_clustered_n16000000_p12_s2000_rhs4", pb.kernel, pb.periodic_mask, pb.p, pb.s,
+        lambda pl: pl.set_points(xyz), torch.as_tensor(pb.density, device="cuda"), pb.n)
+    return res
 
 
 def cpu_baseline(pb, n_leaves_sample=6):
@@ -100,6 +160,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--configs", action="store_true",
+                    help="also time the other configurations (DP slab, batched forest, clustered p=12) and add "
+                         "them to the line under 'other_configs' (takes several minutes)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (a plain copy kernel of known size, "
                          "to calibrate rocprofv3 FETCH_SIZE/WRITE_SIZE)")
@@ -154,11 +217,14 @@ def main():
                  "ms_set_points": r64["s_set_points"] * 1e3, "ms_evaluate": r64["s_evaluate"] * 1e3,
                  "eval_only_targets_per_s": pb.n / r64["s_evaluate"], "ms_phase": r64["stats"]["ms_phase"]},
         "speedup_mixed_vs_fp64": r64["s_total"] / rmx["s_total"],
+        "plan_create_s": {"mixed": rmx["s_plan"], "fp64": r64["s_plan"]},
         "tree": {k: st[k] for k in ("n_boxes", "n_leaves", "depth", "n_u", "n_v", "n_w", "n_x", "u_pairs",
                                     "near_pairs")},
         "accuracy": {"rel_l2_mixed_vs_fp64_gpu": rel_mx_vs_64},
         "roofline": roofline,
     }
+    if args.configs:
+        rec["other_configs"] = other_configs(pk, torch, W)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb, (f, sub) = cpu_baseline(pb)
