@@ -87,7 +87,7 @@ typedef struct {
                                     0 selects 2^-52 * dim(A), the numerical-rank criterion of
                                     Table 1: a bare 2^-52 keeps directions at the rounding level
                                     of A, along which the solution is noise */
-    unsigned flags;              /* PKIFMM_SKIP_CHECKS */
+    unsigned flags;              /* an OR of the PKIFMM_* flags below; other bits are invalid */
 } pkifmm_config;
 
 #define PKIFMM_SKIP_CHECKS 1u    /* skip the SP/DP neutrality check (no device-to-host read) */
@@ -96,6 +96,14 @@ typedef struct {
 #define PKIFMM_GRAPH 4u          /* pkifmm_evaluate captures its launch sequence into a HIP graph
                                     (once per points/n_rhs/density/potential pointers) and replays
                                     it on `stream`; implies no neutrality check and no phase timing */
+#define PKIFMM_FAR_STEP_D 8u     /* the far field (images beyond the first layer) is solved into the
+                                    root's own downward equivalent density T_M2L phi^{B0,u}
+                                    (Section 3.4) and evaluated at every target directly
+                                    (Algorithm 2, step d: n_surf extra float64 kernel evaluations per
+                                    target, in the W/L2T launch), instead of being added to the
+                                    root's downward check potential and handed down the tree.  The
+                                    results agree to the FMM's truncation accuracy, not to rounding.
+                                    No effect when periodic_mask is 0. */
 
 /* phases of one evaluation: up and M2L on the caller's stream; the near field on a
  * library-owned stream, starting during M2L; then down and leaf on the caller's stream.

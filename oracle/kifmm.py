@@ -176,12 +176,20 @@ class KIFMM:
         return phi_u
 
     def evaluate(self, density: np.ndarray, target_leaves: Optional[Sequence[int]] = None,
-                 return_sorted: bool = False):
+                 return_sorted: bool = False, step_d: bool = False):
         """Potentials at all points (input order), or at the points of the given leaves.
 
         density: [N, k] (or [N] for Laplace) in input order.
         With target_leaves, returns {leaf: potentials [count, k] in Morton order};
         only the downward pass along those leaves' ancestors is computed.
+
+        The far field of the images beyond the first layer enters as the root's downward check
+        potential M_root phi^{B0,u} (Section 3.3, Eqs. for q^{F} through the root's upward
+        density).  By default it is added to the root's check potential and reaches the targets
+        through L2L and each leaf's L2T.  With step_d, it is solved into its own downward
+        equivalent density on the root's surface, phi^{B0,d} = T_M2L phi^{B0,u} (Section 3.4),
+        which is evaluated at every target directly (Algorithm 2, step d); the tree's root
+        then carries no far field.  The two agree to the FMM's truncation accuracy.
         """
         t, ops, k, L = self.tree, self.ops, self.k, self.L
         dens = np.asarray(density, dtype=np.float64).reshape(-1, k)
@@ -222,17 +230,21 @@ class KIFMM:
             h = t.edge(b)
             q = qd[b]
             if b == 0:
-                q = q + ops.mroot @ phi_u[0]
+                if not step_d:
+                    q = q + ops.mroot @ phi_u[0]
             else:
                 par = t.parent[b]
                 o = t.children[par].index(b)
                 q = q + ops.l2l[o] @ phi_d[par] / t.edge(par)
             phi_d[b] = h * ops.down.apply(q)
+        phi_far = t.edge(0) * ops.down.apply(ops.mroot @ phi_u[0]) if step_d else None
         out = {}
         for b in leaves:
             x = self._pts(b)
             pot = np.zeros((x.shape[0], k))
             direct(self.kernel, x, self._surf(b, OUTER), phi_d[b], pot)
+            if step_d:
+                direct(self.kernel, x, self._surf(0, OUTER), phi_far, pot)
             for (a, p) in self.lists.W[b]:
                 if self.direct_source(a):
                     direct(self.kernel, x, self._pts(a), ds[t.begin[a]:t.end[a]], pot, shift=p)
@@ -257,10 +269,10 @@ class KIFMM:
 
 
 def evaluate(kernel: int, mask: int, p: int, s: int, points: np.ndarray, density: np.ndarray,
-             rel_threshold: Optional[float] = None) -> np.ndarray:
+             rel_threshold: Optional[float] = None, step_d: bool = False) -> np.ndarray:
     """Convenience wrapper: [R, N, k] densities -> [R, N, k] potentials."""
     f = KIFMM(kernel, mask, p, s, points, rel_threshold)
     dens = np.asarray(density, dtype=np.float64)
     if dens.ndim == 2:
         dens = dens[None]
-    return np.stack([f.evaluate(d) for d in dens])
+    return np.stack([f.evaluate(d, step_d=step_d) for d in dens])

@@ -21,6 +21,7 @@ FP64, MIXED = 0, 1
 SKIP_CHECKS = 1
 PHASE_TIMING = 2
 GRAPH = 4
+FAR_STEP_D = 8
 
 OK = 0
 ERR_INVALID_ARG, ERR_OUT_OF_BOX, ERR_INCOMPATIBLE, ERR_UNSUPPORTED = -1, -2, -3, -4

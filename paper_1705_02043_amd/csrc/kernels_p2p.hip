@@ -193,6 +193,7 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
             }
         }
         const double* phi = seg.kind == 1 ? a.phi_u : a.phi_d;
+        const int64_t pcol = seg.kind == 4 ? seg.slot : (int64_t)b;   // density column block
         const double sf = (seg.kind == 1 ? kInner : kOuter) * sh;
         for (int c0 = 0; c0 < count; c0 += kThreads) {
             const int cnt = min(kThreads, count - c0);
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
                     s_y[tid] = (T)(sf * usurf[3 * s + 1] + scy - shy);
                     s_z[tid] = (T)(sf * usurf[3 * s + 2] + scz - shz);
                     for (int q = 0; q < RB; ++q) {
-                        const double* src = phi + ((int64_t)b * a.R + r0 + q) * kn + KD * s;
+                        const double* src = phi + ((int64_t)pcol * a.R + r0 + q) * kn + KD * s;
                         for (int c = 0; c < KD; ++c) s_d[KD * q + c][tid] = (T)src[c];
                     }
                 }

@@ -45,10 +45,12 @@ void launch_density_sums(const double* ds, int64_t n, int R, int k, const int64_
 struct Seg {         // one source segment
     int kind;        // 0: points of box, 1: inner surface (phi_u), 2: outer surface (phi_d),
                      // 3: points of box, both ways (a U-list pair evaluated once: the box's
-                     //    points also receive the item's targets, into partial slots)
+                     //    points also receive the item's targets, into partial slots),
+                     // 4: outer surface of box, density from phi_d's column block `slot`
+                     //    (the root's far-field density of step d)
     int box;
     int shift;       // (sx+1)*9 + (sy+1)*3 + (sz+1)
-    int64_t slot = 0;   // kind 3: first partial slot (one per point of box)
+    int64_t slot = 0;   // kind 3: first partial slot (one per point of box); kind 4: column block
 };
 struct Work {        // one workgroup's targets and its segment range
     int tbox;        // target box

@@ -18,6 +18,10 @@
 // points than a surface acts (W) or is acted on (X) by direct sums instead of
 // through its equivalent/check surface.
 //   8. un-permute and apply 1/(4 pi) or 1/(8 pi) and 1/L
+// With PKIFMM_FAR_STEP_D the root's downward solve writes its own column block
+// (after the tree's boxes), the roots pass nothing down the tree, and every leaf's
+// L2T item also evaluates that block on the root's outer surface: the paper's own
+// step d.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -184,6 +188,8 @@ void check_config(const pkifmm_config& c) {
     if (c.precision != PKIFMM_FP64 && c.precision != PKIFMM_MIXED) throw Error(PKIFMM_ERR_INVALID_ARG, "precision");
     if (!(c.box_length > 0.0) || !std::isfinite(c.box_length)) throw Error(PKIFMM_ERR_INVALID_ARG, "box_length");
     if (c.svd_rel_threshold < 0.0 || c.svd_rel_threshold >= 1.0) throw Error(PKIFMM_ERR_INVALID_ARG, "svd_rel_threshold");
+    const unsigned known = PKIFMM_SKIP_CHECKS | PKIFMM_PHASE_TIMING | PKIFMM_GRAPH | PKIFMM_FAR_STEP_D;
+    if (c.flags & ~known) throw Error(PKIFMM_ERR_INVALID_ARG, "flags");
 }
 
 // SVD of a kn x kn matrix on the device (rocSOLVER, one-sided bidiagonal QR);
@@ -325,6 +331,12 @@ void build_tree_device(pkifmm_plan* P, const uint64_t* keys, int64_t n, int s_ma
 // into its own buffers, so that an evaluation can launch the kernels of a stage while the
 // host builds the next one.
 
+// The far field evaluated at the targets from the root's own density (step d) rather than
+// handed down the tree
+bool far_step_d(const pkifmm_plan* P) {
+    return (P->cfg.flags & PKIFMM_FAR_STEP_D) != 0 && P->cfg.periodic_mask != 0;
+}
+
 // Stage 1: S2M and X items, per-level and root GEMMs, workspace.
 void build_stage_tree(pkifmm_plan* P, int R) {
     const HostTree& t = P->tree;
@@ -411,7 +423,13 @@ void build_stage_tree(pkifmm_plan* P, int R) {
         P->g_up1[lv] = range([&] { add_gemm(g, 0, P->r_up, cols, cols, one); });
         P->g_up2[lv] = range([&] { add_gemm(g, 0, kn, cols, cols, hs); });
         P->g_dn1[lv] = range([&] { add_gemm(g, 0, P->r_dn, cols, cols, one); });
-        P->g_dn2[lv] = range([&] { add_gemm(g, 0, kn, cols, cols, hs); });
+        if (lv == 0 && far_step_d(P)) {   // the roots' far-field densities go to their own block
+            std::vector<int> far_cols(cols.size());
+            for (size_t i = 0; i < cols.size(); ++i) far_cols[i] = cols[i] - b0 * R + nb * R;
+            P->g_dn2[lv] = range([&] { add_gemm(g, 0, kn, cols, far_cols, hs); });
+        } else {
+            P->g_dn2[lv] = range([&] { add_gemm(g, 0, kn, cols, cols, hs); });
+        }
         if (lv >= 1)
             P->g_l2l[lv] = range([&] {
                 const double hp = 2.0 * h;
@@ -453,7 +471,8 @@ void build_stage_tree(pkifmm_plan* P, int R) {
     P->phi_u.ensure(cols * kn);
     P->q_d.ensure(cols * kn);
     P->q_x.ensure(cols * kn);
-    P->phi_d.ensure(cols * kn);
+    const int n_roots = t.level_start[1] - t.level_start[0];
+    P->phi_d.ensure((cols + (far_step_d(P) ? (size_t)n_roots * R : 0)) * kn);
     P->tmp.ensure(cols * kn);
     P->ds.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
     if (P->cfg.precision == PKIFMM_MIXED) P->ds32.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
@@ -610,6 +629,11 @@ void build_stage_near(pkifmm_plan* P, int R) {
             for (int64_t e = L.w_off[b]; e < L.w_off[b + 1]; ++e)
                 if (!small_leaf(L.w[e].src)) segs.push_back(Seg{1, L.w[e].src, code(L.w[e])});
             segs.push_back(Seg{2, b, kSelf});
+            if (far_step_d(P)) {   // step d: the root's far-field density, column block nb + root
+                int root = b;
+                while (t.parent[root] >= 0) root = t.parent[root];
+                segs.push_back(Seg{4, root, kSelf, (int64_t)nb + (root - t.level_start[0])});
+            }
             const int s1 = (int)segs.size();
             for (int c0 = 0; c0 < cnt; c0 += 512)
                 work.push_back(Work{b, 0, t.begin[b] + c0, std::min(512, cnt - c0), s0, s1});
@@ -891,6 +915,9 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
         launch_fill_zero(P->q_u.p, (int64_t)cols * kn, s);     // kernels, not memset nodes (graph-safe)
         launch_fill_zero(P->q_d.p, (int64_t)cols * kn, s);
         launch_fill_zero(P->q_x.p, (int64_t)cols * kn, s);
+        if (far_step_d(P))   // the roots hand no far field down the tree
+            launch_fill_zero(P->phi_d.p + (size_t)t.level_start[0] * R * kn,
+                             (int64_t)(t.level_start[1] - t.level_start[0]) * R * kn, s);
         run_p2p(P, P->w_s2m, nullptr, P->q_u.p, R, false, false, s, true);
         hipStream_t sx = P->x_stream, sn = P->near_stream;
         PK_HIP(hipEventRecord(P->ev_fork, s));

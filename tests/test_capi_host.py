@@ -36,6 +36,8 @@ def test_status_strings_and_bad_config():
     assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_INVALID_ARG
     cfg.kernel, cfg.periodic_mask = pk.STOKES, 8   # no such axis
     assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_INVALID_ARG
+    cfg.periodic_mask, cfg.flags = 7, 16           # no such flag
+    assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_INVALID_ARG
     assert L.pkifmm_plan_destroy(None) == 0
 
 

@@ -346,6 +346,48 @@ def test_batched_config_sampled():
         assert err < 1e-6
 
 
+@pytest.mark.parametrize("name", ["stokes_tp_n20000", "laplace_sp_n2000", "stokes_dp_slab_n20000",
+                                  "laplace_tp_n3000"])
+def test_far_step_d(name):
+    """PKIFMM_FAR_STEP_D (Algorithm 2, step d: the far field solved into the root's own downward
+    equivalent density and evaluated at every target) against the oracle's step-d evaluation,
+    both forms; and against the default placement only to the FMM's truncation accuracy."""
+    pk = _pk()
+    pb, _, ref_fold = _oracle(name)
+    tol64, tolm = CASES[name][1], CASES[name][2]
+    f = okifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+    ref = np.stack([f.evaluate(d, step_d=True) for d in pb.density])
+    for precision, tol in ((0, tol64), (1, tolm)):
+        plan = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=precision, flags=pk.FAR_STEP_D)
+        plan.set_points(_dev(pb.points))
+        out = plan.evaluate(_dev(pb.density)).cpu().numpy()
+        err = _rel(out, ref)
+        print(f"{name} step d precision={precision}: rel L2 {err:.3e} (vs folded oracle "
+              f"{_rel(out, ref_fold):.3e})", flush=True)
+        assert err < tol
+    assert 0 < _rel(ref, ref_fold) < 1e-5
+
+
+def test_far_step_d_batch():
+    """Step d in a forest: each problem's root has its own far-field density column; a one-leaf
+    problem (root = leaf) and an empty problem included; 2 RHS."""
+    pk = _pk()
+    sizes = [3000, 0, 7, 12000]
+    pts, dens = _batch(sizes, 35, 2)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    for precision, tol in ((0, 1e-10), (1, 1e-6)):
+        plan = pk.Plan(pk.LAPLACE, pk.PERIODIC_X, 6, 40, precision=precision, flags=pk.FAR_STEP_D)
+        plan.set_points_batch(sizes, _dev(np.concatenate(pts)))
+        out = plan.evaluate(_dev(np.concatenate(dens, axis=1))).cpu().numpy()
+        for i, n in enumerate(sizes):
+            if n == 0:
+                continue
+            f = okifmm.KIFMM(1, 1, 6, 40, pts[i])
+            for r in range(2):
+                err = _rel(out[r, off[i]:off[i + 1]], f.evaluate(dens[i][r], step_d=True))
+                assert err < tol, (precision, i, r, err)
+
+
 def test_graph_replay_matches_eager():
     """PKIFMM_GRAPH: captured once, replayed; each replay bitwise equal to the eager evaluation,
     with unrelated eager GPU work between replays; new points trigger a new capture."""

@@ -568,6 +568,35 @@ def test_near_layer_independence():
     assert np.linalg.norm(q1 - res[2]) / np.linalg.norm(ex) < 3e-5
 
 
+def test_step_d_far_field():
+    """Algorithm 2's step d (the far field solved into the root's own downward equivalent
+    density, phi^{B0,d} = T_M2L phi^{B0,u} of Section 3.4, and evaluated at every target) against
+    the Ewald sums, and against the default placement that hands the same check potential down
+    the tree.  The two differ only by the truncation of the downward translations, far below the
+    FMM's own error; a wrong surface, a lost box-size factor or a far field counted twice would
+    each show at the 1e-3 level or above."""
+    cases = [(K.STOKES, 7, W.stokes_tp_uniform(n=300, seed=14, s=30, p=8), 2e-5, 1e-6),
+             (K.LAPLACE, 1, W.laplace_sp_uniform(n=400, seed=16, s=30), 1e-6, 2e-8)]
+    for kern, mask, pb, tol, tol_d in cases:
+        f = kifmm.KIFMM(kern, mask, 8, 30, pb.points)
+        d = pb.density[0]
+        ex = periodic.exact_potential(kern, mask, pb.points, pb.points, d)
+        a = f.evaluate(d)
+        b = f.evaluate(d, step_d=True)
+        nx = np.linalg.norm(ex)
+        assert np.linalg.norm(b - ex) / nx < tol
+        assert 0 < np.linalg.norm(a - b) / nx < tol_d
+        # the step-d term by itself is the images beyond the first layer, to the same accuracy
+        ops = f.ops
+        phi_u = f.upward(np.ascontiguousarray(d.reshape(len(d), -1)[f.tree.perm]))[0]
+        far = (K.kernel_matrix(kern, f.u, ops.outer + 0.5) @ ops.down.apply(ops.mroot @ phi_u))
+        near = np.zeros_like(ex)
+        axes = [np.arange(-1, 2) if mask >> i & 1 else np.zeros(1, int) for i in range(3)]
+        for p in itertools.product(*axes):
+            direct(kern, pb.points, pb.points, d, near, shift=np.array(p, dtype=float))
+        assert np.linalg.norm(far.reshape(ex.shape) - (ex - near)) / nx < tol
+
+
 def test_kifmm_linearity_and_periodic_relabel():
     pb = W.stokes_tp_uniform(n=250, seed=15, s=30, p=6, n_rhs=2)
     f = kifmm.KIFMM(K.STOKES, 7, 6, 30, pb.points)
