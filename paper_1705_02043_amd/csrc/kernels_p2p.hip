@@ -28,11 +28,20 @@
 // partial slot; a gather kernel adds the slots of every leaf in list order.  Results
 // are deterministic and do not depend on scheduling.
 //
-// Mixed precision (U lists and direct W/X): coordinates are float hi + lo
-// offsets from the leaf centres (source offsets plus the exact dyadic
-// difference of the box centres), so only the final differences are rounded;
-// the kernel is evaluated in float32 with v_rsq_f32; partial sums over 32
-// sources are kept in float32 and added into float64 accumulators.
+// Mixed precision (U lists and direct W/X): each point is stored as an integer offset
+// from its leaf centre in units of 2^-29 h (h the leaf's edge).  For a pair of leaves the
+// offsets are brought to the unit 2^-29 H of the larger leaf (an exact or rounded shift) and
+// the centre difference, an exact multiple of that unit, is added to the targets once per
+// segment, so every separation is an exact integer difference rounded once to float32; the
+// kernel is evaluated in float32 with v_rsq_f32 on these scaled separations and the sums are
+// multiplied back by 2^29 / H (both kernels are homogeneous of degree -1).  Partial sums over
+// 32 sources are kept in float32 and added into float64 accumulators.
+//
+// One right-hand side: each 64-source group of a tile is stored twice in a row in LDS, one
+// record (coordinates and densities) per source, so that the rotated sweep reads every step
+// at a constant offset from one address per lane (no index arithmetic in the inner loop).
+#include <climits>
+
 #include "launch.h"
 
 namespace pk {
@@ -103,22 +112,70 @@ __device__ __forceinline__ void interact_both(T dx, T dy, T dz, const T* fs, T* 
 
 __device__ __forceinline__ double box_h(const P2PArgs& a, int b) { return ldexp(1.0, -a.box_level[b]); }
 
+// a staged source: coordinates and densities, one LDS record
+template <int KD, typename C, typename T>
+struct alignas(16) SrcRec {
+    C x, y, z;
+    T d[KD];
+};
+
+// v / 2^k rounded to nearest (ties up), for the integer offsets of a finer leaf
+__device__ __forceinline__ int shr_round(int v, int k) { return (v + ((1 << k) >> 1)) >> k; }
+// LDS slot of tile source i: with one right-hand side each 64-source group is stored twice
+template <int RB>
+__device__ __forceinline__ int slot_of(int i) { return RB == 1 ? ((i >> 6) << 7) + (i & 63) : i; }
+// one component of a separation: exact integer difference (mixed form, wrapping as the
+// hardware does, in unsigned arithmetic), rounded once to float; or a float64 difference
+template <bool MIXED>
+__device__ __forceinline__ float sep(int t, int s) { return (float)(int)((unsigned)t - (unsigned)s); }
+template <bool MIXED>
+__device__ __forceinline__ double sep(double t, double s) { return t - s; }
+
 template <int KD, bool MIXED, int RB>
 __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
-    using T = typename std::conditional<MIXED, float, double>::type;
+    using T = typename std::conditional<MIXED, float, double>::type;   // kernel arithmetic
+    using C = typename std::conditional<MIXED, int, double>::type;     // staged coordinates
     constexpr int ND = KD * RB;
-    __shared__ T s_x[kThreads], s_y[kThreads], s_z[kThreads], s_d[ND][kThreads];
-    __shared__ float s_lx[MIXED ? kThreads : 1], s_ly[MIXED ? kThreads : 1], s_lz[MIXED ? kThreads : 1];
-    // kind-3 segments: per-wave running sums of the reverse terms of a 64-source group
+    // one-RHS passes store each 64-source group of a tile twice in a row, so that the rotated
+    // sweep of the pair-once segments reads LDS at a constant offset from one address per wave
+    // (one record per source, so that each step is one or two vector reads); several
+    // right-hand sides read separate arrays, each at one address for the whole workgroup
+    constexpr bool kRec = RB == 1;
+    __shared__ SrcRec<KD, C, T> s_src[kRec ? 2 * kThreads : 1];
+    __shared__ C s_x[kRec ? 1 : kThreads], s_y[kRec ? 1 : kThreads], s_z[kRec ? 1 : kThreads];
+    __shared__ T s_d[ND][kRec ? 1 : kThreads];
+    auto put = [&](int q, C x, C y, C z, const T* d) {
+        if constexpr (kRec) {
+            SrcRec<KD, C, T> r;
+            r.x = x; r.y = y; r.z = z;
+            for (int c = 0; c < KD; ++c) r.d[c] = d[c];
+            s_src[q] = r;
+        } else {
+            s_x[q] = x; s_y[q] = y; s_z[q] = z;
+            for (int c = 0; c < ND; ++c) s_d[c][q] = d[c];
+        }
+    };
+    auto get = [&](int q, C& x, C& y, C& z, T* d) {
+        if constexpr (kRec) {
+            const SrcRec<KD, C, T> r = s_src[q];
+            x = r.x; y = r.y; z = r.z;
+            for (int c = 0; c < KD; ++c) d[c] = r.d[c];
+        } else {
+            x = s_x[q]; y = s_y[q]; z = s_z[q];
+            for (int c = 0; c < ND; ++c) d[c] = s_d[c][q];
+        }
+    };
+    // kind-3 segments: per-wave running sums of the reverse terms of a 64-source group, in two
+    // halves (a source met before and after the rotation wraps)
     constexpr int NW = RB == 1 ? kThreads / 64 : 1;
-    __shared__ double s_dacc[NW][KD][64];
+    __shared__ double s_dacc[NW][KD][128];
 
     const double* __restrict__ usurf = a.usurf;
     const int kn = KD * a.n_surf;
     const int64_t n = a.n;
     const int tid = threadIdx.x;
     if constexpr (RB == 1) {
-        for (int i = tid; i < NW * KD * 64; i += kThreads) (&s_dacc[0][0][0])[i] = 0.0;
+        for (int i = tid; i < NW * KD * 128; i += kThreads) (&s_dacc[0][0][0])[i] = 0.0;
     }
     // the grid may be smaller than the item list (a capped residency leaves room on every
     // compute unit for the concurrent tree passes): then workgroups take the next item from a
@@ -133,8 +190,9 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
     }
     if (wi >= a.n_work) break;
     const Work w = a.work[wi];
-    // target box centre and edge (the origin of the mixed-precision offsets)
-    const double th = box_h(a, w.tbox);
+    // target box centre and edge
+    const int tlev = a.box_level[w.tbox];
+    const double th = ldexp(1.0, -tlev);
     const double tcx = (a.box_ix[w.tbox] + 0.5) * th;
     const double tcy = (a.box_iy[w.tbox] + 0.5) * th;
     const double tcz = (a.box_iz[w.tbox] + 0.5) * th;
@@ -154,14 +212,13 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
     for (int sg = w.seg0; sg < w.seg1; ++sg) {
         const Seg seg = a.segs[sg];
         const int b = seg.box;
-        const double sh = box_h(a, b);
+        const int slev = a.box_level[b];
+        const double sh = ldexp(1.0, -slev);
         const double shx = (double)(seg.shift / 9 - 1), shy = (double)((seg.shift / 3) % 3 - 1),
                      shz = (double)(seg.shift % 3 - 1);
         const double scx = (a.box_ix[b] + 0.5) * sh + shx;
         const double scy = (a.box_iy[b] + 0.5) * sh + shy;
         const double scz = (a.box_iz[b] + 0.5) * sh + shz;
-        // source-centre minus target-centre: an exact dyadic value (mixed-mode origin shift)
-        const double dcx = scx - tcx, dcy = scy - tcy, dcz = scz - tcz;
         const bool pts = seg.kind == 0 || seg.kind == 3;
         int count, base = 0;
         if (pts) {
@@ -171,25 +228,24 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
             count = a.n_surf;
         }
         const bool self_seg = seg.kind == 0 && b == w.tbox && seg.shift == 13;
-        // per-segment target coordinates in the source frame; mixed: float hi + lo pair
-        T ux[kTPT], uy[kTPT], uz[kTPT];
-        float lx[kTPT], ly[kTPT], lz[kTPT];
+        // Mixed form: separations in integers, in units u = 2^-29 H with H the larger of the
+        // two leaves' edges (|separation| <= 2H component-wise for U, W and X pairs, so every
+        // difference fits); each leaf's offsets are rounded to that unit, the centre difference
+        // is an exact multiple of it, and the float kernel's results are scaled by 1/u (both
+        // kernels are homogeneous of degree -1).  Float64 form: absolute coordinates.
+        const int lc = min(tlev, slev);
+        const int kt = tlev - lc, ks = slev - lc;
+        const double inv_u = MIXED ? ldexp(1.0, lc + 29) : 1.0;
+        C ux[kTPT], uy[kTPT], uz[kTPT];
         for (int j = 0; j < kTPT; ++j) {
-            // target coordinates: absolute (float64 form) or relative to the target centre, as
-            // an exact hi + lo sum (mixed form); reloaded per segment to keep registers free
             const int t = w.t0 + min(tid + j * kThreads, max(w.tcount - 1, 0));
-            if (MIXED) {
-                const double tx = (double)a.off[t] + (double)a.off[3 * n + t];
-                const double ty = (double)a.off[n + t] + (double)a.off[4 * n + t];
-                const double tz = (double)a.off[2 * n + t] + (double)a.off[5 * n + t];
-                double vx = tx - dcx, vy = ty - dcy, vz = tz - dcz;
-                ux[j] = (float)vx; uy[j] = (float)vy; uz[j] = (float)vz;
-                lx[j] = (float)(vx - (double)ux[j]);
-                ly[j] = (float)(vy - (double)uy[j]);
-                lz[j] = (float)(vz - (double)uz[j]);
+            if constexpr (MIXED) {
+                const int e = lc + 29;
+                ux[j] = shr_round(a.ioff[t], kt) + (int)ldexp(tcx - scx, e);
+                uy[j] = shr_round(a.ioff[n + t], kt) + (int)ldexp(tcy - scy, e);
+                uz[j] = shr_round(a.ioff[2 * n + t], kt) + (int)ldexp(tcz - scz, e);
             } else {
-                ux[j] = (T)(a.xs[t] - shx); uy[j] = (T)(a.xs[n + t] - shy); uz[j] = (T)(a.xs[2 * n + t] - shz);
-                lx[j] = ly[j] = lz[j] = 0.f;
+                ux[j] = a.xs[t] - shx; uy[j] = a.xs[n + t] - shy; uz[j] = a.xs[2 * n + t] - shz;
             }
         }
         const double* phi = seg.kind == 1 ? a.phi_u : a.phi_d;
@@ -198,73 +254,84 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
         for (int c0 = 0; c0 < count; c0 += kThreads) {
             const int cnt = min(kThreads, count - c0);
             __syncthreads();
+            const int sl = slot_of<RB>(tid);
             if (tid < cnt) {
                 const int s = c0 + tid;
+                C cx, cy, cz;
+                T dv[ND];
                 if (pts) {
                     const int64_t q = base + s;
-                    if (MIXED) {
-                        s_x[tid] = a.off[q]; s_y[tid] = a.off[n + q]; s_z[tid] = a.off[2 * n + q];
-                        s_lx[tid] = a.off[3 * n + q]; s_ly[tid] = a.off[4 * n + q]; s_lz[tid] = a.off[5 * n + q];
-                        for (int c = 0; c < ND; ++c) s_d[c][tid] = (T)a.ds32[((int64_t)r0 * KD + c) * n + q];
+                    if constexpr (MIXED) {
+                        cx = shr_round(a.ioff[q], ks); cy = shr_round(a.ioff[n + q], ks);
+                        cz = shr_round(a.ioff[2 * n + q], ks);
+                        for (int c = 0; c < ND; ++c) dv[c] = a.ds32[((int64_t)r0 * KD + c) * n + q];
                     } else {
-                        s_x[tid] = a.xs[q]; s_y[tid] = a.xs[n + q]; s_z[tid] = a.xs[2 * n + q];
-                        for (int c = 0; c < ND; ++c) s_d[c][tid] = (T)a.ds[((int64_t)r0 * KD + c) * n + q];
+                        cx = a.xs[q]; cy = a.xs[n + q]; cz = a.xs[2 * n + q];
+                        for (int c = 0; c < ND; ++c) dv[c] = a.ds[((int64_t)r0 * KD + c) * n + q];
                     }
                 } else {   // surface sources exist only in the float64 passes
-                    s_x[tid] = (T)(sf * usurf[3 * s] + scx - shx);
-                    s_y[tid] = (T)(sf * usurf[3 * s + 1] + scy - shy);
-                    s_z[tid] = (T)(sf * usurf[3 * s + 2] + scz - shz);
-                    for (int q = 0; q < RB; ++q) {
-                        const double* src = phi + ((int64_t)pcol * a.R + r0 + q) * kn + KD * s;
-                        for (int c = 0; c < KD; ++c) s_d[KD * q + c][tid] = (T)src[c];
+                    if constexpr (!MIXED) {
+                        cx = sf * usurf[3 * s] + scx - shx;
+                        cy = sf * usurf[3 * s + 1] + scy - shy;
+                        cz = sf * usurf[3 * s + 2] + scz - shz;
+                        for (int q = 0; q < RB; ++q) {
+                            const double* src = phi + ((int64_t)pcol * a.R + r0 + q) * kn + KD * s;
+                            for (int c = 0; c < KD; ++c) dv[KD * q + c] = src[c];
+                        }
                     }
                 }
+                put(sl, cx, cy, cz, dv);
+                if constexpr (kRec) put(sl + 64, cx, cy, cz, dv);
             } else if (seg.kind == 3 && tid < ((cnt + 63) & ~63)) {
-                // padding of the last 64-source group: far away, zero density; its own
-                // reverse sums are computed and discarded
-                s_x[tid] = T(1.0e6); s_y[tid] = T(1.0e6); s_z[tid] = T(1.0e6);
-                if (MIXED) { s_lx[tid] = 0.f; s_ly[tid] = 0.f; s_lz[tid] = 0.f; }
-                for (int c = 0; c < ND; ++c) s_d[c][tid] = T(0);
+                // padding of the last 64-source group: far from every target (integers: the
+                // farthest value, never equal to a target's), zero density; its own reverse
+                // sums are computed and discarded
+                const C far = MIXED ? (C)INT_MIN : (C)1.0e6;
+                T zero[ND];
+                for (int c = 0; c < ND; ++c) zero[c] = T(0);
+                put(sl, far, far, far, zero);
+                if constexpr (kRec) put(sl + 64, far, far, far, zero);
             }
             __syncthreads();
             if constexpr (RB == 1) {
                 if (seg.kind == 3) {
                     const int lane = tid & 63, wv = tid >> 6;
                     for (int g0 = 0; g0 < cnt; g0 += 64) {
+                        const int gs = 2 * g0;              // slot of the group's first copy
                         for (int h = 0; h < 64; h += 32) {
                             T part[kTPT][KD];
                             for (int j = 0; j < kTPT; ++j)
                                 for (int c = 0; c < KD; ++c) part[j][c] = T(0);
+                            const int q0 = gs + lane + h;   // this lane's source at step 0 of the half
+                            double* dacc = &s_dacc[wv][0][lane + h];
+#pragma unroll
                             for (int jj = 0; jj < 32; ++jj) {
-                                const int ql = (lane + h + jj) & 63;
-                                const int q = g0 + ql;
+                                const int q = q0 + jj;
                                 T d[KD], cs[KD];
-                                for (int c = 0; c < KD; ++c) { d[c] = s_d[c][q]; cs[c] = T(0); }
-                                const T sx = s_x[q], sy = s_y[q], sz = s_z[q];
-                                if constexpr (MIXED) {
-                                    const float slx = s_lx[q], sly = s_ly[q], slz = s_lz[q];
-                                    for (int j = 0; j < kTPT; ++j)
-                                        interact_both<KD, T>((ux[j] - sx) + (lx[j] - slx), (uy[j] - sy) + (ly[j] - sly),
-                                                             (uz[j] - sz) + (lz[j] - slz), d, part[j], dt[j], cs);
-                                } else {
-                                    for (int j = 0; j < kTPT; ++j)
-                                        interact_both<KD, T>(ux[j] - sx, uy[j] - sy, uz[j] - sz, d, part[j], dt[j], cs);
-                                }
+                                C sx, sy, sz;
+                                get(q, sx, sy, sz, d);
+                                for (int c = 0; c < KD; ++c) cs[c] = T(0);
+                                for (int j = 0; j < kTPT; ++j)
+                                    interact_both<KD, T>(sep<MIXED>(ux[j], sx), sep<MIXED>(uy[j], sy),
+                                                         sep<MIXED>(uz[j], sz), d, part[j], dt[j], cs);
                                 for (int c = 0; c < KD; ++c)
-                                    __hip_atomic_fetch_add(&s_dacc[wv][c][ql], (double)cs[c], __ATOMIC_RELAXED,
+                                    __hip_atomic_fetch_add(dacc + c * 128 + jj, (double)cs[c], __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_WAVEFRONT);
                             }
                             for (int j = 0; j < kTPT; ++j)
-                                for (int c = 0; c < KD; ++c) acc[j][c] += (double)part[j][c];
+                                for (int c = 0; c < KD; ++c) acc[j][c] += (double)part[j][c] * inv_u;
                         }
                         __syncthreads();
                         if (tid < min(64, cnt - g0))
-                            for (int c = 0; c < KD; ++c)
-                                a.mpart[(int64_t)c * a.n_slots + seg.slot + c0 + g0 + tid] =
-                                    ((s_dacc[0][c][tid] + s_dacc[1][c][tid]) + s_dacc[2][c][tid]) + s_dacc[3][c][tid];
+                            for (int c = 0; c < KD; ++c) {
+                                double v = 0.0;
+                                for (int u = 0; u < NW; ++u) v += s_dacc[u][c][tid] + s_dacc[u][c][tid + 64];
+                                a.mpart[(int64_t)c * a.n_slots + seg.slot + c0 + g0 + tid] = v * inv_u;
+                            }
                         __syncthreads();
-                        // each lane clears its own slot; every add of the next group follows in program order
-                        for (int c = 0; c < KD; ++c) s_dacc[wv][c][lane] = 0.0;
+                        // each lane clears its own two slots; every add of the next group follows
+                        // in program order
+                        for (int c = 0; c < KD; ++c) { s_dacc[wv][c][lane] = 0.0; s_dacc[wv][c][lane + 64] = 0.0; }
                         __asm__ volatile("" ::: "memory");
                     }
                     continue;
@@ -278,31 +345,31 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
                         for (int c = 0; c < ND; ++c) part[j][c] = T(0);
                     for (int q = j0; q < j1; ++q) {
                         T d[ND];
-                        for (int c = 0; c < ND; ++c) d[c] = s_d[c][q];
-                        const float sx = s_x[q], sy = s_y[q], sz = s_z[q];
-                        const float slx = s_lx[q], sly = s_ly[q], slz = s_lz[q];
+                        C sx, sy, sz;
+                        get(slot_of<RB>(q), sx, sy, sz, d);
                         if (self_seg) {
                             for (int j = 0; j < kTPT; ++j)
-                                interact<KD, RB, true, T>((ux[j] - sx) + (lx[j] - slx), (uy[j] - sy) + (ly[j] - sly),
-                                                          (uz[j] - sz) + (lz[j] - slz), d, part[j]);
+                                interact<KD, RB, true, T>(sep<MIXED>(ux[j], sx), sep<MIXED>(uy[j], sy),
+                                                          sep<MIXED>(uz[j], sz), d, part[j]);
                         } else {
                             for (int j = 0; j < kTPT; ++j)
-                                interact<KD, RB, false, T>((ux[j] - sx) + (lx[j] - slx), (uy[j] - sy) + (ly[j] - sly),
-                                                           (uz[j] - sz) + (lz[j] - slz), d, part[j]);
+                                interact<KD, RB, false, T>(sep<MIXED>(ux[j], sx), sep<MIXED>(uy[j], sy),
+                                                           sep<MIXED>(uz[j], sz), d, part[j]);
                         }
                     }
                     for (int j = 0; j < kTPT; ++j)
-                        for (int c = 0; c < ND; ++c) acc[j][c] += (double)part[j][c];
+                        for (int c = 0; c < ND; ++c) acc[j][c] += (double)part[j][c] * inv_u;
                 }
             } else {
                 for (int q = 0; q < cnt; ++q) {
                     T d[ND];
-                    for (int c = 0; c < ND; ++c) d[c] = s_d[c][q];
+                    C sx, sy, sz;
+                    get(slot_of<RB>(q), sx, sy, sz, d);
                     for (int j = 0; j < kTPT; ++j) {
                         if (self_seg)
-                            interact<KD, RB, true, T>(ux[j] - s_x[q], uy[j] - s_y[q], uz[j] - s_z[q], d, acc[j]);
+                            interact<KD, RB, true, T>(ux[j] - sx, uy[j] - sy, uz[j] - sz, d, acc[j]);
                         else
-                            interact<KD, RB, false, T>(ux[j] - s_x[q], uy[j] - s_y[q], uz[j] - s_z[q], d, acc[j]);
+                            interact<KD, RB, false, T>(ux[j] - sx, uy[j] - sy, uz[j] - sz, d, acc[j]);
                     }
                 }
             }

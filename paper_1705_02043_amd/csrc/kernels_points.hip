@@ -61,23 +61,22 @@ __global__ void k_gather_points(const double* __restrict__ u, const uint32_t* __
     xs[2 * n + i] = u[2 * n + j];
 }
 
-// offsets from the leaf centre as a float hi + lo pair (the centre (i + 1/2) 2^-l
-// is dyadic, so the offset itself is exact in double).
+// offsets from the leaf centre as integers in units of 2^-29 h (h the leaf's edge): the
+// centre (i + 1/2) 2^-l is dyadic, so x - c is exact in double and the rounding to that grid
+// (at most 2^-30 h) is the only approximation; |offset| <= 2^28.
 // One workgroup per leaf (leaves[blockIdx.x]), threads over its points.
 __global__ void k_leaf_offsets(const double* __restrict__ xs, int64_t n, const int* __restrict__ leaves,
                                const int* __restrict__ box_begin, const int* __restrict__ box_end,
                                const int* __restrict__ lv, const int* __restrict__ bx, const int* __restrict__ by,
-                               const int* __restrict__ bz, float* __restrict__ off) {
+                               const int* __restrict__ bz, int* __restrict__ ioff) {
     const int b = leaves[blockIdx.x];
     const double h = ldexp(1.0, -lv[b]);
     const double cx = (bx[b] + 0.5) * h, cy = (by[b] + 0.5) * h, cz = (bz[b] + 0.5) * h;
+    const int e = lv[b] + 29;
     for (int64_t i = box_begin[b] + threadIdx.x; i < box_end[b]; i += blockDim.x) {
-        double o[3] = {xs[i] - cx, xs[n + i] - cy, xs[2 * n + i] - cz};
-        for (int c = 0; c < 3; ++c) {
-            float hi = (float)o[c];
-            off[c * n + i] = hi;
-            off[(3 + c) * n + i] = (float)(o[c] - (double)hi);
-        }
+        ioff[i] = (int)rint(ldexp(xs[i] - cx, e));
+        ioff[n + i] = (int)rint(ldexp(xs[n + i] - cy, e));
+        ioff[2 * n + i] = (int)rint(ldexp(xs[2 * n + i] - cz, e));
     }
 }
 
@@ -216,11 +215,11 @@ void launch_gather_points(const double* u, const uint32_t* perm, int64_t n, doub
 }
 
 void launch_leaf_offsets(const double* xs, int64_t n, const int* leaves, int n_leaves, const int* box_begin,
-                         const int* box_end, const int* lv, const int* bx, const int* by, const int* bz, float* off,
+                         const int* box_end, const int* lv, const int* bx, const int* by, const int* bz, int* ioff,
                          hipStream_t s) {
     if (n == 0 || n_leaves == 0) return;
     hipLaunchKernelGGL(k_leaf_offsets, dim3(n_leaves), dim3(256), 0, s, xs, n, leaves, box_begin, box_end, lv, bx, by,
-                       bz, off);
+                       bz, ioff);
     PK_HIP(hipGetLastError());
 }
 

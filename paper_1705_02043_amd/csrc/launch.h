@@ -21,7 +21,7 @@ void radix_sort_pairs(uint64_t* keys_in, uint64_t* keys_out, uint32_t* vals_in, 
 void launch_gather_points(const double* u, const uint32_t* perm, int64_t n, double* xs, hipStream_t s);
 void launch_leaf_offsets(const double* xs, int64_t n, const int* leaves, int n_leaves, const int* box_begin,
                          const int* box_end, const int* box_level, const int* box_ix, const int* box_iy,
-                         const int* box_iz, float* off, hipStream_t s);
+                         const int* box_iz, int* ioff, hipStream_t s);
 // density [R][n][k] input order -> ds [R][k][n] sorted (double) and optionally float
 void launch_permute_density(const double* dens, const uint32_t* perm, int64_t n, int R, int k,
                             double* ds, float* ds32, hipStream_t s);
@@ -64,7 +64,7 @@ struct P2PArgs {
     int R;               // right-hand sides
     int64_t n;           // points
     const double* xs;    // [3][n] sorted absolute coordinates
-    const float* off;    // [6][n] float hi (x,y,z) then lo (x,y,z) offsets from the leaf centre (mixed)
+    const int* ioff;     // [3][n] offsets from the leaf centre in units of 2^-29 h_leaf (mixed)
     const double* ds;    // [R][k][n] sorted densities
     const float* ds32;   // [R][k][n] (mixed)
     const double* phi_u; // [nbox*R][kn]

@@ -129,7 +129,7 @@ struct pkifmm_plan {
     DBuf<uint64_t> keys_a, keys_b;
     DBuf<uint32_t> vals_a, perm;
     DBuf<double> u_wrapped, xs;
-    DBuf<float> off;
+    DBuf<int> ioff;
     DBuf<char> sort_temp;
     DBuf<int> err_flag;
     DBuf<int> b_level, b_ix, b_iy, b_iz, b_begin, b_end, leaf_boxes;
@@ -828,7 +828,7 @@ void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_sur
     a.R = R;
     a.n = P->n;
     a.xs = P->xs.p;
-    a.off = P->off.p;
+    a.ioff = P->ioff.p;
     a.ds = P->ds.p;
     a.ds32 = P->ds32.p;
     a.phi_u = P->phi_u.p;
@@ -1166,9 +1166,9 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
         P->b_end.upload(t.end, s);
         P->leaf_boxes.upload(t.leaves, s);
         if (P->cfg.precision == PKIFMM_MIXED) {
-            P->off.ensure(6 * m);
+            P->ioff.ensure(3 * m);
             launch_leaf_offsets(P->xs.p, n, P->leaf_boxes.p, (int)t.leaves.size(), P->b_begin.p, P->b_end.p, P->b_level.p,
-                                P->b_ix.p, P->b_iy.p, P->b_iz.p, P->off.p, s);
+                                P->b_ix.p, P->b_iy.p, P->b_iz.p, P->ioff.p, s);
         }
         std::vector<int> vt;
         for (int b = 0; b < t.nbox(); ++b)
