@@ -26,6 +26,25 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int TM = 64, TN = 64, TK = 16, PAD = 2;
 
+// column j of a tile: its input column (K block kb), output column and scale
+__device__ __forceinline__ int gemm_in(const GemmArgs& a, int j, int kb) {
+    if (a.rhs > 0) {
+        const int e = j / a.rhs;
+        return a.in_col[e] * a.rhs + (j - e * a.rhs);
+    }
+    return a.in_col[(int64_t)j * 8 + kb];
+}
+__device__ __forceinline__ int gemm_out(const GemmArgs& a, int j) {
+    if (a.rhs > 0) {
+        const int e = j / a.rhs;
+        return a.out_col[e] * a.rhs + (j - e * a.rhs);
+    }
+    return a.out_col[j];
+}
+__device__ __forceinline__ double gemm_scale(const GemmArgs& a, int j) {
+    return a.scale[a.rhs > 0 ? j / a.rhs : j];
+}
+
 struct Stage {     // one thread's share of a K slice: 4 elements of A and 4 of B
     double a[4], b[4];
 };
@@ -70,7 +89,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_f64(GemmArgs a, int split, do
     const int nkb = a.in_stride;
     for (int i = tid; i < TN * nkb; i += 256) {
         int c = i / nkb;
-        s_in[i] = c < t.ncol ? a.in_col[(int64_t)(t.col0 + c) * 8 + (i % nkb)] : -1;
+        s_in[i] = c < t.ncol ? gemm_in(a, t.col0 + c, i % nkb) : -1;
     }
     v4d acc[2][2];
     for (int i = 0; i < 2; ++i)
@@ -112,8 +131,8 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_f64(GemmArgs a, int split, do
     for (int j = 0; j < 2; ++j) {
         const int n = wn + 16 * j + (lane & 15);
         if (n >= t.ncol) continue;
-        const int oc = a.out_col[t.col0 + n];
-        const double sc = a.scale[t.col0 + n];
+        const int oc = gemm_out(a, t.col0 + n);
+        const double sc = gemm_scale(a, t.col0 + n);
         double* C = a.C + (int64_t)oc * a.ldc;
         for (int i = 0; i < 2; ++i)
             for (int v = 0; v < 4; ++v) {
@@ -135,9 +154,9 @@ __global__ __launch_bounds__(256) void k_gemm_split_reduce(GemmArgs a, int split
         if (cc >= t.ncol || row >= a.M) continue;
         double s = 0.0;
         for (int q = 0; q < split; ++q) s += P[(int64_t)q * (TM * TN) + e];
-        const int oc = a.out_col[t.col0 + cc];
+        const int oc = gemm_out(a, t.col0 + cc);
         double* C = a.C + (int64_t)oc * a.ldc;
-        const double r = a.scale[t.col0 + cc] * s;
+        const double r = gemm_scale(a, t.col0 + cc) * s;
         C[row] = a.accumulate ? C[row] + r : r;
     }
 }

@@ -121,6 +121,9 @@ struct GemmArgs {
     const int* out_col;
     const double* scale;
     int accumulate;       // C = scale*Op*B (+ C)
+    int rhs;              // > 0: in_col, out_col and scale hold one value per entry e, and column j of
+                          // a tile is entry j / rhs with right-hand side r = j % rhs: input column
+                          // in_col[e] * rhs + r, output column out_col[e] * rhs + r (one K block)
 };
 // partial: workspace for split-K partial tiles (NULL disables splitting), capacity in doubles
 void launch_gemm(const GemmArgs& a, hipStream_t s, double* partial = nullptr, int64_t partial_cap = 0);
@@ -128,6 +131,32 @@ int gemm_split_factor(int n_tiles, int K);
 // q[b] += sum_{e in [off[b], off[b+1])} temp[e]  over R columns each; rows kn
 void launch_segment_reduce(const double* temp, const int64_t* off, const int* boxes, int nboxes,
                            int R, int kn, double* q, hipStream_t s);
+
+// ---- M2L on the int8 matrix cores with exact accumulation (kernels_oz.hip), mixed form
+constexpr int kOzSlices = 6;          // base-2^7 digits per operand entry
+struct OzArgs {
+    const int8_t* a_sl;   // operator slices [op][kOzSlices][Mp][Kp]
+    const int* a_exp;     // [op][Mp] row exponents
+    int Mp, Kp, M;        // padded rows and K (multiples of 64), real rows
+    const int8_t* b_sl;   // column slices [kOzSlices][ncols][Kp]
+    const int* b_exp;     // [ncols] column exponents
+    int64_t b_slice_stride;   // ncols * Kp
+    double* C;            // column j at C + j * ldc
+    int64_t ldc;
+    const Tile* tiles;
+    int n_tiles;
+    const int* in_col;    // per entry: input box column (columns expanded as GemmArgs::rhs)
+    const int* out_col;   // per entry: output slot
+    const double* scale;  // per entry
+    int rhs;              // right-hand sides (>= 1)
+    int accumulate;
+};
+int oz_padded(int n);     // n rounded up to the GEMM's 64
+// operators: n_ops column-major M x K float64 matrices, consecutive
+void launch_oz_slice_operators(const double* ops, int n_ops, int M, int K, int8_t* out, int* e, hipStream_t s);
+// columns c < ncols of B (at B + c * ldb, K rows)
+void launch_oz_slice_columns(const double* B, int64_t ldb, int K, int64_t ncols, int8_t* out, int* e, hipStream_t s);
+void launch_gemm_oz(const OzArgs& a, hipStream_t s);
 
 // ---- operator construction (kernels_ops.hip), raw kernels (no 1/(4pi), 1/(8pi))
 // out[(k*i+a) + (k*j+b)*ld] = K(X_i - Y_j)_{ab}; X, Y: [m][3], [n][3]

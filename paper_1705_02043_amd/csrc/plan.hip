@@ -114,6 +114,11 @@ struct pkifmm_plan {
     DBuf<double> up_Ut, up_VS, dn_Ut, dn_VS;   // U^T: r x kn, V S^+: kn x r
     DBuf<double> m2m, l2l;              // [8][kn*kn]
     DBuf<double> m2l;                   // [316][kn*kn]
+    // mixed form: M2L operators and upward densities as int8 digit slices (kernels_oz.hip)
+    DBuf<int8_t> m2l_oz;                // [316][kOzSlices][Mp][Kp]
+    DBuf<int> m2l_oz_e;                 // [316][Mp] row exponents
+    DBuf<int8_t> phi_oz;                // [kOzSlices][nbox*R][Kp]
+    DBuf<int> phi_oz_e;                 // [nbox*R] column exponents
     DBuf<double> mroot;                 // [kn*kn]
 
     // points and tree (a forest: one tree per problem, boxes numbered level-major)
@@ -474,6 +479,10 @@ void build_stage_tree(pkifmm_plan* P, int R) {
     const int n_roots = t.level_start[1] - t.level_start[0];
     P->phi_d.ensure((cols + (far_step_d(P) ? (size_t)n_roots * R : 0)) * kn);
     P->tmp.ensure(cols * kn);
+    if (P->cfg.precision == PKIFMM_MIXED) {
+        P->phi_oz.ensure((size_t)kOzSlices * cols * oz_padded(kn));
+        P->phi_oz_e.ensure(cols);
+    }
     P->ds.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
     if (P->cfg.precision == PKIFMM_MIXED) P->ds32.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
     P->pot.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
@@ -733,8 +742,10 @@ void build_stage_m2l(pkifmm_plan* P, int R) {
         std::vector<int> slot_count(kM2LGroups, 0);
         std::vector<std::vector<int>> gtarg(kM2LGroups);
         std::vector<int64_t> pos(per_idx.begin(), per_idx.end() - 1);
-        std::vector<int> in_c((size_t)nv * R), out_c((size_t)nv * R);
-        std::vector<double> sc_c((size_t)nv * R);
+        // per entry (laid out by offset): source box, slot in its group, scale; the GEMMs expand
+        // each entry into its R right-hand-side columns on the device
+        std::vector<int> in_c((size_t)nv), out_c((size_t)nv);
+        std::vector<double> sc_c((size_t)nv);
         for (int b = 0; b < nb; ++b) {
             for (int q = 0; q < kM2LGroups; ++q) goff[(size_t)q * (nb + 1) + b] = slot_count[q];
             const double sc = std::ldexp(1.0, t.level[b]);
@@ -742,12 +753,10 @@ void build_stage_m2l(pkifmm_plan* P, int R) {
                 const int idx = vidx[e];
                 const int q = idx * kM2LGroups / kNumM2L;
                 const int slot = slot_count[q]++;
-                const int64_t p0 = pos[idx]++ * R;
-                for (int r = 0; r < R; ++r) {
-                    in_c[p0 + r] = L.v[e].src * R + r;
-                    out_c[p0 + r] = slot * R + r;
-                    sc_c[p0 + r] = sc;
-                }
+                const int64_t p0 = pos[idx]++;
+                in_c[p0] = L.v[e].src;
+                out_c[p0] = slot;
+                sc_c[p0] = sc;
             }
             for (int q = 0; q < kM2LGroups; ++q)
                 if (slot_count[q] > goff[(size_t)q * (nb + 1) + b]) gtarg[q].push_back(b);
@@ -755,17 +764,20 @@ void build_stage_m2l(pkifmm_plan* P, int R) {
         for (int q = 0; q < kM2LGroups; ++q) goff[(size_t)q * (nb + 1) + nb] = slot_count[q];
         P->g_m2l.assign(kM2LGroups, GemmRange());
         P->m2l_targets.assign(kM2LGroups, {});
-        g.in.reserve(g.in.size() + 8 * (size_t)nv * R);
-        g.out.reserve(g.out.size() + (size_t)nv * R);
-        g.scale.reserve(g.scale.size() + (size_t)nv * R);
+        if ((int64_t)nv * R >= (int64_t)INT32_MAX) throw Error(PKIFMM_ERR_INVALID_ARG, "too many V-list columns");
+        g.in = std::move(in_c);
+        g.out = std::move(out_c);
+        g.scale = std::move(sc_c);
         int max_slots = 1;
         std::vector<int> all_targets;
         for (int q = 0; q < kM2LGroups; ++q) {
             P->g_m2l[q] = range([&] {
                 for (int d = 0; d < kNumM2L; ++d) {
                     if (d * kM2LGroups / kNumM2L != q || per_idx[d + 1] == per_idx[d]) continue;
-                    const int64_t c0 = per_idx[d] * R, nc = (per_idx[d + 1] - per_idx[d]) * R;
-                    add_gemm(g, d, kn, in_c.data() + c0, out_c.data() + c0, sc_c.data() + c0, (size_t)nc);
+                    const int64_t c0 = per_idx[d] * R, c1 = per_idx[d + 1] * R;   // expanded columns
+                    for (int64_t j = c0; j < c1; j += 64)
+                        for (int r0 = 0; r0 < kn; r0 += 64)
+                            g.tiles.push_back(Tile{d, (int)j, (int)std::min<int64_t>(64, c1 - j), r0});
                 }
             });
             P->m2l_targets[q] = {(int)all_targets.size(), (int)gtarg[q].size()};
@@ -794,7 +806,7 @@ void build_work(pkifmm_plan* P, int R) {
 
 void run_gemm(pkifmm_plan* P, const GemmRange& gr, const double* ops, int64_t op_stride, int M, int K,
               const double* B, int64_t ldb, double* C, int64_t ldc, bool acc, hipStream_t s, int nkb = 1,
-              bool allow_split = true) {
+              bool allow_split = true, int rhs = 0) {
     if (gr.ntile == 0) return;
     GemmArgs a{};
     a.ops = ops;
@@ -814,9 +826,37 @@ void run_gemm(pkifmm_plan* P, const GemmRange& gr, const double* ops, int64_t op
     a.out_col = G.col_out.p;
     a.scale = G.col_scale.p;
     a.accumulate = acc ? 1 : 0;
+    a.rhs = rhs;
     // the per-level launches split K (latency-bound, few tiles); M2L never does
     if (allow_split) launch_gemm(a, s, P->split_tmp.p, (int64_t)P->split_tmp.n);
     else launch_gemm(a, s);
+}
+
+// M2L of the mixed form: the same tiles and column lists on the int8 slices of the operators
+// and of the upward densities (sliced once per evaluation, all nbox*R columns)
+void run_gemm_oz(pkifmm_plan* P, const GemmRange& gr, int R, double* C, int64_t ldc, hipStream_t s) {
+    if (gr.ntile == 0) return;
+    const int kp = oz_padded(P->kn);
+    OzArgs a{};
+    a.a_sl = P->m2l_oz.p;
+    a.a_exp = P->m2l_oz_e.p;
+    a.Mp = kp;
+    a.Kp = kp;
+    a.M = P->kn;
+    a.b_sl = P->phi_oz.p;
+    a.b_exp = P->phi_oz_e.p;
+    a.b_slice_stride = (int64_t)P->tree.nbox() * R * kp;
+    a.C = C;
+    a.ldc = ldc;
+    const GemmSet& G = P->gsets[gr.set];
+    a.tiles = G.tiles.p + gr.tile0;
+    a.n_tiles = gr.ntile;
+    a.in_col = G.col_in.p;
+    a.out_col = G.col_out.p;
+    a.scale = G.col_scale.p;
+    a.rhs = R;
+    a.accumulate = 0;
+    launch_gemm_oz(a, s);
 }
 
 void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_surf, int R, bool f32, bool acc_pts,
@@ -933,9 +973,13 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
         // 3. root far field and V-list M2L into the downward check potentials
         if (build) build_stage_m2l(P, R);       // host work while the upward pass runs
         run_gemm(P, P->g_root, P->mroot.p, 0, kn, kn, P->phi_u.p, kn, P->q_d.p, kn, true, s);
+        if (mixed) launch_oz_slice_columns(P->phi_u.p, kn, kn, (int64_t)cols, P->phi_oz.p, P->phi_oz_e.p, s);
         for (int q = 0; q < kM2LGroups; ++q) {
             if (P->g_m2l[q].ntile == 0) continue;
-            run_gemm(P, P->g_m2l[q], P->m2l.p, kk, kn, kn, P->phi_u.p, kn, P->m2l_tmp.p, kn, false, s, 1, false);
+            if (mixed)
+                run_gemm_oz(P, P->g_m2l[q], R, P->m2l_tmp.p, kn, s);
+            else
+                run_gemm(P, P->g_m2l[q], P->m2l.p, kk, kn, kn, P->phi_u.p, kn, P->m2l_tmp.p, kn, false, s, 1, false, R);
             launch_segment_reduce(P->m2l_tmp.p, P->v_goff.p + (size_t)q * (t.nbox() + 1),
                                   P->v_gtargets.p + P->m2l_targets[q].first, P->m2l_targets[q].second, R, kn,
                                   P->q_d.p, s);
@@ -1067,6 +1111,12 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
         } else {
             d_tmp.upload(scaled(u, kInnerHalf, 0.5, 0.5, 0.5), s);
             launch_far_kmat(cfg->kernel, cfg->periodic_mask, d_tmp.p, ns, d_tmp.p, ns, P->mroot.p, kn, nullptr, s);
+        }
+        if (cfg->precision == PKIFMM_MIXED) {   // M2L of the mixed form runs on int8 slices
+            const int kp = oz_padded(kn);
+            P->m2l_oz.ensure((size_t)kNumM2L * kOzSlices * kp * kp);
+            P->m2l_oz_e.ensure((size_t)kNumM2L * kp);
+            launch_oz_slice_operators(P->m2l.p, kNumM2L, kn, kn, P->m2l_oz.p, P->m2l_oz_e.p, s);
         }
         P->err_flag.ensure(1);
         PK_HIP(hipStreamSynchronize(s));
