@@ -97,6 +97,7 @@ struct pkifmm_plan {
     std::string last_error;
     hipStream_t setup_stream = nullptr;
     hipStream_t setup_stream2 = nullptr;        // uploads of the M2L work lists (built on a second host thread)
+    hipStream_t setup_stream3 = nullptr;        // uploads of the near-field work lists (a third host thread)
     hipStream_t near_stream = nullptr;          // near field, concurrent with the end of M2L
     hipStream_t x_stream = nullptr;             // X list, beside the upward pass and M2L
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_xjoin = nullptr;
@@ -676,7 +677,7 @@ void build_stage_near(pkifmm_plan* P, int R) {
                       (segs[sg].kind == 3 ? 2 : 1);
         P->stats.near_pairs = np;
     }
-    hipStream_t s = P->setup_stream;
+    hipStream_t s = P->setup_stream3;
     P->mutual = mutual;
     P->n_slots = n_slots;
     P->n_in = 0;
@@ -909,6 +910,41 @@ void drop_graph(pkifmm_plan* P) {
     P->graph = nullptr;
 }
 
+// A host thread building one stage's work lists on the caller's device.  join() rethrows what
+// the stage threw; the destructor joins (errors then dropped), so an exception elsewhere never
+// leaves the thread running.
+class StageThread {
+  public:
+    template <class F>
+    void start(F f) {
+        int dev = 0;
+        PK_HIP(hipGetDevice(&dev));
+        th_ = std::thread([this, f, dev] {
+            try {
+                PK_HIP(hipSetDevice(dev));
+                f();
+            } catch (...) {
+                err_ = std::current_exception();
+            }
+        });
+    }
+    void join() {
+        if (th_.joinable()) th_.join();
+        if (err_) {
+            std::exception_ptr e = err_;
+            err_ = nullptr;
+            std::rethrow_exception(e);
+        }
+    }
+    ~StageThread() {
+        if (th_.joinable()) th_.join();
+    }
+
+  private:
+    std::thread th_;
+    std::exception_ptr err_;
+};
+
 // Enqueue one evaluation on stream s (no host synchronisation unless `checks`).
 void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* potential, hipStream_t s, bool checks,
                       bool allow_timing, bool build = false) {
@@ -926,7 +962,15 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
             ev.push_back(e);
         };
         auto mark = [&]() { mark_on(s); };
-        if (build) build_stage_tree(P, R);
+        // first evaluation on new points: the M2L and near-field work lists are built on two
+        // host threads (their own upload streams) while this thread builds the tree-pass lists
+        // and enqueues the upward pass; each is joined just before its kernels are enqueued
+        StageThread th_m2l, th_near;
+        if (build) {
+            th_m2l.start([P, R] { build_stage_m2l(P, R); });
+            th_near.start([P, R] { build_stage_near(P, R); });
+            build_stage_tree(P, R);
+        }
         launch_permute_density(density, P->perm.p, n, R, k, P->ds.p, mixed ? P->ds32.p : nullptr, s);
         const int naxes = __builtin_popcount(P->cfg.periodic_mask);
         if (checks && (naxes == 1 || naxes == 2) && !(P->cfg.flags & PKIFMM_SKIP_CHECKS)) {
@@ -971,7 +1015,7 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
         }
         mark();
         // 3. root far field and V-list M2L into the downward check potentials
-        if (build) build_stage_m2l(P, R);       // host work while the upward pass runs
+        th_m2l.join();                          // built while the upward pass was enqueued and ran
         run_gemm(P, P->g_root, P->mroot.p, 0, kn, kn, P->phi_u.p, kn, P->q_d.p, kn, true, s);
         if (mixed) launch_oz_slice_columns(P->phi_u.p, kn, kn, (int64_t)cols, P->phi_oz.p, P->phi_oz_e.p, s);
         for (int q = 0; q < kM2LGroups; ++q) {
@@ -987,7 +1031,7 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
         mark();
         // 4. near field (U lists and the direct W/X entries) on the second stream; it needs only
         // the permuted densities
-        if (build) build_stage_near(P, R);      // host work while M2L runs
+        th_near.join();
         PK_HIP(hipStreamWaitEvent(sn, P->ev_fork, 0));
         mark_on(sn);
         run_p2p(P, P->w_leaf_u, P->pot.p, nullptr, R, mixed, false, sn, false, P->near_grid_cap);
@@ -1053,6 +1097,7 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
         // stage on the caller's stream (a legacy default stream would otherwise order them)
         PK_HIP(hipStreamCreateWithFlags(&P->setup_stream, hipStreamNonBlocking));
         PK_HIP(hipStreamCreateWithFlags(&P->setup_stream2, hipStreamNonBlocking));
+        PK_HIP(hipStreamCreateWithFlags(&P->setup_stream3, hipStreamNonBlocking));
         // non-blocking: no implicit synchronisation with the legacy null stream; default priority
         PK_HIP(hipStreamCreateWithFlags(&P->near_stream, hipStreamNonBlocking));
         PK_HIP(hipStreamCreateWithFlags(&P->x_stream, hipStreamNonBlocking));
@@ -1128,6 +1173,7 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
         if (h) rocblas_destroy_handle(h);
         if (P->setup_stream) (void)hipStreamDestroy(P->setup_stream);
         if (P->setup_stream2) (void)hipStreamDestroy(P->setup_stream2);
+        if (P->setup_stream3) (void)hipStreamDestroy(P->setup_stream3);
         if (P->near_stream) (void)hipStreamDestroy(P->near_stream);
         if (P->x_stream) (void)hipStreamDestroy(P->x_stream);
         if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
@@ -1383,6 +1429,7 @@ int pkifmm_plan_destroy(pkifmm_plan* P) {
     drop_graph(P);
     if (P->setup_stream) (void)hipStreamDestroy(P->setup_stream);
     if (P->setup_stream2) (void)hipStreamDestroy(P->setup_stream2);
+        if (P->setup_stream3) (void)hipStreamDestroy(P->setup_stream3);
     if (P->near_stream) (void)hipStreamDestroy(P->near_stream);
     if (P->x_stream) (void)hipStreamDestroy(P->x_stream);
     if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
