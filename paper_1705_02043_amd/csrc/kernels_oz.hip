@@ -136,8 +136,11 @@ __global__ __launch_bounds__(256) void k_gemm_oz(OzArgs a) {
         s_in[tid] = tid < t.ncol ? a.in_col[e] * a.rhs + (j - e * a.rhs) : -1;
     }
     __syncthreads();
-    // this thread's share of a stage: row/column tid / 4, 16 bytes at (tid % 4) * 16
-    const int sr = tid >> 2, sq = tid & 3;
+    // this thread's share of a stage: 16 bytes at (lane % 4) * 16 of row/column
+    // 16 * wave + 4 * ((lane / 4) % 4) + lane / 16: four consecutive lanes load one row's 64
+    // contiguous bytes, and the 16 lanes of a quarter-wave store rows r, r+4, r+8, r+12, which the
+    // 80-byte row stride places in distinct LDS banks
+    const int sr = 16 * wave + 4 * ((lane >> 2) & 3) + (lane >> 4), sq = lane & 3;
     const int bcol = s_in[sr];
     const int8_t* ap = A + (int64_t)(t.row0 + sr) * a.Kp + sq * 16;
     // a padding column reads column 0 of the slices (in bounds) and is masked to zero

@@ -392,11 +392,12 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
 // leaf points to a box's downward check surface), float64.  A workgroup owns up
 // to 64 surface targets; its 256 threads form 4 groups that sweep interleaved
 // quarters of every source tile, and the four partial sums are added in a
-// fixed order at the end.
-template <int KD>
-__global__ __launch_bounds__(kThreads) void k_p2s(P2PArgs a, int r) {
-    __shared__ double s_x[kThreads], s_y[kThreads], s_z[kThreads], s_d[KD][kThreads];
-    __shared__ double s_red[4][64][KD];
+// fixed order at the end.  RB right-hand sides share each pair's geometry.
+template <int KD, int RB>
+__global__ __launch_bounds__(kThreads) void k_p2s(P2PArgs a, int r0) {
+    constexpr int ND = KD * RB;
+    __shared__ double s_x[kThreads], s_y[kThreads], s_z[kThreads], s_d[ND][kThreads];
+    __shared__ double s_red[4][64][ND];
     const Work w = a.work[blockIdx.x];
     const int kn = KD * a.n_surf;
     const int64_t n = a.n;
@@ -408,8 +409,8 @@ __global__ __launch_bounds__(kThreads) void k_p2s(P2PArgs a, int r) {
     const double tx = (a.box_ix[w.tbox] + 0.5) * th + f * a.usurf[3 * t];
     const double ty = (a.box_iy[w.tbox] + 0.5) * th + f * a.usurf[3 * t + 1];
     const double tz = (a.box_iz[w.tbox] + 0.5) * th + f * a.usurf[3 * t + 2];
-    double acc[KD];
-    for (int c = 0; c < KD; ++c) acc[c] = 0.0;
+    double acc[ND];
+    for (int c = 0; c < ND; ++c) acc[c] = 0.0;
     for (int sg = w.seg0; sg < w.seg1; ++sg) {
         const Seg seg = a.segs[sg];
         const int b = seg.box;
@@ -423,22 +424,26 @@ __global__ __launch_bounds__(kThreads) void k_p2s(P2PArgs a, int r) {
             if (tid < cnt) {
                 const int64_t q = base + c0 + tid;
                 s_x[tid] = a.xs[q]; s_y[tid] = a.xs[n + q]; s_z[tid] = a.xs[2 * n + q];
-                for (int c = 0; c < KD; ++c) s_d[c][tid] = a.ds[((int64_t)r * KD + c) * n + q];
+                for (int c = 0; c < ND; ++c) s_d[c][tid] = a.ds[((int64_t)r0 * KD + c) * n + q];
             }
             __syncthreads();
             for (int q = grp; q < cnt; q += 4) {
-                double d[KD];
-                for (int c = 0; c < KD; ++c) d[c] = s_d[c][q];
-                interact<KD, 1, true, double>(ux - s_x[q], uy - s_y[q], uz - s_z[q], d, acc);
+                double d[ND];
+                for (int c = 0; c < ND; ++c) d[c] = s_d[c][q];
+                interact<KD, RB, true, double>(ux - s_x[q], uy - s_y[q], uz - s_z[q], d, acc);
             }
         }
     }
-    for (int c = 0; c < KD; ++c) s_red[grp][lt][c] = acc[c];
+    for (int c = 0; c < ND; ++c) s_red[grp][lt][c] = acc[c];
     __syncthreads();
-    if (grp == 0 && lt < w.tcount) {
-        double* q = a.out_surf + ((int64_t)w.tbox * a.R + r) * kn + KD * (w.t0 + lt);
-        for (int c = 0; c < KD; ++c) q[c] += ((s_red[0][lt][c] + s_red[1][lt][c]) + s_red[2][lt][c]) + s_red[3][lt][c];
-    }
+    if (grp == 0 && lt < w.tcount)
+        for (int rr = 0; rr < RB; ++rr) {
+            double* q = a.out_surf + ((int64_t)w.tbox * a.R + r0 + rr) * kn + KD * (w.t0 + lt);
+            for (int c = 0; c < KD; ++c) {
+                const int e = KD * rr + c;
+                q[c] += ((s_red[0][lt][e] + s_red[1][lt][e]) + s_red[2][lt][e]) + s_red[3][lt][e];
+            }
+        }
 }
 
 __global__ __launch_bounds__(kThreads) void k_mutual_gather(const double* __restrict__ mpart, int64_t n_slots, int kd,
@@ -490,12 +495,27 @@ void launch_rhs(const P2PArgs& a, hipStream_t s) {
 
 }  // namespace
 
+template <int KD, int RB>
+void launch_p2s_block(const P2PArgs& a, int r0, hipStream_t s) {
+    hipLaunchKernelGGL((k_p2s<KD, RB>), dim3(a.n_work), dim3(kThreads), 0, s, a, r0);
+    PK_HIP(hipGetLastError());
+}
+
 void launch_p2s(const P2PArgs& a, hipStream_t s) {
     if (a.n_work == 0) return;
-    for (int r = 0; r < a.R; ++r) {
-        if (a.kernel == PKIFMM_LAPLACE) hipLaunchKernelGGL((k_p2s<1>), dim3(a.n_work), dim3(kThreads), 0, s, a, r);
-        else hipLaunchKernelGGL((k_p2s<3>), dim3(a.n_work), dim3(kThreads), 0, s, a, r);
-        PK_HIP(hipGetLastError());
+    // right-hand sides in blocks: up to 8 (Laplace) or 4 (Stokes) share one geometry pass
+    for (int r0 = 0; r0 < a.R;) {
+        const int left = a.R - r0;
+        if (a.kernel == PKIFMM_LAPLACE) {
+            if (left >= 8) { launch_p2s_block<1, 8>(a, r0, s); r0 += 8; }
+            else if (left >= 4) { launch_p2s_block<1, 4>(a, r0, s); r0 += 4; }
+            else if (left >= 2) { launch_p2s_block<1, 2>(a, r0, s); r0 += 2; }
+            else { launch_p2s_block<1, 1>(a, r0, s); r0 += 1; }
+        } else {
+            if (left >= 4) { launch_p2s_block<3, 4>(a, r0, s); r0 += 4; }
+            else if (left >= 2) { launch_p2s_block<3, 2>(a, r0, s); r0 += 2; }
+            else { launch_p2s_block<3, 1>(a, r0, s); r0 += 1; }
+        }
     }
 }
 
