@@ -155,6 +155,53 @@ def other_configs(pk, torch, W, steps=3, warmup=1):
     return res
 
 
+def paper_configs(pk, torch, W, ps, steps=2, warmup=1):
+    """The paper's timing workloads (Section 3.5): 97^3 Chebyshev and lognormal
+    points, Stokes, free space / SP / DP / TP, s = 1000, mixed form.  Per (periodicity, p) one
+    plan serves both point sets.  set_points (octree, lists) stands beside the paper's tau_tree;
+    the evaluation covers its tau_N and tau_F together (the far field is folded into the tree)."""
+    res = []
+    names = {0: "free", 1: "SP", 3: "DP", 7: "TP"}
+    for mask in (0, 1, 3, 7):
+        for p in ps:
+            t0 = time.perf_counter()
+            plan = pk.Plan(pk.STOKES, mask, p, 1000, precision=pk.MIXED, flags=pk.PHASE_TIMING)
+            torch.cuda.synchronize()
+            t_plan = time.perf_counter() - t0
+            for kind in ("chebyshev", "lognormal"):
+                pb = W.stokes_paper_points(kind, mask, p)
+                xyz = torch.as_tensor(pb.points, device="cuda")
+                dens = torch.as_tensor(pb.density, device="cuda")
+                out = torch.empty_like(dens)
+                for _ in range(warmup):
+                    plan.set_points(xyz)
+                    plan.evaluate(dens, out=out)
+                torch.cuda.synchronize()
+                plan.stats()
+                t_sp = t_ev = 0.0
+                for _ in range(steps):
+                    a = time.perf_counter()
+                    plan.set_points(xyz)
+                    torch.cuda.synchronize()
+                    b = time.perf_counter()
+                    plan.evaluate(dens, out=out)
+                    torch.cuda.synchronize()
+                    t_sp += b - a
+                    t_ev += time.perf_counter() - b
+                st = plan.stats()
+                rec = {"points": kind, "periodic": names[mask], "p": p, "s": 1000, "n": pb.n,
+                       "ms_set_points": t_sp / steps * 1e3, "ms_evaluate": t_ev / steps * 1e3,
+                       "targets_per_s": pb.n / ((t_sp + t_ev) / steps), "ms_phase": st["ms_phase"],
+                       "plan_create_s": t_plan, "boxes": st["n_boxes"], "depth": st["depth"],
+                       "near_pairs": st["near_pairs"]}
+                res.append(rec)
+                log(f"paper {kind} {names[mask]} p={p}: set_points {rec['ms_set_points']:.1f} ms, "
+                    f"evaluate {rec['ms_evaluate']:.1f} ms")
+                del xyz, dens, out
+            plan.close()
+    return res
+
+
 def cpu_baseline(pb, n_leaves_sample=6):
     """The oracle (plain FP64 CPU KIFMM) on a bounded sample of the same workload."""
     from oracle import kifmm
@@ -196,6 +243,10 @@ def main():
     ap.add_argument("--configs", action="store_true",
                     help="also time the other configurations (DP slab, batched forest, clustered p=12) and add "
                          "them to the line under 'other_configs' (takes several minutes)")
+    ap.add_argument("--paper", default="",
+                    help="comma-separated p values (6..16): also time the paper's 97^3 Chebyshev and "
+                         "lognormal Stokes workloads (free, SP, DP, TP; s = 1000) and add them under "
+                         "'paper_configs'")
     ap.add_argument("--forms", default="fp64,mixed",
                     help="forms to time: 'fp64,mixed' (default) or 'mixed' alone (for counter passes)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -266,6 +317,8 @@ def main():
         rec["accuracy"]["rel_l2_mixed_vs_fp64_gpu"] = float(np.linalg.norm(outmx - out64) / np.linalg.norm(out64))
     if args.configs:
         rec["other_configs"] = other_configs(pk, torch, W)
+    if args.paper:
+        rec["paper_configs"] = paper_configs(pk, torch, W, [int(x) for x in args.paper.split(",")])
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb, (f, sub) = cpu_baseline(pb)

@@ -343,6 +343,13 @@ bool far_step_d(const pkifmm_plan* P) {
     return (P->cfg.flags & PKIFMM_FAR_STEP_D) != 0 && P->cfg.periodic_mask != 0;
 }
 
+// The per-level GEMMs of levels 0 .. kSplitLevels split K over several workgroups (few boxes
+// per problem there: the launches are latency-bound); deeper levels never do, since their
+// launches fill the chip and the partial tiles would cost more than they save.  The choice
+// depends on the level alone, so a problem's summation order (and every result bit) is the
+// same alone and in a batch.
+constexpr int kSplitLevels = 3;
+
 // Stage 1: S2M and X items, per-level and root GEMMs, workspace.
 void build_stage_tree(pkifmm_plan* P, int R) {
     const HostTree& t = P->tree;
@@ -494,7 +501,7 @@ void build_stage_tree(pkifmm_plan* P, int R) {
             if (gr.ntile == 0) return;
             need = std::max<int64_t>(need, (int64_t)gr.ntile * gemm_split_factor(gr.ntile, K) * 64 * 64);
         };
-        for (int lv = 0; lv <= depth; ++lv) {
+        for (int lv = 0; lv <= std::min(depth, kSplitLevels); ++lv) {
             consider(P->g_m2m[lv], 8 * kn);
             consider(P->g_up1[lv], kn); consider(P->g_up2[lv], P->r_up);
             consider(P->g_dn1[lv], kn); consider(P->g_dn2[lv], P->r_dn);
@@ -1009,9 +1016,10 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
         run_p2p(P, P->w_x, nullptr, P->q_x.p, R, false, false, sx, true);
         PK_HIP(hipEventRecord(P->ev_xjoin, sx));
         for (int lv = t.depth; lv >= 0; --lv) {
-            run_gemm(P, P->g_m2m[lv], P->m2m.p, 0, kn, 8 * kn, P->phi_u.p, kn, P->q_u.p, kn, true, s, 8);
-            run_gemm(P, P->g_up1[lv], P->up_Ut.p, 0, P->r_up, kn, P->q_u.p, kn, P->tmp.p, kn, false, s);
-            run_gemm(P, P->g_up2[lv], P->up_VS.p, 0, kn, P->r_up, P->tmp.p, kn, P->phi_u.p, kn, false, s);
+            const bool split = lv <= kSplitLevels;
+            run_gemm(P, P->g_m2m[lv], P->m2m.p, 0, kn, 8 * kn, P->phi_u.p, kn, P->q_u.p, kn, true, s, 8, split);
+            run_gemm(P, P->g_up1[lv], P->up_Ut.p, 0, P->r_up, kn, P->q_u.p, kn, P->tmp.p, kn, false, s, 1, split);
+            run_gemm(P, P->g_up2[lv], P->up_VS.p, 0, kn, P->r_up, P->tmp.p, kn, P->phi_u.p, kn, false, s, 1, split);
         }
         mark();
         // 3. root far field and V-list M2L into the downward check potentials
@@ -1046,9 +1054,11 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
         PK_HIP(hipStreamWaitEvent(s, P->ev_xjoin, 0));
         launch_add_into(P->q_d.p, P->q_x.p, (int64_t)cols * kn, s);
         for (int lv = 0; lv <= t.depth; ++lv) {
-            if (lv >= 1) run_gemm(P, P->g_l2l[lv], P->l2l.p, kk, kn, kn, P->phi_d.p, kn, P->q_d.p, kn, true, s);
-            run_gemm(P, P->g_dn1[lv], P->dn_Ut.p, 0, P->r_dn, kn, P->q_d.p, kn, P->tmp.p, kn, false, s);
-            run_gemm(P, P->g_dn2[lv], P->dn_VS.p, 0, kn, P->r_dn, P->tmp.p, kn, P->phi_d.p, kn, false, s);
+            const bool split = lv <= kSplitLevels;
+            if (lv >= 1)
+                run_gemm(P, P->g_l2l[lv], P->l2l.p, kk, kn, kn, P->phi_d.p, kn, P->q_d.p, kn, true, s, 1, split);
+            run_gemm(P, P->g_dn1[lv], P->dn_Ut.p, 0, P->r_dn, kn, P->q_d.p, kn, P->tmp.p, kn, false, s, 1, split);
+            run_gemm(P, P->g_dn2[lv], P->dn_VS.p, 0, kn, P->r_dn, P->tmp.p, kn, P->phi_d.p, kn, false, s, 1, split);
         }
         mark();
         // 6. W list and L2T (float64: they consume equivalent densities)

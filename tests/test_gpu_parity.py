@@ -226,6 +226,30 @@ def test_full_size_stokes_tp_sampled(precision, tol):
     assert err < tol
 
 
+@pytest.mark.timeout(1100)
+@pytest.mark.parametrize("kind,mask,precision,tol", [("chebyshev", 7, 1, 1e-6), ("chebyshev", 7, 0, STOKES_P8_FP64_TOL),
+                                                     ("lognormal", 3, 1, 1e-6)])
+def test_paper_timing_workloads_sampled(kind, mask, precision, tol):
+    """The paper's timing workloads (97^3 Chebyshev grid, which puts points on every face of the
+    box, and lognormal points), Stokes, p = 8, s = 1000: every target of 3 random leaves against
+    the oracle."""
+    pb = W.stokes_paper_points(kind, mask, p=8)
+    plan, out = _run(pb, precision)
+    f = okifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+    leaves = f.tree.leaves()
+    pick = [leaves[i] for i in sorted(np.random.default_rng(11).choice(len(leaves), 3, replace=False))]
+    sub = f.evaluate(pb.density[0], target_leaves=pick)
+    num = den = 0.0
+    for b, ref in sub.items():
+        idx = f.tree.perm[f.tree.begin[b]:f.tree.end[b]]
+        num += np.sum((out[0][idx] - ref) ** 2)
+        den += np.sum(ref ** 2)
+    err = np.sqrt(num / den)
+    print(f"paper {kind} mask={mask} precision={precision}: sampled rel L2 {err:.3e} "
+          f"({plan.stats()['n_boxes']} boxes)", flush=True)
+    assert err < tol
+
+
 _c3 = {}
 
 

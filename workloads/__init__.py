@@ -113,6 +113,40 @@ def stokes_tp_clustered(n: int = 16_000_000, seed: int = 5, p: int = 12, s: int 
     return Problem(f"stokes_tp_clustered_n{n}", STOKES, TP, p, s, pts, f)
 
 
+def clenshaw_curtis_nodes(m: int = 97) -> np.ndarray:
+    """The m Clenshaw-Curtis (Chebyshev extreme) nodes mapped to [0, 1], endpoints included."""
+    return 0.5 * (1.0 - np.cos(np.pi * np.arange(m) / (m - 1)))
+
+
+def stokes_paper_points(kind: str, mask: int = TP, p: int = 8, s: int = 1000, m: int = 97) -> Problem:
+    """The timing workloads of Section 3.5: m^3 = 912673 points for m = 97,
+    sources = targets, one force per point with components uniform in [-0.5, 0.5), made
+    force-free (mean subtracted) for singly and doubly periodic sums; at most 1000 points per
+    leaf.
+
+    kind = "chebyshev": the tensor grid of Clenshaw-Curtis nodes, the paper's uniform set
+    (forces seed 6).
+    kind = "lognormal": each coordinate drawn from numpy's lognormal(mean=0.2, sigma=0.5) and
+    taken modulo 1 into the unit box, the paper's non-uniform set (how its lognormal samples
+    are placed in the box is not stated; seed 7, points first, then forces).
+    """
+    n = m ** 3
+    if kind == "chebyshev":
+        rng = np.random.default_rng(6)
+        c = clenshaw_curtis_nodes(m)
+        pts = np.stack(np.meshgrid(c, c, c, indexing="ij"), axis=-1).reshape(n, 3)
+    elif kind == "lognormal":
+        rng = np.random.default_rng(7)
+        pts = np.mod(rng.lognormal(0.2, 0.5, (n, 3)), 1.0)
+    else:
+        raise ValueError(kind)
+    f = rng.uniform(-0.5, 0.5, (1, n, 3))
+    naxes = bin(mask).count("1")
+    if naxes in (1, 2):
+        f -= f.mean(axis=1, keepdims=True)
+    return Problem(f"stokes_paper_{kind}_mask{mask}_n{n}", STOKES, mask, p, s, np.ascontiguousarray(pts), f)
+
+
 def madelung_chain(axis: int = 0):
     """Four alternating unit charges on a line along ``axis`` at 1/8, 3/8, 5/8, 7/8."""
     pts = np.full((4, 3), 0.5)
