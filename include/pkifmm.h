@@ -59,10 +59,16 @@ typedef struct pkifmm_plan pkifmm_plan;
 
 /* arithmetic of the evaluation pass */
 #define PKIFMM_FP64 0        /* every step in double precision */
-#define PKIFMM_MIXED 1       /* U-list near field (leaf-to-leaf direct sums) in float32 with
-                                float64 partial-sum accumulation; every quantity that feeds a
-                                check-to-equivalent solve (S2M, X, M2M, M2L, L2L, the root far
-                                field) and every use of an equivalent density (W, L2T) in float64 */
+#define PKIFMM_MIXED 1       /* near field (U lists and direct W/X leaf pairs) in float32 on
+                                exact integer separations, with float64 partial-sum
+                                accumulation; the V-list M2L (Section 2.2) on int8 digit slices
+                                of the operators and upward densities (6 base-2^7 digits each,
+                                products accumulated exactly in int32, recombined in float64:
+                                about 42 significant bits); S2M, X, M2M, L2L, the solves, the
+                                root far field, W and L2T in float64.  Target: 1e-6 relative L2
+                                against the float64 result.  Two points of different leaves
+                                closer than 2^-30 times the larger leaf's edge in every
+                                coordinate are outside this form's range */
 
 /* status codes */
 #define PKIFMM_OK 0
