@@ -173,13 +173,24 @@ void build_lists_host(const HostTree& t, unsigned mask, HostLists& L) {
                     auto it = at[lv].find(morton3(g[0], g[1], g[2]));
                     if (it != at[lv].end()) coll[b].push_back({it->second, {p[0], p[1], p[2]}});
                 }
+        // ordered by (box, shift code): the V lists built from them then come out ordered
+        // (children are numbered in their parents' order), and need no sort below
+        std::sort(coll[b].begin(), coll[b].end(), [](const Col& x, const Col& y) {
+            if (x.box != y.box) return x.box < y.box;
+            return (x.p[0] + 1) * 9 + (x.p[1] + 1) * 3 + (x.p[2] + 1) < (y.p[0] + 1) * 9 + (y.p[1] + 1) * 3 + (y.p[2] + 1);
+        });
     }
     auto mk = [](int a, const int p[3]) { return Entry{a, (int8_t)p[0], (int8_t)p[1], (int8_t)p[2]}; };
     // sort by (source, shift) through a packed 64-bit key (the shift code is lexicographic)
     auto sort_entries = [](std::vector<Entry>& v) {
-        std::vector<int64_t> key(v.size());
-        for (size_t i = 0; i < v.size(); ++i)
+        thread_local std::vector<int64_t> key;   // reused: no allocation per list
+        key.resize(v.size());
+        bool ordered = true;   // strictly increasing: already sorted, no duplicates
+        for (size_t i = 0; i < v.size(); ++i) {
             key[i] = ((int64_t)v[i].src << 8) | ((v[i].sx + 1) * 9 + (v[i].sy + 1) * 3 + (v[i].sz + 1));
+            if (i > 0 && key[i] <= key[i - 1]) ordered = false;
+        }
+        if (ordered) return;
         std::sort(key.begin(), key.end());
         key.erase(std::unique(key.begin(), key.end()), key.end());
         v.resize(key.size());
@@ -207,7 +218,8 @@ void build_lists_host(const HostTree& t, unsigned mask, HostLists& L) {
             sort_entries(V[b]);
         }
         if (!t.is_leaf(b)) continue;
-        std::vector<Col> stack(coll[b].begin(), coll[b].end());
+        thread_local std::vector<Col> stack;
+        stack.assign(coll[b].begin(), coll[b].end());
         while (!stack.empty()) {
             Col c = stack.back();
             stack.pop_back();
