@@ -433,6 +433,32 @@ def test_lists_cover_every_pair_exactly_once(mask, n, s, seed):
     assert t.depth() >= 2 or n < 10
 
 
+@pytest.mark.parametrize("mask,n,s,seed", [(0, 400, 6, 41), (7, 400, 6, 42), (3, 300, 5, 43), (1, 300, 5, 44)])
+def test_direct_pair_separations_fit_twice_the_larger_edge(mask, n, s, seed):
+    """The float32 near field forms every separation of a direct pair (U, and the W/X pairs
+    taken through points) as an integer in units of 2^-29 H, H the larger of the two boxes'
+    edges, and relies on |d| <= 2H per component (so |d| <= 2^30 units) and on the centre
+    difference |c_B - c_A - p| <= 1.25 H.  Both hold for every U, W and X entry of adaptive
+    trees (graded and clustered points, every periodicity)."""
+    rng = np.random.default_rng(seed)
+    pts = np.concatenate([rng.random((n // 2, 3)) ** 3,
+                          np.mod(0.3 + 0.01 * rng.standard_normal((n - n // 2, 3)), 1.0)])
+    u = otree.wrap(pts, mask)
+    t = otree.build_tree(u, s)
+    lists = otree.build_lists(t, mask)
+    assert t.depth() >= 4
+    worst_d = worst_c = 0.0
+    for name in ("U", "W", "X"):
+        for b, entries in getattr(lists, name).items():
+            for (a, p) in entries:
+                H = max(t.edge(a), t.edge(b))
+                dc = np.abs(t.centre(b) - t.centre(a) - np.array(p, dtype=float))
+                dmax = dc + 0.5 * (t.edge(a) + t.edge(b))
+                worst_d = max(worst_d, float(np.max(dmax)) / H)
+                worst_c = max(worst_c, float(np.max(dc)) / H)
+    assert worst_d <= 2.0 and worst_c <= 1.25, (worst_d, worst_c)
+
+
 def test_root_leaf_lists():
     t = otree.build_tree(np.array([[0.1, 0.2, 0.3], [0.6, 0.7, 0.8]]), 5)
     lists = otree.build_lists(t, 7)
