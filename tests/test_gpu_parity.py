@@ -199,6 +199,20 @@ def test_boundary_coordinates_and_errors():
     assert e.value.status == pk.ERR_INCOMPATIBLE
 
 
+@pytest.mark.parametrize("precision", [1, 0])
+def test_power_of_two_scaling_is_exact(precision):
+    """Scaling a right-hand side by 2^k scales every float operation and, in the mixed form,
+    only the column exponents of the int8 M2L digits: the output scales bitwise exactly.  A zero
+    right-hand side gives exact zeros (zero columns take exponent 0 and zero digits)."""
+    pb = W.stokes_tp_uniform(n=20000, seed=36, p=8, s=600)
+    d = pb.density[0]
+    dens = np.stack([d, d * 2.0 ** 40, d * 2.0 ** -40, np.zeros_like(d)])
+    _, out = _run(pb, precision, density=dens)
+    assert np.array_equal(out[1], out[0] * 2.0 ** 40)
+    assert np.array_equal(out[2], out[0] * 2.0 ** -40)
+    assert not np.any(out[3])
+
+
 def test_repeat_is_bitwise_deterministic():
     pb = W.stokes_tp_uniform(n=30000, seed=27, p=6, s=400)
     plan, a = _run(pb, 1)
