@@ -254,8 +254,8 @@ def main():
                          "to calibrate rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the distributed design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(a problem is evaluated on one device); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1705_02043_amd as pk
