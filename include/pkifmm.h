@@ -68,7 +68,10 @@ typedef struct pkifmm_plan pkifmm_plan;
                                 root far field, W and L2T in float64.  Target: 1e-6 relative L2
                                 against the float64 result.  Two points of different leaves
                                 closer than 2^-30 times the larger leaf's edge in every
-                                coordinate are outside this form's range */
+                                coordinate are outside this form's range, and so are density
+                                magnitudes outside about 1e-28 ... 1e29: the near field rounds
+                                densities to float32 and its terms reach 2^-31 ... 2^31 times
+                                them (PKIFMM_FP64 has neither limit) */
 
 /* status codes */
 #define PKIFMM_OK 0
