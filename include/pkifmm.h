@@ -189,7 +189,10 @@ int pkifmm_set_points_batch(pkifmm_plan *plan, int n_problems, const int64_t *co
  * unless the SP/DP neutrality check runs (it reads one reduction back).  The
  * first evaluation after set_points also builds the work lists on the host,
  * stage by stage while the previous stage's kernels run.  The output is float64 in every
- * precision mode.
+ * precision mode.  Densities are not checked: a non-finite density makes non-finite
+ * potentials wherever its terms reach.  density and potential may be the same
+ * buffer (the first kernel reads every density into library storage, the last writes
+ * the potentials); partly overlapping ranges are not supported.
  * Errors: NO_POINTS, INVALID_ARG, INCOMPATIBLE, OOM, HIP.
  */
 int pkifmm_evaluate(pkifmm_plan *plan, int n_rhs, const double *density, double *potential,

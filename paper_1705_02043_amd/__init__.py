@@ -165,17 +165,28 @@ class Plan:
         self.n = xyz.shape[0]
 
     def evaluate(self, density, out=None, stream=None):
-        """density: float64 CUDA [R, n, k] (or [n, k]); returns potentials of the same shape."""
+        """density: float64 CUDA [R, n, k] (or [n, k]); returns potentials of the same shape.
+
+        out, if given, is a contiguous float64 CUDA tensor of the density's shape; it may be the
+        density tensor itself (the pass reads every density before it writes a potential)."""
         import torch
+        if density.dim() not in (2, 3):
+            raise ValueError("density must be [n, k] or [R, n, k]")
         squeeze = density.dim() == 2
         d = density[None] if squeeze else density
-        assert d.is_cuda and d.dtype == torch.float64 and d.shape[1] == self.n and d.shape[2] == self.k
+        if not (d.is_cuda and d.dtype == torch.float64 and d.shape[1] == self.n and d.shape[2] == self.k):
+            raise ValueError(f"density must be float64 on the GPU with shape [R, {self.n}, {self.k}]")
         d = d.contiguous()
         if out is None:
-            out = torch.empty_like(d)
+            res = torch.empty_like(d)
+        else:
+            if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+                    and tuple(out.shape) == tuple(density.shape)):
+                raise ValueError("out must be a contiguous float64 GPU tensor of the density's shape")
+            res = out[None] if squeeze else out
         _check(lib().pkifmm_evaluate(self._h, d.shape[0], ctypes.c_void_p(d.data_ptr()),
-                                     ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), self._h)
-        return out[0] if squeeze else out
+                                     ctypes.c_void_p(res.data_ptr()), _stream_ptr(stream)), self._h)
+        return res[0] if squeeze else res
 
     def stats(self) -> dict:
         st = pkifmm_stats()

@@ -213,6 +213,35 @@ def test_power_of_two_scaling_is_exact(precision):
     assert not np.any(out[3])
 
 
+def test_in_place_evaluation_and_out_validation():
+    """density and potential may be one buffer, eagerly and in a captured graph (the pass reads
+    every density into library storage before it writes a potential); an `out` of the wrong
+    shape or layout is refused on the host before anything is enqueued."""
+    pk = _pk()
+    pb = W.stokes_tp_uniform(n=20000, seed=38, p=6, s=300)
+    plan, ref = _run(pb, 1)
+    buf = _dev(pb.density)
+    res = plan.evaluate(buf, out=buf)
+    torch.cuda.synchronize()
+    assert res.data_ptr() == buf.data_ptr()
+    assert np.array_equal(buf.cpu().numpy(), ref)
+    g = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=1, flags=pk.GRAPH)
+    g.set_points(_dev(pb.points))
+    buf = _dev(pb.density)
+    for i in range(3):                               # capture, then replays on refilled input
+        g.evaluate(buf, out=buf)
+        torch.cuda.synchronize()
+        assert np.array_equal(buf.cpu().numpy(), ref), i
+        buf.copy_(_dev(pb.density))
+    dens = _dev(pb.density)
+    n = pb.n
+    for bad in (torch.empty(1, n - 1, 3, dtype=torch.float64, device="cuda"),
+                torch.empty(1, 3, n, dtype=torch.float64, device="cuda").transpose(1, 2),
+                torch.empty(1, n, 3, dtype=torch.float32, device="cuda")):
+        with pytest.raises(ValueError):
+            plan.evaluate(dens, out=bad)
+
+
 def test_repeat_is_bitwise_deterministic():
     pb = W.stokes_tp_uniform(n=30000, seed=27, p=6, s=400)
     plan, a = _run(pb, 1)
