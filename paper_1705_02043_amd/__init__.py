@@ -184,6 +184,13 @@ class Plan:
                     and tuple(out.shape) == tuple(density.shape)):
                 raise ValueError("out must be a contiguous float64 GPU tensor of the density's shape")
             res = out[None] if squeeze else out
+        if stream is not None:
+            # the pass runs on `stream`: it starts after the work queued so far on torch's current
+            # stream (a contiguous copy made above included), and torch must not recycle that copy
+            # or an output allocated here until `stream` has used them
+            stream.wait_stream(torch.cuda.current_stream())
+            d.record_stream(stream)
+            res.record_stream(stream)
         _check(lib().pkifmm_evaluate(self._h, d.shape[0], ctypes.c_void_p(d.data_ptr()),
                                      ctypes.c_void_p(res.data_ptr()), _stream_ptr(stream)), self._h)
         return res[0] if squeeze else res

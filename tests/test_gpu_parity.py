@@ -233,6 +233,14 @@ def test_in_place_evaluation_and_out_validation():
         torch.cuda.synchronize()
         assert np.array_equal(buf.cpu().numpy(), ref), i
         buf.copy_(_dev(pb.density))
+    # a non-contiguous density on a side stream: the binding's contiguous copy is ordered before
+    # the pass and kept alive for it
+    side = torch.cuda.Stream()
+    nc = _dev(np.ascontiguousarray(pb.density.transpose(0, 2, 1))).transpose(1, 2)
+    assert not nc.is_contiguous()
+    res = plan.evaluate(nc, stream=side)
+    side.synchronize()
+    assert np.array_equal(res.cpu().numpy(), ref)
     dens = _dev(pb.density)
     n = pb.n
     for bad in (torch.empty(1, n - 1, 3, dtype=torch.float64, device="cuda"),
