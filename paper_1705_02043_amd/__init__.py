@@ -114,6 +114,11 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _check_points(torch, xyz):
+    if not (xyz.is_cuda and xyz.dtype == torch.float64 and xyz.dim() == 2 and xyz.shape[1] == 3):
+        raise ValueError("xyz must be a float64 GPU tensor of shape [n, 3]")
+
+
 class Plan:
     """One (kernel, periodicity, p, s, precision) set of operators, a point set and its tree."""
 
@@ -146,7 +151,7 @@ class Plan:
     def set_points(self, xyz, stream=None):
         """xyz: torch float64 CUDA tensor [n, 3] (input order)."""
         import torch
-        assert xyz.is_cuda and xyz.dtype == torch.float64 and xyz.dim() == 2 and xyz.shape[1] == 3
+        _check_points(torch, xyz)
         xyz = xyz.contiguous()
         _check(lib().pkifmm_set_points(self._h, xyz.shape[0], ctypes.c_void_p(xyz.data_ptr()),
                                        _stream_ptr(stream)), self._h)
@@ -156,9 +161,11 @@ class Plan:
         """counts: point count of each problem; xyz: float64 CUDA [sum(counts), 3], problems packed."""
         import numpy as np
         import torch
-        assert xyz.is_cuda and xyz.dtype == torch.float64 and xyz.dim() == 2 and xyz.shape[1] == 3
-        c = np.ascontiguousarray(counts, dtype=np.int64)
-        assert int(c.sum()) == xyz.shape[0]
+        _check_points(torch, xyz)
+        c = np.ascontiguousarray(counts, dtype=np.int64).reshape(-1)
+        # the library reads sum(counts) rows of xyz: a mismatch would read past the tensor
+        if np.any(c < 0) or int(c.sum()) != xyz.shape[0]:
+            raise ValueError(f"counts must be non-negative and sum to the {xyz.shape[0]} rows of xyz")
         xyz = xyz.contiguous()
         _check(lib().pkifmm_set_points_batch(self._h, len(c), c.ctypes.data, ctypes.c_void_p(xyz.data_ptr()),
                                              _stream_ptr(stream)), self._h)

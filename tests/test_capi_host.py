@@ -64,3 +64,30 @@ def test_host_topology_matches_oracle(mask, n, s, seed):
         for b in range(t.nbox):
             got = [(int(e[0]), (int(e[1]), int(e[2]), int(e[3]))) for e in ent[off[b]:off[b + 1]]]
             assert got == list(ref.get(b, [])), (which, b)
+
+
+class _DeviceLike:
+    """Stands in for a float64 GPU tensor of n rows in the binding's host-side checks."""
+
+    def __init__(self, n):
+        import torch
+        self.is_cuda, self.dtype, self.shape = True, torch.float64, (n, 3)
+
+    def dim(self):
+        return 2
+
+
+def test_binding_refuses_point_arguments_before_any_library_call():
+    """The library reads sum(counts) rows of xyz and cannot see the tensor's length: the binding
+    refuses a mismatch (and host tensors, and negative counts) before it calls the library."""
+    import torch
+    plan = pk.Plan.__new__(pk.Plan)          # no library handle: a call that got through would fail
+    plan._h = None
+    with pytest.raises(ValueError):
+        plan.set_points(torch.zeros(4, 3, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        plan.set_points_batch([3, 4], _DeviceLike(10))
+    with pytest.raises(ValueError):
+        plan.set_points_batch([-1, 11], _DeviceLike(10))
+    with pytest.raises(ValueError):
+        plan.set_points_batch([5, 5], torch.zeros(10, 3, dtype=torch.float32))
