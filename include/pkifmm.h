@@ -152,6 +152,9 @@ int pkifmm_config_default(pkifmm_config *cfg);
  * periodic root operator K^{P,F} over images |p|_inf >= 2.  Runs on the
  * current HIP device; blocking.  *out receives a plan owned by the caller
  * (release with pkifmm_plan_destroy).
+ * Errors (*out is then NULL): INVALID_ARG (NULL argument, a field out of range or
+ * unknown flag bits), NUMERICS (an operator failed its backward-error self-check),
+ * OOM, HIP.
  */
 int pkifmm_plan_create(const pkifmm_config *cfg, pkifmm_plan **out);
 
@@ -200,7 +203,8 @@ int pkifmm_evaluate(pkifmm_plan *plan, int n_rhs, const double *density, double 
 
 /* Tree and list sizes of the current points and the last call timings.  With
  * PKIFMM_PHASE_TIMING this waits for the recorded events of every evaluation since
- * the previous call, reports their per-phase averages and starts a new window. */
+ * the previous call, reports their per-phase averages and starts a new window.
+ * Errors: INVALID_ARG (NULL argument), HIP (waiting for the events). */
 int pkifmm_get_stats(pkifmm_plan *plan, pkifmm_stats *out);
 
 /*
@@ -210,6 +214,7 @@ int pkifmm_get_stats(pkifmm_plan *plan, pkifmm_stats *out);
  * Boxes are numbered level by level, in Morton order within a level (for a
  * batch: level by level, problems in order within a level, Morton order
  * within a problem; begin/end index the packed points).
+ * Errors: INVALID_ARG (NULL plan), NO_POINTS, HIP (copying the permutation).
  */
 int pkifmm_get_tree(const pkifmm_plan *plan, int64_t *perm, int32_t *boxes);
 
@@ -219,6 +224,7 @@ int pkifmm_get_tree(const pkifmm_plan *plan, int64_t *perm, int32_t *boxes);
  *   offsets [nbox + 1] int64 (CSR over boxes; boxes without such a list are empty)
  *   entries [offsets[nbox]][4] int32: source box, shift x, shift y, shift z
  * Call with entries = NULL to obtain offsets (and so the size) first.
+ * Errors: INVALID_ARG (NULL plan or offsets, unknown `which`), NO_POINTS.
  */
 int pkifmm_get_list(const pkifmm_plan *plan, char which, int64_t *offsets, int32_t *entries);
 
@@ -233,6 +239,8 @@ int pkifmm_get_list(const pkifmm_plan *plan, char which, int64_t *offsets, int32
  *   offsets:     NULL or host [n_boxes + 1] int64
  *   entries:     NULL or host [offsets[n_boxes]][4] int32 (same rows as pkifmm_get_list)
  * Call first with the arrays NULL to size them.
+ * Errors: INVALID_ARG (NULL n_boxes, n < 0, max_pts_per_leaf < 1, NULL keys with
+ * n > 0, mask bits above 7, unknown `which`), OOM.
  */
 int pkifmm_host_topology(const uint64_t *sorted_keys, int64_t n, int max_pts_per_leaf, unsigned periodic_mask,
                          char which, int64_t *n_boxes, int32_t *boxes, int64_t *offsets, int32_t *entries);
