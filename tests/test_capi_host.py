@@ -91,3 +91,16 @@ def test_binding_refuses_point_arguments_before_any_library_call():
         plan.set_points_batch([-1, 11], _DeviceLike(10))
     with pytest.raises(ValueError):
         plan.set_points_batch([5, 5], torch.zeros(10, 3, dtype=torch.float32))
+
+
+def test_binding_refuses_density_arguments_before_any_library_call():
+    """evaluate refuses a density that is not a float64 GPU tensor of shape [R, n, k] (or [n, k])
+    before it calls the library: the library reads R * n * k values and cannot see the tensor."""
+    import torch
+    plan = pk.Plan.__new__(pk.Plan)
+    plan._h, plan.n, plan.k = None, 10, 3
+    for bad in (torch.zeros(1, 10, 3, dtype=torch.float64),              # host memory
+                torch.zeros(10, dtype=torch.float64),                    # wrong rank
+                torch.zeros(2, 1, 10, 3, dtype=torch.float64)):          # wrong rank
+        with pytest.raises(ValueError):
+            plan.evaluate(bad)
