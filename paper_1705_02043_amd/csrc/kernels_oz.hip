@@ -9,8 +9,9 @@
 // accumulator; the S diagonals are converted to float64 and added smallest first.  The only
 // approximation is the truncation of the digit expansions (about 2^-7S of a row's largest
 // entry times a column's largest entry per term), so the rounding of a float32 or bf16 GEMM
-// never enters: it is the exact-integer splitting of Ozaki et al. applied to the M2L
-// translations.  The float64 form keeps its float64 GEMM.
+// never enters: it is the exact-integer splitting of Ozaki et al. applied to the V-list M2L
+// translations (Section 2.2; one operator per offset, shared by every level and periodic
+// shift).  The float64 form keeps its float64 GEMM.
 //
 // Layouts (int8): operator slices [op][S][Mp][Kp], row-major, K contiguous; column slices
 // [S][col][Kp].  Mp and Kp are kn rounded up to 64 and the padding is zero, so the GEMM has no
