@@ -66,18 +66,21 @@ typedef struct pkifmm_plan pkifmm_plan;
                                 products accumulated exactly in int32, recombined in float64:
                                 about 42 significant bits); S2M, X, M2M, L2L, the solves, the
                                 root far field, W and L2T in float64.  Target: 1e-6 relative L2
-                                against the float64 result.  Two points of different leaves
-                                closer than 2^-30 times the larger leaf's edge in every
-                                coordinate are outside this form's range, and so are density
-                                magnitudes outside about 1e-28 ... 1e29: the near field rounds
-                                densities to float32 and its terms reach 2^-31 ... 2^31 times
-                                them (PKIFMM_FP64 has neither limit) */
+                                against the float64 result.  Points are resolved to 2^-29 of
+                                their leaf's edge: two points closer than that in every
+                                coordinate may meet as coincident points (contributing nothing
+                                to each other; pkifmm_set_points detects such inputs and guards
+                                every pair then).  Density magnitudes outside about
+                                1e-28 ... 1e29 are outside this form's range: the near field
+                                rounds densities to float32 and its terms reach 2^-31 ... 2^31
+                                times them (PKIFMM_FP64 has neither limit) */
 
 /* status codes */
 #define PKIFMM_OK 0
 #define PKIFMM_ERR_INVALID_ARG -1
 #define PKIFMM_ERR_OUT_OF_BOX -2     /* a coordinate on a non-periodic axis outside [0, L], or not finite */
-#define PKIFMM_ERR_INCOMPATIBLE -3   /* SP or DP input with a non-zero net density */
+#define PKIFMM_ERR_INCOMPATIBLE -3   /* SP or DP input with a non-zero net density: |sum phi| > 1e-12 sum |phi|
+                                        for some problem, right-hand side and component */
 #define PKIFMM_ERR_UNSUPPORTED -4    /* kernel x periodicity without a far-field operator (none at present) */
 #define PKIFMM_ERR_OOM -5
 #define PKIFMM_ERR_HIP -6
@@ -140,6 +143,9 @@ typedef struct {
                                     unless a check synchronised) */
     int n_timed;                 /* evaluations averaged in ms_phase (PKIFMM_PHASE_TIMING) */
     double ms_phase[PKIFMM_NUM_PHASES];   /* average device time per phase, HIP events */
+    int close_points;            /* mixed form: 1 if pkifmm_set_points found points of different
+                                    leaves or images closer than 2^-27 L in every coordinate (every
+                                    near-field pair then guards zero separations), else 0 */
 } pkifmm_stats;
 
 /* Fill `cfg` with defaults: Laplace, free space, p = 8, s = 64, FP64, L = 1. */
@@ -163,7 +169,12 @@ int pkifmm_plan_create(const pkifmm_config *cfg, pkifmm_plan **out);
  * the periodic U/V/W/X lists.
  *   xyz: device, [n][3] float64, row-major, n >= 0 (copied; may be freed
  *        after the call returns).
- * Synchronises `stream` (the tree topology is built on the host).
+ * Waits for the plan's last evaluation to finish (on whatever stream it ran) and
+ * synchronises `stream` (the tree topology is built on the host).  In the mixed form it
+ * also looks for points of different leaves, or a point and another point's periodic
+ * image, closer than 2^-27 L in every coordinate; if there are any, every near-field
+ * segment guards zero separations (such points then meet as coincident points, at the
+ * cost of one instruction per pair).
  * Errors: OUT_OF_BOX (nothing is kept), INVALID_ARG, OOM, HIP.
  */
 int pkifmm_set_points(pkifmm_plan *plan, int64_t n, const double *xyz, void *stream);
@@ -191,7 +202,10 @@ int pkifmm_set_points_batch(pkifmm_plan *plan, int n_problems, const int64_t *co
  * completion of `stream` covers all of it); the call returns after enqueueing
  * unless the SP/DP neutrality check runs (it reads one reduction back).  The
  * first evaluation after set_points also builds the work lists on the host,
- * stage by stage while the previous stage's kernels run.  The output is float64 in every
+ * stage by stage while the previous stage's kernels run.  Each call is ordered on the device
+ * after the plan's previous evaluation, also when that ran on another stream; a call with a
+ * different n_rhs than the previous one first waits on the host for it to finish (its work
+ * lists are rebuilt).  The output is float64 in every
  * precision mode.  Densities are not checked: a non-finite density makes non-finite
  * potentials wherever its terms reach.  density and potential may be the same
  * buffer (the first kernel reads every density into library storage, the last writes

@@ -48,7 +48,8 @@ class pkifmm_stats(ctypes.Structure):
                 ("near_pairs", ctypes.c_int64),
                 ("svd_rank_up", ctypes.c_int), ("svd_rank_down", ctypes.c_int),
                 ("ms_set_points", ctypes.c_double), ("ms_evaluate", ctypes.c_double),
-                ("n_timed", ctypes.c_int), ("ms_phase", ctypes.c_double * 5)]
+                ("n_timed", ctypes.c_int), ("ms_phase", ctypes.c_double * 5),
+                ("close_points", ctypes.c_int)]
 
 PHASES = ["near", "up", "m2l", "down", "leaf"]
 
@@ -153,6 +154,8 @@ class Plan:
         import torch
         _check_points(torch, xyz)
         xyz = xyz.contiguous()
+        if stream is not None:   # the points (or their contiguous copy) come from torch's current stream
+            stream.wait_stream(torch.cuda.current_stream())
         _check(lib().pkifmm_set_points(self._h, xyz.shape[0], ctypes.c_void_p(xyz.data_ptr()),
                                        _stream_ptr(stream)), self._h)
         self.n = xyz.shape[0]
@@ -167,6 +170,8 @@ class Plan:
         if np.any(c < 0) or int(c.sum()) != xyz.shape[0]:
             raise ValueError(f"counts must be non-negative and sum to the {xyz.shape[0]} rows of xyz")
         xyz = xyz.contiguous()
+        if stream is not None:   # the library synchronises `stream` before it returns
+            stream.wait_stream(torch.cuda.current_stream())
         _check(lib().pkifmm_set_points_batch(self._h, len(c), c.ctypes.data, ctypes.c_void_p(xyz.data_ptr()),
                                              _stream_ptr(stream)), self._h)
         self.n = xyz.shape[0]

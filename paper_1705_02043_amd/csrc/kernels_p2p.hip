@@ -41,6 +41,7 @@
 // record (coordinates and densities) per source, so that the rotated sweep reads every step
 // at a constant offset from one address per lane (no index arithmetic in the inner loop).
 #include <climits>
+#include <type_traits>
 
 #include "launch.h"
 
@@ -65,13 +66,24 @@ __device__ __forceinline__ double rsq(double x) {
     return fma(0.5 * y, e, y);
 }
 
-// K(d) applied to RB densities; GUARD drops a zero separation.  Only a leaf's own
-// segment can hold one (coincident points share a leaf; a point never meets its
-// own image), so the guard is compiled in only for that segment.
+// 1/|d| from r2 = |d|^2; with GUARD, 0 for a zero separation (a pair that contributes
+// nothing).  Float separations are integers (the mixed form's units), so a non-zero r2 is at
+// least 1 and rsq(r2) <= 1 <= r2: min(rsq(r2), r2) is rsq(r2) there and 0 at r2 = 0 (where
+// rsq gives +inf), one instruction.  A zero separation occurs in a leaf's own segment
+// (coincident points share a leaf, and a point never meets its own image exactly in float64),
+// so only that segment is guarded, unless set-up found points of different leaves or images
+// so close that their integer positions may coincide (P2PArgs::guard_all): then every
+// segment of the mixed form is, and such points meet as coincident points.
+template <bool GUARD>
+__device__ __forceinline__ float rinv(float r2) { return GUARD ? fminf(rsq(r2), r2) : rsq(r2); }
+template <bool GUARD>
+__device__ __forceinline__ double rinv(double r2) { return GUARD ? (r2 > 0.0 ? rsq(r2) : 0.0) : rsq(r2); }
+
+// K(d) applied to RB densities; with GUARD a zero separation contributes nothing.
 template <int KD, int RB, bool GUARD, typename T>
 __device__ __forceinline__ void interact(T dx, T dy, T dz, const T* d, T* acc) {
     T r2 = dx * dx + dy * dy + dz * dz;
-    T ri = GUARD ? (r2 > T(0) ? rsq(r2) : T(0)) : rsq(r2);
+    T ri = rinv<GUARD>(r2);
     if constexpr (KD == 1) {
 #pragma unroll
         for (int q = 0; q < RB; ++q) acc[q] += d[q] * ri;
@@ -89,11 +101,11 @@ __device__ __forceinline__ void interact(T dx, T dy, T dz, const T* d, T* acc) {
 }
 
 // K(d) applied both ways: fs (the source's density) into acc_t, ft (the target's) into acc_s.
-// Only used between different leaves, where no separation is zero.
-template <int KD, typename T>
+// Only used between different leaves; GUARD as for interact.
+template <int KD, bool GUARD, typename T>
 __device__ __forceinline__ void interact_both(T dx, T dy, T dz, const T* fs, T* acc_t, const T* ft, T* acc_s) {
     T r2 = dx * dx + dy * dy + dz * dz;
-    T ri = rsq(r2);
+    T ri = rinv<GUARD>(r2);
     if constexpr (KD == 1) {
         acc_t[0] += fs[0] * ri;
         acc_s[0] += ft[0] * ri;
@@ -296,43 +308,52 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
             if constexpr (RB == 1) {
                 if (seg.kind == 3) {
                     const int lane = tid & 63, wv = tid >> 6;
-                    for (int g0 = 0; g0 < cnt; g0 += 64) {
-                        const int gs = 2 * g0;              // slot of the group's first copy
-                        for (int h = 0; h < 64; h += 32) {
-                            T part[kTPT][KD];
-                            for (int j = 0; j < kTPT; ++j)
-                                for (int c = 0; c < KD; ++c) part[j][c] = T(0);
-                            const int q0 = gs + lane + h;   // this lane's source at step 0 of the half
-                            double* dacc = &s_dacc[wv][0][lane + h];
-#pragma unroll
-                            for (int jj = 0; jj < 32; ++jj) {
-                                const int q = q0 + jj;
-                                T d[KD], cs[KD];
-                                C sx, sy, sz;
-                                get(q, sx, sy, sz, d);
-                                for (int c = 0; c < KD; ++c) cs[c] = T(0);
+                    auto sweep = [&](auto guard) {
+                        constexpr bool G = decltype(guard)::value;
+                        for (int g0 = 0; g0 < cnt; g0 += 64) {
+                            const int gs = 2 * g0;              // slot of the group's first copy
+                            for (int h = 0; h < 64; h += 32) {
+                                T part[kTPT][KD];
                                 for (int j = 0; j < kTPT; ++j)
-                                    interact_both<KD, T>(sep<MIXED>(ux[j], sx), sep<MIXED>(uy[j], sy),
-                                                         sep<MIXED>(uz[j], sz), d, part[j], dt[j], cs);
-                                for (int c = 0; c < KD; ++c)
-                                    __hip_atomic_fetch_add(dacc + c * 128 + jj, (double)cs[c], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+                                    for (int c = 0; c < KD; ++c) part[j][c] = T(0);
+                                const int q0 = gs + lane + h;   // this lane's source at step 0 of the half
+                                double* dacc = &s_dacc[wv][0][lane + h];
+#pragma unroll
+                                for (int jj = 0; jj < 32; ++jj) {
+                                    const int q = q0 + jj;
+                                    T d[KD], cs[KD];
+                                    C sx, sy, sz;
+                                    get(q, sx, sy, sz, d);
+                                    for (int c = 0; c < KD; ++c) cs[c] = T(0);
+                                    for (int j = 0; j < kTPT; ++j)
+                                        interact_both<KD, G, T>(sep<MIXED>(ux[j], sx), sep<MIXED>(uy[j], sy),
+                                                                sep<MIXED>(uz[j], sz), d, part[j], dt[j], cs);
+                                    for (int c = 0; c < KD; ++c)
+                                        __hip_atomic_fetch_add(dacc + c * 128 + jj, (double)cs[c], __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_WAVEFRONT);
+                                }
+                                for (int j = 0; j < kTPT; ++j)
+                                    for (int c = 0; c < KD; ++c) acc[j][c] += (double)part[j][c] * inv_u;
                             }
-                            for (int j = 0; j < kTPT; ++j)
-                                for (int c = 0; c < KD; ++c) acc[j][c] += (double)part[j][c] * inv_u;
+                            __syncthreads();
+                            if (tid < min(64, cnt - g0))
+                                for (int c = 0; c < KD; ++c) {
+                                    double v = 0.0;
+                                    for (int u = 0; u < NW; ++u) v += s_dacc[u][c][tid] + s_dacc[u][c][tid + 64];
+                                    a.mpart[(int64_t)c * a.n_slots + seg.slot + c0 + g0 + tid] = v * inv_u;
+                                }
+                            __syncthreads();
+                            // each lane clears its own two slots; every add of the next group follows
+                            // in program order
+                            for (int c = 0; c < KD; ++c) { s_dacc[wv][c][lane] = 0.0; s_dacc[wv][c][lane + 64] = 0.0; }
+                            __asm__ volatile("" ::: "memory");
                         }
-                        __syncthreads();
-                        if (tid < min(64, cnt - g0))
-                            for (int c = 0; c < KD; ++c) {
-                                double v = 0.0;
-                                for (int u = 0; u < NW; ++u) v += s_dacc[u][c][tid] + s_dacc[u][c][tid + 64];
-                                a.mpart[(int64_t)c * a.n_slots + seg.slot + c0 + g0 + tid] = v * inv_u;
-                            }
-                        __syncthreads();
-                        // each lane clears its own two slots; every add of the next group follows
-                        // in program order
-                        for (int c = 0; c < KD; ++c) { s_dacc[wv][c][lane] = 0.0; s_dacc[wv][c][lane + 64] = 0.0; }
-                        __asm__ volatile("" ::: "memory");
+                    };
+                    if constexpr (MIXED) {
+                        if (a.guard_all) sweep(std::true_type{});
+                        else sweep(std::false_type{});
+                    } else {
+                        sweep(std::false_type{});
                     }
                     continue;
                 }
@@ -347,7 +368,7 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
                         T d[ND];
                         C sx, sy, sz;
                         get(slot_of<RB>(q), sx, sy, sz, d);
-                        if (self_seg) {
+                        if (self_seg || a.guard_all) {
                             for (int j = 0; j < kTPT; ++j)
                                 interact<KD, RB, true, T>(sep<MIXED>(ux[j], sx), sep<MIXED>(uy[j], sy),
                                                           sep<MIXED>(uz[j], sz), d, part[j]);
@@ -474,6 +495,9 @@ __global__ __launch_bounds__(kThreads) void k_mutual_gather(const double* __rest
 
 template <int KD, bool MIXED, int RB>
 void launch_block(const P2PArgs& a, int r0, hipStream_t s) {
+    // every launch of a right-hand-side block takes the item list from the start: the counter
+    // is cleared before each one, by a kernel (no memset node under graph capture)
+    if (a.work_counter) launch_fill_zero(reinterpret_cast<double*>(a.work_counter), 1, s);
     const int grid = a.work_counter ? std::min(a.n_work, a.grid_cap) : a.n_work;
     hipLaunchKernelGGL((k_p2p<KD, MIXED, RB>), dim3(grid), dim3(kThreads), 0, s, a, r0);
     PK_HIP(hipGetLastError());

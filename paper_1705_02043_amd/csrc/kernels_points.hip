@@ -103,20 +103,107 @@ __global__ void k_unpermute(const double* __restrict__ pot, const uint32_t* __re
             out[((int64_t)r * n + j) * k + c] = scale * pot[((int64_t)r * k + c) * n + i];
 }
 
-// one workgroup per (problem, rhs x component); deterministic tree reduction in LDS
+// one workgroup per (problem, rhs x component): the sum and the sum of magnitudes;
+// deterministic tree reduction in LDS
 __global__ void k_density_sums(const double* __restrict__ ds, int64_t n, const int64_t* __restrict__ off,
                                double* __restrict__ out) {
-    __shared__ double sh[256];
+    __shared__ double sh[2][256];
     const double* src = ds + (int64_t)blockIdx.y * n;
-    double acc = 0.0;
-    for (int64_t i = off[blockIdx.x] + threadIdx.x; i < off[blockIdx.x + 1]; i += 256) acc += src[i];
-    sh[threadIdx.x] = acc;
+    double acc = 0.0, mag = 0.0;
+    for (int64_t i = off[blockIdx.x] + threadIdx.x; i < off[blockIdx.x + 1]; i += 256) {
+        acc += src[i];
+        mag += fabs(src[i]);
+    }
+    sh[0][threadIdx.x] = acc;
+    sh[1][threadIdx.x] = mag;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        if ((int)threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * gridDim.y + blockIdx.y] = sh[0];
+    if (threadIdx.x == 0) {
+        const int64_t o = 2 * ((int64_t)blockIdx.x * gridDim.y + blockIdx.y);
+        out[o] = sh[0][0];
+        out[o + 1] = sh[1][0];
+    }
+}
+
+// Pairs of points whose separation the mixed form's integer coordinates could round to zero
+// although they are different points or different images: points in different cells of the
+// finest (2^-21) grid, or one point and another's periodic image, closer than `delta` in every
+// coordinate.  Points in one cell share a leaf and meet there without an image, where the
+// kernels guard zero separations anyway.  One thread per sorted point: a point within delta of
+// a face of its cell looks through the neighbouring cells across those faces (their key
+// ranges found by binary search inside the point's problem; periodic axes wrap with an image
+// shift, other axes stop at the box) for a point closer than delta.  Sets *flag on a find,
+// and also, conservatively, when a neighbouring cell holds more than kScan points.
+constexpr int kScan = 64;
+__global__ void k_close_pairs(const uint64_t* __restrict__ keys, const double* __restrict__ xs, int64_t n,
+                              const int64_t* __restrict__ off, int n_prob, unsigned mask, double delta,
+                              int* __restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double cell = 1.0 / 2097152.0;
+    double x[3];
+    int c[3], lo[3], hi[3];
+    bool any = false;
+    for (int a = 0; a < 3; ++a) {
+        x[a] = xs[a * n + i];
+        c[a] = (int)fmin(floor(x[a] * 2097152.0), 2097151.0);
+        lo[a] = x[a] - c[a] * cell < delta ? -1 : 0;
+        hi[a] = (c[a] + 1) * cell - x[a] < delta ? 1 : 0;
+        any = any || lo[a] || hi[a];
+    }
+    if (!any) return;
+    int q0 = 0, q1 = n_prob;   // the problem of point i: last q with off[q] <= i
+    while (q1 - q0 > 1) {
+        const int m = (q0 + q1) >> 1;
+        if (off[m] <= i) q0 = m;
+        else q1 = m;
+    }
+    const int64_t pb = off[q0], pe = off[q0 + 1];
+    for (int ox = lo[0]; ox <= hi[0]; ++ox)
+        for (int oy = lo[1]; oy <= hi[1]; ++oy)
+            for (int oz = lo[2]; oz <= hi[2]; ++oz) {
+                if (ox == 0 && oy == 0 && oz == 0) continue;
+                const int o[3] = {ox, oy, oz};
+                uint32_t nc[3];
+                double shift[3];
+                bool ok = true;
+                for (int a = 0; a < 3; ++a) {
+                    int v = c[a] + o[a];
+                    shift[a] = 0.0;
+                    if (v < 0 || v >= 2097152) {
+                        if (!(mask & (1u << a))) ok = false;
+                        shift[a] = v < 0 ? -1.0 : 1.0;
+                        v = v < 0 ? v + 2097152 : v - 2097152;
+                    }
+                    nc[a] = (uint32_t)v;
+                }
+                if (!ok) continue;
+                const uint64_t key = (spread3(nc[0]) << 2) | (spread3(nc[1]) << 1) | spread3(nc[2]);
+                int64_t l = pb, h = pe;
+                while (l < h) {   // first key >= key
+                    const int64_t m = l + ((h - l) >> 1);
+                    if (keys[m] < key) l = m + 1;
+                    else h = m;
+                }
+                for (int64_t j = l, cnt = 0; j < pe && keys[j] == key; ++j, ++cnt) {
+                    if (cnt >= kScan) {
+                        atomicOr(flag, 1);
+                        return;
+                    }
+                    double dmax = 0.0;
+                    for (int a = 0; a < 3; ++a) dmax = fmax(dmax, fabs(x[a] - (xs[a * n + j] + shift[a])));
+                    if (dmax < delta) {
+                        atomicOr(flag, 1);
+                        return;
+                    }
+                }
+            }
 }
 
 __global__ void k_fill_zero(double* __restrict__ x, int64_t n) {
@@ -234,6 +321,14 @@ void launch_unpermute(const double* pot, const uint32_t* perm, int64_t n, int R,
                       hipStream_t s) {
     if (n == 0) return;
     hipLaunchKernelGGL(k_unpermute, dim3(nblk(n, 256)), dim3(256), 0, s, pot, perm, n, R, k, scale, out);
+    PK_HIP(hipGetLastError());
+}
+
+void launch_close_pairs(const uint64_t* keys, const double* xs, int64_t n, const int64_t* off, int n_prob,
+                        unsigned mask, double delta, int* flag, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_close_pairs, dim3(nblk(n, 256)), dim3(256), 0, s, keys, xs, n, off, n_prob, mask, delta,
+                       flag);
     PK_HIP(hipGetLastError());
 }
 

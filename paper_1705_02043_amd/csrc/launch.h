@@ -36,10 +36,16 @@ void launch_tree_children(const uint64_t* keys, const int* box, int n_split, int
                           hipStream_t s);
 // y[0..n) += x[0..n)
 void launch_add_into(double* y, const double* x, int64_t n, hipStream_t s);
-// per-problem, per-RHS, per-component sums of the sorted densities (neutrality check):
-// out [n_prob][R*k]; problem i owns sorted points [off[i], off[i+1]) (off: device)
+// per-problem, per-RHS, per-component sums and sums of magnitudes of the sorted densities
+// (neutrality check): out [n_prob][R*k][2]; problem i owns sorted points [off[i], off[i+1])
+// (off: device)
 void launch_density_sums(const double* ds, int64_t n, int R, int k, const int64_t* off, int n_prob, double* out,
                          hipStream_t s);
+// sets *flag if two different points, or a point and another point's periodic image, lie in
+// different cells of the 2^-21 grid and closer than delta in every coordinate (keys and xs
+// sorted, per problem; xs the wrapped unit-box coordinates [3][n])
+void launch_close_pairs(const uint64_t* keys, const double* xs, int64_t n, const int64_t* off, int n_prob,
+                        unsigned mask, double delta, int* flag, hipStream_t s);
 
 // ---- direct interactions (kernels_p2p.hip)
 struct Seg {         // one source segment
@@ -85,7 +91,10 @@ struct P2PArgs {
     double* mpart;       // [k][n_slots] kind-3 partial sums (float64), written once each
     int64_t n_slots;
     int grid_cap;        // k_p2p with work_counter: this many workgroups take items from the counter
-    unsigned long long* work_counter;   // zero before the launch; NULL: one workgroup per item
+    int guard_all;       // mixed form: guard zero separations in every segment (set when points of
+                         // different leaves or images may round to one integer position)
+    unsigned long long* work_counter;   // one word, cleared by launch_p2p before each launch of a
+                                        // right-hand-side block; NULL: one workgroup per item
 };
 // right-hand sides are processed in blocks that share each pair's geometry; segments of
 // kind 3 require R == 1

@@ -40,6 +40,10 @@ using namespace pk;
 namespace {
 
 constexpr double kInnerHalf = 0.525;   // half edge of the 1.05 cube, in box edges
+constexpr double kNeutralRel = 1e-12;  // SP/DP neutrality: |sum phi| <= this * sum |phi|
+// mixed form: points closer than this (unit-box coordinates) in every coordinate may share an
+// integer position in the near field (at most 2 units of 2^-29 of a leaf edge <= 1 apart)
+constexpr double kCloseDelta = 1.0 / (1 << 27);
 constexpr double kOuterHalf = 1.475;   // half edge of the 2.95 cube
 
 std::vector<double> unit_surface(int p) {
@@ -101,10 +105,12 @@ struct pkifmm_plan {
     hipStream_t near_stream = nullptr;          // near field, concurrent with the end of M2L
     hipStream_t x_stream = nullptr;             // X list, beside the upward pass and M2L
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_xjoin = nullptr;
+    hipEvent_t ev_done = nullptr;               // end of the last evaluation enqueued (all streams joined)
     hipStream_t capture_stream = nullptr;      // PKIFMM_GRAPH: the evaluation is captured here
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int g_key_R = 0;
+    bool capturing = false;
     const double* g_key_in = nullptr;
     double* g_key_out = nullptr;
     uint64_t g_key_gen = 0, generation = 0;
@@ -137,7 +143,8 @@ struct pkifmm_plan {
     DBuf<double> u_wrapped, xs;
     DBuf<int> ioff;
     DBuf<char> sort_temp;
-    DBuf<int> err_flag;
+    DBuf<int> err_flag;                 // [0]: a coordinate out of the box; [1]: close points (mixed form)
+    bool guard_all = false;             // mixed form: guard zero separations in every near-field segment
     DBuf<int> b_level, b_ix, b_iy, b_iz, b_begin, b_end, leaf_boxes;
     PinnedBuf<uint64_t> keys_host;
     DBuf<int> tree_box, tree_out;       // per-level split boxes and their children (device tree build)
@@ -497,7 +504,7 @@ void build_stage_tree(pkifmm_plan* P, int R) {
     P->ds.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
     if (P->cfg.precision == PKIFMM_MIXED) P->ds32.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
     P->pot.ensure((size_t)R * P->k * std::max<int64_t>(P->n, 1));
-    P->sums.ensure((size_t)P->n_problems * R * P->k);
+    P->sums.ensure((size_t)P->n_problems * R * P->k * 2);
     {   // split-K partial tiles: the largest small launch of the tree passes
         int64_t need = 1;
         auto consider = [&](const GemmRange& gr, int K) {
@@ -900,11 +907,10 @@ void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_sur
     a.mpart = P->mpart.p;
     a.n_slots = P->n_slots;
     a.grid_cap = grid_cap;
+    a.guard_all = P->guard_all ? 1 : 0;
     a.work_counter = nullptr;
-    if (grid_cap > 0 && grid_cap < w.nwork) {   // the counter is cleared by a kernel (graph-safe)
+    if (grid_cap > 0 && grid_cap < w.nwork)     // cleared before each launch (launch_p2p)
         a.work_counter = reinterpret_cast<unsigned long long*>(P->counter.p);
-        launch_fill_zero(P->counter.p, 1, s);
-    }
     if (to_surface) launch_p2s(a, s);
     else launch_p2p(a, f32, s);
 }
@@ -912,6 +918,10 @@ void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_sur
 }  // namespace
 
 namespace {
+
+// Wait until the last evaluation enqueued (on any stream) has finished: work lists, workspace and
+// point buffers are rewritten or reallocated only after that.
+void wait_idle(pkifmm_plan* P) { PK_HIP(hipEventSynchronize(P->ev_done)); }
 
 void drop_graph(pkifmm_plan* P) {
     if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
@@ -984,17 +994,17 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
         launch_permute_density(density, P->perm.p, n, R, k, P->ds.p, mixed ? P->ds32.p : nullptr, s);
         const int naxes = __builtin_popcount(P->cfg.periodic_mask);
         if (checks && (naxes == 1 || naxes == 2) && !(P->cfg.flags & PKIFMM_SKIP_CHECKS)) {
+            // zero net density (Section 2, the compatibility condition), relative to the density's
+            // magnitude so that the test does not depend on its scale: |sum phi| <= 1e-12 sum |phi|
+            // per problem, right-hand side and component
             const int np = P->n_problems;
-            std::vector<double> sums((size_t)np * R * k);
+            std::vector<double> sums((size_t)np * R * k * 2);
             launch_density_sums(P->ds.p, n, R, k, P->prob_off.p, np, P->sums.p, s);
             PK_HIP(hipMemcpyAsync(sums.data(), P->sums.p, sizeof(double) * sums.size(), hipMemcpyDeviceToHost, s));
             PK_HIP(hipStreamSynchronize(s));
-            for (int q = 0; q < np; ++q) {
-                const double cnt = (double)(P->prob_off_h[q + 1] - P->prob_off_h[q]);
-                for (int i = 0; i < R * k; ++i)
-                    if (!(std::fabs(sums[(size_t)q * R * k + i]) <= 1e-10 * std::max(1.0, cnt)))
-                        throw Error(PKIFMM_ERR_INCOMPATIBLE, "singly and doubly periodic input needs a zero net density");
-            }
+            for (size_t i = 0; i < sums.size(); i += 2)
+                if (!(std::fabs(sums[i]) <= kNeutralRel * sums[i + 1]))
+                    throw Error(PKIFMM_ERR_INCOMPATIBLE, "singly and doubly periodic input needs a zero net density");
         }
         const size_t cols = (size_t)t.nbox() * R;
         const int64_t kk = (int64_t)kn * kn;
@@ -1070,6 +1080,7 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
         const double c = (P->cfg.kernel == PKIFMM_LAPLACE ? 1.0 / (4.0 * M_PI) : 1.0 / (8.0 * M_PI)) / P->cfg.box_length;
         launch_unpermute(P->pot.p, P->perm.p, n, R, k, c, potential, s);
         mark();
+        if (!P->capturing) PK_HIP(hipEventRecord(P->ev_done, s));
         if (timing) P->pending_events.push_back(ev);
         if (build) P->R_built = R;
 }
@@ -1118,6 +1129,7 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
         PK_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
         PK_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
         PK_HIP(hipEventCreateWithFlags(&P->ev_xjoin, hipEventDisableTiming));
+        PK_HIP(hipEventCreateWithFlags(&P->ev_done, hipEventDisableTiming));
         hipStream_t s = P->setup_stream;
         {
             int dev = 0;
@@ -1176,7 +1188,7 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
             P->m2l_oz_e.ensure((size_t)kNumM2L * kp);
             launch_oz_slice_operators(P->m2l.p, kNumM2L, kn, kn, P->m2l_oz.p, P->m2l_oz_e.p, s);
         }
-        P->err_flag.ensure(1);
+        P->err_flag.ensure(2);
         PK_HIP(hipStreamSynchronize(s));
         rocblas_destroy_handle(h);
         h = nullptr;
@@ -1193,6 +1205,7 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
         if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
         if (P->ev_join) (void)hipEventDestroy(P->ev_join);
         if (P->ev_xjoin) (void)hipEventDestroy(P->ev_xjoin);
+        if (P->ev_done) (void)hipEventDestroy(P->ev_done);
         return e.code;
     } catch (const std::bad_alloc&) {
         if (h) rocblas_destroy_handle(h);
@@ -1220,6 +1233,7 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
     try {
+        wait_idle(P);   // an evaluation in flight still reads the current points and lists
         P->have_points = false;
         P->R_built = -1;
         ++P->generation;
@@ -1235,15 +1249,18 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
         P->perm.ensure(m);
         P->u_wrapped.ensure(3 * m);
         P->xs.ensure(3 * m);
-        PK_HIP(hipMemsetAsync(P->err_flag.p, 0, sizeof(int), s));
+        PK_HIP(hipMemsetAsync(P->err_flag.p, 0, 2 * sizeof(int), s));
         launch_keys(xyz, n, P->cfg.box_length, P->cfg.periodic_mask, P->keys_a.p, P->vals_a.p, P->u_wrapped.p,
                     P->err_flag.p, s);
-        int err = 0;
-        PK_HIP(hipMemcpyAsync(&err, P->err_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
         // each problem's points are sorted on their own (segmented sort for a batch)
         radix_sort_pairs(P->keys_a.p, P->keys_b.p, P->vals_a.p, P->perm.p, n, P->sort_temp, s, n_problems,
                          P->prob_off.p);
         launch_gather_points(P->u_wrapped.p, P->perm.p, n, P->xs.p, s);
+        if (P->cfg.precision == PKIFMM_MIXED)   // are zero separations possible outside a leaf's own segment?
+            launch_close_pairs(P->keys_b.p, P->xs.p, n, P->prob_off.p, n_problems, P->cfg.periodic_mask, kCloseDelta,
+                               P->err_flag.p + 1, s);
+        int err[2] = {0, 0};
+        PK_HIP(hipMemcpyAsync(err, P->err_flag.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
         const uint64_t* keys = nullptr;
         if (n_problems > 1) {   // the forest is built on the host, one problem per thread
             P->keys_host.ensure(m);
@@ -1251,7 +1268,9 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
             if (n) PK_HIP(hipMemcpyAsync(P->keys_host.p, P->keys_b.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
         }
         PK_HIP(hipStreamSynchronize(s));
-        if (err) throw Error(PKIFMM_ERR_OUT_OF_BOX, "coordinate outside the box on a non-periodic axis, or not finite");
+        if (err[0]) throw Error(PKIFMM_ERR_OUT_OF_BOX, "coordinate outside the box on a non-periodic axis, or not finite");
+        P->guard_all = err[1] != 0;
+        P->stats.close_points = P->guard_all ? 1 : 0;
         if (n_problems == 1) {
             build_tree_device(P, P->keys_b.p, n, P->cfg.max_pts_per_leaf, P->tree, s);
             build_lists_host(P->tree, P->cfg.periodic_mask, P->lists);
@@ -1321,6 +1340,11 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
     hipStream_t s = (hipStream_t)stream;
     try {
         if (P->n == 0) return PKIFMM_OK;
+        // new work lists (another n_rhs) overwrite lists and workspace that an evaluation still in
+        // flight may read: wait for it first.  Otherwise the stream is ordered after the previous
+        // evaluation on the device, whichever stream that ran on.
+        if (P->R_built != R) wait_idle(P);
+        PK_HIP(hipStreamWaitEvent(s, P->ev_done, 0));
         if (!(P->cfg.flags & PKIFMM_GRAPH)) {
             // a first evaluation on new points builds its work lists stage by stage, each
             // while the kernels of the previous stage run
@@ -1331,17 +1355,21 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
             const bool same = P->gexec && P->g_key_R == R && P->g_key_in == density && P->g_key_out == potential &&
                               P->g_key_gen == P->generation;
             if (!same) {
+                wait_idle(P);   // the previous graph may still be running
                 drop_graph(P);
                 hipStream_t cs = P->capture_stream;
                 PK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+                P->capturing = true;
                 try {
                     enqueue_evaluate(P, R, density, potential, cs, false, false);
                 } catch (...) {
+                    P->capturing = false;
                     hipGraph_t g = nullptr;
                     (void)hipStreamEndCapture(cs, &g);
                     if (g) (void)hipGraphDestroy(g);
                     throw;
                 }
+                P->capturing = false;
                 PK_HIP(hipStreamEndCapture(cs, &P->graph));
                 PK_HIP(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
                 P->g_key_R = R;
@@ -1350,6 +1378,7 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
                 P->g_key_gen = P->generation;
             }
             PK_HIP(hipGraphLaunch(P->gexec, s));
+            PK_HIP(hipEventRecord(P->ev_done, s));
         }
     } catch (const Error& e) {
         return fail(P, e);
@@ -1437,18 +1466,20 @@ int pkifmm_get_list(const pkifmm_plan* P, char which, int64_t* offsets, int32_t*
 
 int pkifmm_plan_destroy(pkifmm_plan* P) {
     if (!P) return PKIFMM_OK;
+    if (P->ev_done) (void)hipEventSynchronize(P->ev_done);   // no evaluation may still read plan buffers
     for (auto& ev : P->pending_events)
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     drop_graph(P);
     if (P->setup_stream) (void)hipStreamDestroy(P->setup_stream);
     if (P->setup_stream2) (void)hipStreamDestroy(P->setup_stream2);
-        if (P->setup_stream3) (void)hipStreamDestroy(P->setup_stream3);
+    if (P->setup_stream3) (void)hipStreamDestroy(P->setup_stream3);
     if (P->near_stream) (void)hipStreamDestroy(P->near_stream);
     if (P->x_stream) (void)hipStreamDestroy(P->x_stream);
     if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
     if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
     if (P->ev_join) (void)hipEventDestroy(P->ev_join);
     if (P->ev_xjoin) (void)hipEventDestroy(P->ev_xjoin);
+    if (P->ev_done) (void)hipEventDestroy(P->ev_done);
     delete P;
     return PKIFMM_OK;
 }
