@@ -86,6 +86,7 @@ typedef struct pkifmm_plan pkifmm_plan;
 #define PKIFMM_ERR_HIP -6
 #define PKIFMM_ERR_NO_POINTS -7      /* evaluate before set_points */
 #define PKIFMM_ERR_NUMERICS -8       /* operator construction failed its self-check */
+#define PKIFMM_ERR_CAPACITY -9       /* pkifmm_evaluate_noalloc: the workspace exceeds its static array */
 
 typedef struct {
     int kernel;                  /* PKIFMM_LAPLACE or PKIFMM_STOKES */
@@ -214,6 +215,30 @@ int pkifmm_set_points_batch(pkifmm_plan *plan, int n_problems, const int64_t *co
  */
 int pkifmm_evaluate(pkifmm_plan *plan, int n_rhs, const double *density, double *potential,
                     void *stream);
+
+/*
+ * pkifmm_evaluate without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid it).  Same
+ * arguments, layouts and result as pkifmm_evaluate; the result is bitwise that of
+ * pkifmm_evaluate (same kernels in the same order).  Differences:
+ *   * the work lists for (points, n_rhs) must exist already: pkifmm_evaluate with this n_rhs on
+ *     the current points has been called once (else INVALID_ARG; it would have to allocate them);
+ *   * the evaluation's workspace (permuted densities, potentials, per-box check potentials and
+ *     densities, M2L and split-K temporaries, near-field partial slots, int8 digit slices, the
+ *     work counter) is a static device array of 64 MiB per GPU, held from the library's first
+ *     use on that GPU until the process ends (its address on each device is looked up when a plan
+ *     is created there); a larger need returns CAPACITY (it holds, for example, a Stokes problem
+ *     at p = 6 of 1.2e4 points with 3 right-hand sides, or of 2e4 points with 1);
+ *   * no neutrality check and no phase timing; never captured by the library (PKIFMM_GRAPH is
+ *     ignored), but the caller may capture `stream` around the call;
+ *   * every call on a GPU shares that GPU's array, which keeps the previous call's contents (every
+ *     region is written or cleared before it is read): calls that overlap in time on one GPU,
+ *     from any plans or threads, race and give wrong results.
+ * Calls no hipMalloc, hipFree or allocating library routine.
+ * Errors: NO_POINTS, INVALID_ARG, CAPACITY, HIP.
+ */
+int pkifmm_evaluate_noalloc(pkifmm_plan *plan, int n_rhs, const double *density, double *potential,
+                            void *stream);
 
 /* Tree and list sizes of the current points and the last call timings.  With
  * PKIFMM_PHASE_TIMING this waits for the recorded events of every evaluation since

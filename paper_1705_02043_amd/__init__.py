@@ -25,10 +25,10 @@ FAR_STEP_D = 8
 
 OK = 0
 ERR_INVALID_ARG, ERR_OUT_OF_BOX, ERR_INCOMPATIBLE, ERR_UNSUPPORTED = -1, -2, -3, -4
-ERR_OOM, ERR_HIP, ERR_NO_POINTS, ERR_NUMERICS = -5, -6, -7, -8
+ERR_OOM, ERR_HIP, ERR_NO_POINTS, ERR_NUMERICS, ERR_CAPACITY = -5, -6, -7, -8, -9
 
 EXPORTED = ["pkifmm_config_default", "pkifmm_plan_create", "pkifmm_set_points", "pkifmm_set_points_batch",
-            "pkifmm_evaluate",
+            "pkifmm_evaluate", "pkifmm_evaluate_noalloc",
             "pkifmm_get_stats", "pkifmm_get_tree", "pkifmm_get_list", "pkifmm_plan_destroy",
             "pkifmm_status_string", "pkifmm_last_error", "pkifmm_host_topology"]
 
@@ -71,6 +71,7 @@ def lib():
             "pkifmm_set_points": (i32, [vp, i64, vp, vp]),
             "pkifmm_set_points_batch": (i32, [vp, i32, vp, vp, vp]),
             "pkifmm_evaluate": (i32, [vp, i32, vp, vp, vp]),
+            "pkifmm_evaluate_noalloc": (i32, [vp, i32, vp, vp, vp]),
             "pkifmm_get_stats": (i32, [vp, ctypes.POINTER(pkifmm_stats)]),
             "pkifmm_get_tree": (i32, [vp, vp, vp]),
             "pkifmm_get_list": (i32, [vp, ctypes.c_char, vp, vp]),
@@ -176,11 +177,14 @@ class Plan:
                                              _stream_ptr(stream)), self._h)
         self.n = xyz.shape[0]
 
-    def evaluate(self, density, out=None, stream=None):
+    def evaluate(self, density, out=None, stream=None, noalloc=False):
         """density: float64 CUDA [R, n, k] (or [n, k]); returns potentials of the same shape.
 
         out, if given, is a contiguous float64 CUDA tensor of the density's shape; it may be the
-        density tensor itself (the pass reads every density before it writes a potential)."""
+        density tensor itself (the pass reads every density before it writes a potential).
+        noalloc=True calls pkifmm_evaluate_noalloc (the library allocates nothing; its workspace is
+        a static device array): give a contiguous density and an `out` so that this binding
+        allocates nothing either."""
         import torch
         if density.dim() not in (2, 3):
             raise ValueError("density must be [n, k] or [R, n, k]")
@@ -203,8 +207,9 @@ class Plan:
             stream.wait_stream(torch.cuda.current_stream())
             d.record_stream(stream)
             res.record_stream(stream)
-        _check(lib().pkifmm_evaluate(self._h, d.shape[0], ctypes.c_void_p(d.data_ptr()),
-                                     ctypes.c_void_p(res.data_ptr()), _stream_ptr(stream)), self._h)
+        fn = lib().pkifmm_evaluate_noalloc if noalloc else lib().pkifmm_evaluate
+        _check(fn(self._h, d.shape[0], ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(res.data_ptr()),
+                  _stream_ptr(stream)), self._h)
         return res[0] if squeeze else res
 
     def stats(self) -> dict:

@@ -31,7 +31,9 @@
 #include <cstring>
 #include <exception>
 #include <memory>
+#include <mutex>
 #include <thread>
+#include <type_traits>
 
 #include "launch.h"
 
@@ -92,6 +94,41 @@ struct GemmSet {            // device copy of one Gemm description
     DBuf<double> col_scale;
 };
 
+// Device workspace of one evaluation: the plan's own buffers (pkifmm_evaluate), or regions of
+// the library's static array (pkifmm_evaluate_noalloc).
+struct Workspace {
+    bool from_plan = true;
+    double *ds = nullptr, *pot = nullptr, *q_u = nullptr, *phi_u = nullptr, *q_d = nullptr, *q_x = nullptr;
+    double *phi_d = nullptr, *tmp = nullptr, *m2l_tmp = nullptr, *split_tmp = nullptr, *mpart = nullptr;
+    double *sums = nullptr, *counter = nullptr;
+    float* ds32 = nullptr;
+    int8_t* phi_oz = nullptr;
+    int* phi_oz_e = nullptr;
+    int64_t split_cap = 0;      // doubles at split_tmp
+};
+
+// pkifmm_evaluate_noalloc's workspace: one array per GPU, held until the process ends.  Host
+// code never uses the name itself as an address: each device's address of it is looked up once
+// (scratch_address) and kept.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be the current device.
+void* scratch_address(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) throw Error(PKIFMM_ERR_INVALID_ARG, "device ordinal beyond the static workspace table");
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        PK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Error(PKIFMM_ERR_HIP, "static workspace has no device address");
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 struct pkifmm_plan {
@@ -115,6 +152,8 @@ struct pkifmm_plan {
     double* g_key_out = nullptr;
     uint64_t g_key_gen = 0, generation = 0;
     int n_cu = 256;
+    int dev = 0;                        // the device the plan was created on
+    void* scratch_base = nullptr;       // that device's address of the static workspace
 
     // operators (device, float64, column-major kn x kn unless noted)
     DBuf<double> usurf;                 // [n][3]
@@ -176,6 +215,7 @@ struct pkifmm_plan {
     DBuf<int64_t> v_goff;                                // per group: CSR over boxes of temp slots
     DBuf<int> v_gtargets;
     int m2l_slots = 1;
+    int64_t split_need = 1;             // doubles of split-K partial tiles the tree passes use
     GemmSet gsets[2];                   // per GemmRange set
 
     // workspace
@@ -518,6 +558,7 @@ void build_stage_tree(pkifmm_plan* P, int R) {
             consider(P->g_l2l[lv], kn);
         }
         consider(P->g_root, kn);
+        P->split_need = need;
         P->split_tmp.ensure(need);
     }
     PK_HIP(hipStreamSynchronize(s));
@@ -822,8 +863,8 @@ void build_work(pkifmm_plan* P, int R) {
     P->R_built = R;
 }
 
-void run_gemm(pkifmm_plan* P, const GemmRange& gr, const double* ops, int64_t op_stride, int M, int K,
-              const double* B, int64_t ldb, double* C, int64_t ldc, bool acc, hipStream_t s, int nkb = 1,
+void run_gemm(pkifmm_plan* P, const Workspace& w, const GemmRange& gr, const double* ops, int64_t op_stride, int M,
+              int K, const double* B, int64_t ldb, double* C, int64_t ldc, bool acc, hipStream_t s, int nkb = 1,
               bool allow_split = true, int rhs = 0) {
     if (gr.ntile == 0) return;
     GemmArgs a{};
@@ -846,13 +887,14 @@ void run_gemm(pkifmm_plan* P, const GemmRange& gr, const double* ops, int64_t op
     a.accumulate = acc ? 1 : 0;
     a.rhs = rhs;
     // the per-level launches split K (latency-bound, few tiles); M2L never does
-    if (allow_split) launch_gemm(a, s, P->split_tmp.p, (int64_t)P->split_tmp.n);
+    if (allow_split) launch_gemm(a, s, w.split_tmp, w.split_cap);
     else launch_gemm(a, s);
 }
 
 // M2L of the mixed form: the same tiles and column lists on the int8 slices of the operators
 // and of the upward densities (sliced once per evaluation, all nbox*R columns)
-void run_gemm_oz(pkifmm_plan* P, const GemmRange& gr, int R, double* C, int64_t ldc, hipStream_t s) {
+void run_gemm_oz(pkifmm_plan* P, const Workspace& w, const GemmRange& gr, int R, double* C, int64_t ldc,
+                 hipStream_t s) {
     if (gr.ntile == 0) return;
     const int kp = oz_padded(P->kn);
     OzArgs a{};
@@ -861,8 +903,8 @@ void run_gemm_oz(pkifmm_plan* P, const GemmRange& gr, int R, double* C, int64_t 
     a.Mp = kp;
     a.Kp = kp;
     a.M = P->kn;
-    a.b_sl = P->phi_oz.p;
-    a.b_exp = P->phi_oz_e.p;
+    a.b_sl = w.phi_oz;
+    a.b_exp = w.phi_oz_e;
     a.b_slice_stride = (int64_t)P->tree.nbox() * R * kp;
     a.C = C;
     a.ldc = ldc;
@@ -877,8 +919,8 @@ void run_gemm_oz(pkifmm_plan* P, const GemmRange& gr, int R, double* C, int64_t 
     launch_gemm_oz(a, s);
 }
 
-void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_surf, int R, bool f32, bool acc_pts,
-             hipStream_t s, bool to_surface = false, int grid_cap = 0) {
+void run_p2p(pkifmm_plan* P, const Workspace& ws, const SegRange& w, double* out_pts, double* out_surf, int R, bool f32,
+             bool acc_pts, hipStream_t s, bool to_surface = false, int grid_cap = 0) {
     if (w.nwork == 0) return;
     P2PArgs a{};
     a.kernel = P->cfg.kernel;
@@ -887,10 +929,10 @@ void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_sur
     a.n = P->n;
     a.xs = P->xs.p;
     a.ioff = P->ioff.p;
-    a.ds = P->ds.p;
-    a.ds32 = P->ds32.p;
-    a.phi_u = P->phi_u.p;
-    a.phi_d = P->phi_d.p;
+    a.ds = ws.ds;
+    a.ds32 = ws.ds32;
+    a.phi_u = ws.phi_u;
+    a.phi_d = ws.phi_d;
     a.box_level = P->b_level.p;
     a.box_ix = P->b_ix.p;
     a.box_iy = P->b_iy.p;
@@ -904,13 +946,13 @@ void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_sur
     a.out_pts = out_pts;
     a.out_surf = out_surf;
     a.accumulate_pts = acc_pts ? 1 : 0;
-    a.mpart = P->mpart.p;
+    a.mpart = ws.mpart;
     a.n_slots = P->n_slots;
     a.grid_cap = grid_cap;
     a.guard_all = P->guard_all ? 1 : 0;
     a.work_counter = nullptr;
     if (grid_cap > 0 && grid_cap < w.nwork)     // cleared before each launch (launch_p2p)
-        a.work_counter = reinterpret_cast<unsigned long long*>(P->counter.p);
+        a.work_counter = reinterpret_cast<unsigned long long*>(ws.counter);
     if (to_surface) launch_p2s(a, s);
     else launch_p2p(a, f32, s);
 }
@@ -918,6 +960,81 @@ void run_p2p(pkifmm_plan* P, const SegRange& w, double* out_pts, double* out_sur
 }  // namespace
 
 namespace {
+
+// Point a plan-backed workspace at the plan's buffers, part by part: the M2L temporary and the
+// near-field partial slots are sized by the build stages on other host threads, and are read
+// only after those threads have been joined.
+enum WsPart { kWsTree, kWsM2L, kWsNear };
+void bind_plan_workspace(pkifmm_plan* P, Workspace& w, WsPart part) {
+    if (!w.from_plan) return;
+    if (part == kWsM2L) {
+        w.m2l_tmp = P->m2l_tmp.p;
+        return;
+    }
+    if (part == kWsNear) {
+        w.mpart = P->mpart.p;
+        return;
+    }
+    w.ds = P->ds.p;
+    w.ds32 = P->ds32.p;
+    w.pot = P->pot.p;
+    w.q_u = P->q_u.p;
+    w.phi_u = P->phi_u.p;
+    w.q_d = P->q_d.p;
+    w.q_x = P->q_x.p;
+    w.phi_d = P->phi_d.p;
+    w.tmp = P->tmp.p;
+    w.split_tmp = P->split_tmp.p;
+    w.split_cap = (int64_t)P->split_tmp.n;
+    w.sums = P->sums.p;
+    w.counter = P->counter.p;
+    w.phi_oz = P->phi_oz.p;
+    w.phi_oz_e = P->phi_oz_e.p;
+}
+
+// The same workspace as regions of one array at `base` (each 256-byte aligned), sized exactly as
+// the plan's buffers for the current work lists and n_rhs R, so that every kernel takes the same
+// path (split-K factors included) and the results are the same bits.  Returns the bytes needed;
+// with base == nullptr only counts them.  The neutrality sums are not placed (no checks there).
+size_t carve_workspace(const pkifmm_plan* P, int R, char* base, Workspace& w) {
+    const bool mixed = P->cfg.precision == PKIFMM_MIXED;
+    const size_t cols = (size_t)P->tree.nbox() * R, kn = (size_t)P->kn;
+    const size_t npts = (size_t)R * P->k * std::max<int64_t>(P->n, 1);
+    const int n_roots = P->tree.level_start[1] - P->tree.level_start[0];
+    size_t off = 0;
+    auto take = [&](auto*& ptr, size_t count) {
+        using T = std::remove_pointer_t<std::remove_reference_t<decltype(ptr)>>;
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        ptr = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += (bytes + 255) / 256 * 256;
+    };
+    w.from_plan = false;
+    take(w.ds, npts);
+    if (mixed) take(w.ds32, npts);
+    else w.ds32 = nullptr;
+    take(w.pot, npts);
+    take(w.q_u, cols * kn);
+    take(w.phi_u, cols * kn);
+    take(w.q_d, cols * kn);
+    take(w.q_x, cols * kn);
+    take(w.phi_d, (cols + (far_step_d(P) ? (size_t)n_roots * R : 0)) * kn);
+    take(w.tmp, cols * kn);
+    take(w.m2l_tmp, (size_t)P->m2l_slots * R * kn);
+    take(w.split_tmp, (size_t)P->split_need);
+    w.split_cap = P->split_need;
+    if (P->mutual) take(w.mpart, (size_t)P->k * std::max<int64_t>(P->n_slots, 1));
+    else w.mpart = nullptr;
+    take(w.counter, 1);
+    if (mixed) {
+        take(w.phi_oz, (size_t)kOzSlices * cols * oz_padded(P->kn));
+        take(w.phi_oz_e, cols);
+    } else {
+        w.phi_oz = nullptr;
+        w.phi_oz_e = nullptr;
+    }
+    w.sums = nullptr;
+    return off;
+}
 
 // Wait until the last evaluation enqueued (on any stream) has finished: work lists, workspace and
 // point buffers are rewritten or reallocated only after that.
@@ -966,8 +1083,10 @@ class StageThread {
 };
 
 // Enqueue one evaluation on stream s (no host synchronisation unless `checks`).
-void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* potential, hipStream_t s, bool checks,
-                      bool allow_timing, bool build = false) {
+// The workspace comes from the plan (w.from_plan: its buffers, bound after each build stage that
+// sizes them) or is given (the static array).
+void enqueue_evaluate(pkifmm_plan* P, Workspace& w, int R, const double* density, double* potential, hipStream_t s,
+                      bool checks, bool allow_timing, bool build = false) {
         const int64_t n = P->n;
         const int k = P->k, kn = P->kn;
         const HostTree& t = P->tree;
@@ -991,7 +1110,12 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
             th_near.start([P, R] { build_stage_near(P, R); });
             build_stage_tree(P, R);
         }
-        launch_permute_density(density, P->perm.p, n, R, k, P->ds.p, mixed ? P->ds32.p : nullptr, s);
+        bind_plan_workspace(P, w, kWsTree);
+        if (!build) {
+            bind_plan_workspace(P, w, kWsM2L);
+            bind_plan_workspace(P, w, kWsNear);
+        }
+        launch_permute_density(density, P->perm.p, n, R, k, w.ds, mixed ? w.ds32 : nullptr, s);
         const int naxes = __builtin_popcount(P->cfg.periodic_mask);
         if (checks && (naxes == 1 || naxes == 2) && !(P->cfg.flags & PKIFMM_SKIP_CHECKS)) {
             // zero net density (Section 2, the compatibility condition), relative to the density's
@@ -999,8 +1123,8 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
             // per problem, right-hand side and component
             const int np = P->n_problems;
             std::vector<double> sums((size_t)np * R * k * 2);
-            launch_density_sums(P->ds.p, n, R, k, P->prob_off.p, np, P->sums.p, s);
-            PK_HIP(hipMemcpyAsync(sums.data(), P->sums.p, sizeof(double) * sums.size(), hipMemcpyDeviceToHost, s));
+            launch_density_sums(w.ds, n, R, k, P->prob_off.p, np, w.sums, s);
+            PK_HIP(hipMemcpyAsync(sums.data(), w.sums, sizeof(double) * sums.size(), hipMemcpyDeviceToHost, s));
             PK_HIP(hipStreamSynchronize(s));
             for (size_t i = 0; i < sums.size(); i += 2)
                 if (!(std::fabs(sums[i]) <= kNeutralRel * sums[i + 1]))
@@ -1016,69 +1140,71 @@ void enqueue_evaluate(pkifmm_plan* P, int R, const double* density, double* pote
         // on a third stream into its own buffer.
         // 2. S2M and the upward pass; X list beside them
         mark();
-        launch_fill_zero(P->q_u.p, (int64_t)cols * kn, s);     // kernels, not memset nodes (graph-safe)
-        launch_fill_zero(P->q_d.p, (int64_t)cols * kn, s);
-        launch_fill_zero(P->q_x.p, (int64_t)cols * kn, s);
+        launch_fill_zero(w.q_u, (int64_t)cols * kn, s);     // kernels, not memset nodes (graph-safe)
+        launch_fill_zero(w.q_d, (int64_t)cols * kn, s);
+        launch_fill_zero(w.q_x, (int64_t)cols * kn, s);
         if (far_step_d(P))   // the roots hand no far field down the tree
-            launch_fill_zero(P->phi_d.p + (size_t)t.level_start[0] * R * kn,
+            launch_fill_zero(w.phi_d + (size_t)t.level_start[0] * R * kn,
                              (int64_t)(t.level_start[1] - t.level_start[0]) * R * kn, s);
-        run_p2p(P, P->w_s2m, nullptr, P->q_u.p, R, false, false, s, true);
+        run_p2p(P, w, P->w_s2m, nullptr, w.q_u, R, false, false, s, true);
         hipStream_t sx = P->x_stream, sn = P->near_stream;
         PK_HIP(hipEventRecord(P->ev_fork, s));
         PK_HIP(hipStreamWaitEvent(sx, P->ev_fork, 0));
-        run_p2p(P, P->w_x, nullptr, P->q_x.p, R, false, false, sx, true);
+        run_p2p(P, w, P->w_x, nullptr, w.q_x, R, false, false, sx, true);
         PK_HIP(hipEventRecord(P->ev_xjoin, sx));
         for (int lv = t.depth; lv >= 0; --lv) {
             const bool split = lv <= kSplitLevels;
-            run_gemm(P, P->g_m2m[lv], P->m2m.p, 0, kn, 8 * kn, P->phi_u.p, kn, P->q_u.p, kn, true, s, 8, split);
-            run_gemm(P, P->g_up1[lv], P->up_Ut.p, 0, P->r_up, kn, P->q_u.p, kn, P->tmp.p, kn, false, s, 1, split);
-            run_gemm(P, P->g_up2[lv], P->up_VS.p, 0, kn, P->r_up, P->tmp.p, kn, P->phi_u.p, kn, false, s, 1, split);
+            run_gemm(P, w, P->g_m2m[lv], P->m2m.p, 0, kn, 8 * kn, w.phi_u, kn, w.q_u, kn, true, s, 8, split);
+            run_gemm(P, w, P->g_up1[lv], P->up_Ut.p, 0, P->r_up, kn, w.q_u, kn, w.tmp, kn, false, s, 1, split);
+            run_gemm(P, w, P->g_up2[lv], P->up_VS.p, 0, kn, P->r_up, w.tmp, kn, w.phi_u, kn, false, s, 1, split);
         }
         mark();
         // 3. root far field and V-list M2L into the downward check potentials
         th_m2l.join();                          // built while the upward pass was enqueued and ran
-        run_gemm(P, P->g_root, P->mroot.p, 0, kn, kn, P->phi_u.p, kn, P->q_d.p, kn, true, s);
-        if (mixed) launch_oz_slice_columns(P->phi_u.p, kn, kn, (int64_t)cols, P->phi_oz.p, P->phi_oz_e.p, s);
+        bind_plan_workspace(P, w, kWsM2L);
+        run_gemm(P, w, P->g_root, P->mroot.p, 0, kn, kn, w.phi_u, kn, w.q_d, kn, true, s);
+        if (mixed) launch_oz_slice_columns(w.phi_u, kn, kn, (int64_t)cols, w.phi_oz, w.phi_oz_e, s);
         for (int q = 0; q < kM2LGroups; ++q) {
             if (P->g_m2l[q].ntile == 0) continue;
             if (mixed)
-                run_gemm_oz(P, P->g_m2l[q], R, P->m2l_tmp.p, kn, s);
+                run_gemm_oz(P, w, P->g_m2l[q], R, w.m2l_tmp, kn, s);
             else
-                run_gemm(P, P->g_m2l[q], P->m2l.p, kk, kn, kn, P->phi_u.p, kn, P->m2l_tmp.p, kn, false, s, 1, false, R);
-            launch_segment_reduce(P->m2l_tmp.p, P->v_goff.p + (size_t)q * (t.nbox() + 1),
+                run_gemm(P, w, P->g_m2l[q], P->m2l.p, kk, kn, kn, w.phi_u, kn, w.m2l_tmp, kn, false, s, 1, false, R);
+            launch_segment_reduce(w.m2l_tmp, P->v_goff.p + (size_t)q * (t.nbox() + 1),
                                   P->v_gtargets.p + P->m2l_targets[q].first, P->m2l_targets[q].second, R, kn,
-                                  P->q_d.p, s);
+                                  w.q_d, s);
         }
         mark();
         // 4. near field (U lists and the direct W/X entries) on the second stream; it needs only
         // the permuted densities
         th_near.join();
+        bind_plan_workspace(P, w, kWsNear);
         PK_HIP(hipStreamWaitEvent(sn, P->ev_fork, 0));
         mark_on(sn);
-        run_p2p(P, P->w_leaf_u, P->pot.p, nullptr, R, mixed, false, sn, false, P->near_grid_cap);
+        run_p2p(P, w, P->w_leaf_u, w.pot, nullptr, R, mixed, false, sn, false, P->near_grid_cap);
         if (P->mutual)
-            launch_mutual_gather(P->mpart.p, P->n_slots, k, P->in_box.p, P->in_off.p, P->in_slot.p, P->n_in,
-                                 P->b_begin.p, P->b_end.p, n, P->pot.p, sn);
+            launch_mutual_gather(w.mpart, P->n_slots, k, P->in_box.p, P->in_off.p, P->in_slot.p, P->n_in,
+                                 P->b_begin.p, P->b_end.p, n, w.pot, sn);
         mark_on(sn);
         PK_HIP(hipEventRecord(P->ev_join, sn));
         // 5. after the near field and the X list: X-list check potentials join, then the
         // downward pass with the whole chip
         PK_HIP(hipStreamWaitEvent(s, P->ev_join, 0));
         PK_HIP(hipStreamWaitEvent(s, P->ev_xjoin, 0));
-        launch_add_into(P->q_d.p, P->q_x.p, (int64_t)cols * kn, s);
+        launch_add_into(w.q_d, w.q_x, (int64_t)cols * kn, s);
         for (int lv = 0; lv <= t.depth; ++lv) {
             const bool split = lv <= kSplitLevels;
             if (lv >= 1)
-                run_gemm(P, P->g_l2l[lv], P->l2l.p, kk, kn, kn, P->phi_d.p, kn, P->q_d.p, kn, true, s, 1, split);
-            run_gemm(P, P->g_dn1[lv], P->dn_Ut.p, 0, P->r_dn, kn, P->q_d.p, kn, P->tmp.p, kn, false, s, 1, split);
-            run_gemm(P, P->g_dn2[lv], P->dn_VS.p, 0, kn, P->r_dn, P->tmp.p, kn, P->phi_d.p, kn, false, s, 1, split);
+                run_gemm(P, w, P->g_l2l[lv], P->l2l.p, kk, kn, kn, w.phi_d, kn, w.q_d, kn, true, s, 1, split);
+            run_gemm(P, w, P->g_dn1[lv], P->dn_Ut.p, 0, P->r_dn, kn, w.q_d, kn, w.tmp, kn, false, s, 1, split);
+            run_gemm(P, w, P->g_dn2[lv], P->dn_VS.p, 0, kn, P->r_dn, w.tmp, kn, w.phi_d, kn, false, s, 1, split);
         }
         mark();
         // 6. W list and L2T (float64: they consume equivalent densities)
-        run_p2p(P, P->w_leaf_far, P->pot.p, nullptr, R, false, true, s);
+        run_p2p(P, w, P->w_leaf_far, w.pot, nullptr, R, false, true, s);
         // 7. output
         const double c = (P->cfg.kernel == PKIFMM_LAPLACE ? 1.0 / (4.0 * M_PI) : 1.0 / (8.0 * M_PI)) / P->cfg.box_length;
-        launch_unpermute(P->pot.p, P->perm.p, n, R, k, c, potential, s);
+        launch_unpermute(w.pot, P->perm.p, n, R, k, c, potential, s);
         mark();
         if (!P->capturing) PK_HIP(hipEventRecord(P->ev_done, s));
         if (timing) P->pending_events.push_back(ev);
@@ -1135,6 +1261,8 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
             int dev = 0;
             PK_HIP(hipGetDevice(&dev));
             PK_HIP(hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+            P->dev = dev;
+            P->scratch_base = scratch_address(dev);   // once per device, this device current
             // near field: four workgroups per compute unit take items from a counter in list
             // (longest-first) order
             P->near_grid_cap = 4 * P->n_cu;
@@ -1348,7 +1476,8 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
         if (!(P->cfg.flags & PKIFMM_GRAPH)) {
             // a first evaluation on new points builds its work lists stage by stage, each
             // while the kernels of the previous stage run
-            enqueue_evaluate(P, R, density, potential, s, true, true, P->R_built != R);
+            Workspace w;
+            enqueue_evaluate(P, w, R, density, potential, s, true, true, P->R_built != R);
         } else {
             if (P->R_built != R) build_work(P, R);
             // captured once per (tree, R, buffers) on a library stream, replayed on the caller's
@@ -1361,7 +1490,8 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
                 PK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
                 P->capturing = true;
                 try {
-                    enqueue_evaluate(P, R, density, potential, cs, false, false);
+                    Workspace w;
+                    enqueue_evaluate(P, w, R, density, potential, cs, false, false);
                 } catch (...) {
                     P->capturing = false;
                     hipGraph_t g = nullptr;
@@ -1386,6 +1516,43 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
         return fail(P, Error(PKIFMM_ERR_OOM, "host allocation"));
     }
     P->stats.ms_evaluate = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return PKIFMM_OK;
+}
+
+int pkifmm_evaluate_noalloc(pkifmm_plan* P, int R, const double* density, double* potential, void* stream) {
+    if (!P) return PKIFMM_ERR_INVALID_ARG;
+    if (!P->have_points) return fail(P, Error(PKIFMM_ERR_NO_POINTS, "set_points has not succeeded"));
+    if (R < 1 || (P->n > 0 && (!density || !potential))) return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n_rhs or pointers"));
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        if (P->n == 0) return PKIFMM_OK;
+        // the work lists live in plan buffers, made by pkifmm_evaluate for this n_rhs
+        if (P->R_built != R)
+            throw Error(PKIFMM_ERR_INVALID_ARG, "no work lists for this n_rhs on these points: call pkifmm_evaluate "
+                                                "with it once first");
+        Workspace w;
+        const size_t need = carve_workspace(P, R, nullptr, w);
+        if (need > kScratchBytes)
+            throw Error(PKIFMM_ERR_CAPACITY, "workspace of " + std::to_string(need) + " bytes exceeds the " +
+                                                 std::to_string(kScratchBytes) + "-byte static array");
+        carve_workspace(P, R, static_cast<char*>(P->scratch_base), w);
+        // ordered after the plan's previous evaluation, unless the caller is capturing `stream`
+        // into a graph (an event recorded outside the capture cannot be waited on inside it)
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        PK_HIP(hipStreamIsCapturing(s, &cap));
+        const bool capturing = cap != hipStreamCaptureStatusNone;
+        if (!capturing) PK_HIP(hipStreamWaitEvent(s, P->ev_done, 0));
+        P->capturing = capturing;
+        try {
+            enqueue_evaluate(P, w, R, density, potential, s, false, false);
+        } catch (...) {
+            P->capturing = false;
+            throw;
+        }
+        P->capturing = false;
+    } catch (const Error& e) {
+        return fail(P, e);
+    }
     return PKIFMM_OK;
 }
 
@@ -1495,6 +1662,7 @@ const char* pkifmm_status_string(int s) {
         case PKIFMM_ERR_HIP: return "HIP runtime error";
         case PKIFMM_ERR_NO_POINTS: return "no points set";
         case PKIFMM_ERR_NUMERICS: return "operator construction failed its self-check";
+        case PKIFMM_ERR_CAPACITY: return "workspace exceeds the static array";
         default: return "unknown status";
     }
 }
