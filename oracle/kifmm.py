@@ -155,6 +155,43 @@ class KIFMM:
         t = self.tree
         return t.centre(b) + np.asarray(shift, dtype=np.float64) + 0.5 * factor * t.edge(b) * unit_surface(self.p)
 
+    # -- the two surface-form interactions of the adaptive lists (Section 2.2: a W-list box acts
+    #    through its upward equivalent density, an X-list leaf's points act on the target box's
+    #    downward check surface)
+    def m2t(self, x, a, p, phi_u, pot):
+        """W list: box a's upward equivalent density, on its inner (equivalent) surface moved by
+        the image shift p, evaluated at the points x (added to pot)."""
+        direct(self.kernel, x, self._surf(a, INNER, p), phi_u[a], pot)
+
+    def s2l(self, b, a, p, ds, q):
+        """X list: the points of leaf a moved by the image shift p, evaluated on box b's inner
+        (downward check) surface (added to q)."""
+        t = self.tree
+        direct(self.kernel, self._surf(b, INNER), self._pts(a, p), ds[t.begin[a]:t.end[a]], q)
+
+    def tp_laplace_background(self, ds, phi_root) -> float:
+        """The part of the triply periodic Laplace far field that the root's equivalent density
+        cannot carry (0 for every other kernel and periodicity).
+
+        The Ewald kernel with its k = 0 mode removed (the zero-mean sum, which includes the
+        uniform neutralising background of Section 5's one-component-plasma remark) satisfies
+        laplacian G = 1/V away from the lattice points.  So, as a function of the source
+        position y near the box, the far kernel is a harmonic function plus |y - c|^2 / 6
+        (V = 1, c the box centre).  The equivalent density reproduces the sources' action on
+        harmonic functions (Section 2.2) but not on |y - c|^2, the one moment that a harmonic
+        field never sees; the far field M_root phi^{B0,u} therefore misses the constant
+        (sum_s q_s |y_s - c|^2 - sum_j phi_j |y_j - c|^2) / 6, added here to every target.
+        Its form does not depend on c for neutral densities (the sums of q and phi, and their
+        dipoles, agree)."""
+        if self.kernel != LAPLACE or self.mask != 7:
+            return 0.0
+        c = np.full(3, 0.5)
+        ys = self.sorted_pts
+        yj = self.tree.centre(0) + 0.5 * INNER * self.tree.edge(0) * unit_surface(self.p)
+        m_src = float(np.sum(ds[:, 0] * np.sum((ys - c) ** 2, axis=1)))
+        m_eq = float(np.sum(phi_root * np.sum((yj - c) ** 2, axis=1)))
+        return (m_src - m_eq) / 6.0
+
     def upward(self, dens_sorted: np.ndarray) -> np.ndarray:
         """phi^{B,u} for every box (dens_sorted: [N, k] in Morton order), level by level."""
         t, ops, k = self.tree, self.ops, self.k
@@ -223,7 +260,7 @@ class KIFMM:
             if self.direct_target(b):
                 continue                     # its X-list sources go straight to its points below
             for (a, p) in self.lists.X[b]:
-                direct(self.kernel, self._surf(b, INNER), self._pts(a, p), ds[t.begin[a]:t.end[a]], qd[b])
+                self.s2l(b, a, p, ds, qd[b])
         # root far field (folded step c), L2L and downward solves
         phi_d = {}
         for b in sorted(need, key=lambda b: t.level[b]):
@@ -238,6 +275,7 @@ class KIFMM:
                 q = q + ops.l2l[o] @ phi_d[par] / t.edge(par)
             phi_d[b] = h * ops.down.apply(q)
         phi_far = t.edge(0) * ops.down.apply(ops.mroot @ phi_u[0]) if step_d else None
+        background = self.tp_laplace_background(ds, phi_u[0])
         out = {}
         for b in leaves:
             x = self._pts(b)
@@ -249,13 +287,13 @@ class KIFMM:
                 if self.direct_source(a):
                     direct(self.kernel, x, self._pts(a), ds[t.begin[a]:t.end[a]], pot, shift=p)
                 else:
-                    direct(self.kernel, x, self._surf(a, INNER, p), phi_u[a], pot)
+                    self.m2t(x, a, p, phi_u, pot)
             if self.direct_target(b):
                 for (a, p) in self.lists.X[b]:
                     direct(self.kernel, x, self._pts(a), ds[t.begin[a]:t.end[a]], pot, shift=p)
             for (a, p) in self.lists.U[b]:
                 direct(self.kernel, x, self._pts(a), ds[t.begin[a]:t.end[a]], pot, shift=p)
-            out[b] = pot / L
+            out[b] = (pot + background) / L
         if target_leaves is not None:
             return out
         res = np.zeros((t.end[0], k))
