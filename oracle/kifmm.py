@@ -9,12 +9,14 @@ discussion:
   are homogeneous of degree -1):
     * upward / downward check-to-equivalent solves from the SVD A = U S V^T,
       applied as (V S_eps^+)(U^T q) (Appendix B, the backward-stable solver),
-      with S_eps^+ dropping singular values below eps * s_max * dim(A): the
-      numerical-rank criterion under which Table 1 reports its ranks.
-      Appendix B's bare eps * s_max keeps directions whose singular values
-      sit at the rounding level of A itself; the solution along them is not
-      determined by the data (two SVD drivers disagree there) and the
-      equivalent densities then carry that noise to other points;
+      with S_eps^+ dropping singular values at or below 1e-11 * s_max (the
+      paper leaves this cutoff free).  Directions with smaller singular values
+      carry no information that survives the rounding of the check potentials
+      (sums with cancellation, tens of ulps): kept, they turn that rounding into
+      equivalent-density noise (two SVD drivers, or two summation orders, then
+      disagree at 1e-9 for Stokes at p = 8) and cost accuracy against the exact
+      periodic sums (Stokes TP p = 8: 1.9e-5 with Table 1's rank criterion
+      eps * s_max * dim(A), 5.2e-6 with 1e-11);
     * M2M, L2L for the eight octants and M2L for the 316 offsets in
       [-3,3]^3 \\ [-1,1]^3, from the free-space kernel between surfaces;
     * the periodic root operator M_root = K^{P,F}(x^{B0,d}, y^{B0,u}) over
@@ -63,14 +65,17 @@ class Pinv:
         return self.VS @ (self.Ut @ q)
 
 
+DEFAULT_CUTOFF = 1e-11
+
+
 def rank_threshold(A: np.ndarray) -> float:
-    """Relative singular-value cutoff eps * dim(A) (the rank criterion of Table 1)."""
+    """Relative singular-value cutoff eps * dim(A): the rank criterion of Table 1."""
     return EPS * max(A.shape)
 
 
 def pinv_factors(A: np.ndarray, rel_threshold: Optional[float] = None) -> Pinv:
     U, s, Vt = np.linalg.svd(A)
-    thr = rank_threshold(A) if rel_threshold is None else rel_threshold
+    thr = DEFAULT_CUTOFF if rel_threshold is None else rel_threshold
     keep = s > thr * s[0]
     return Pinv(Ut=U[:, keep].T.copy(), VS=(Vt[keep].T / s[keep][None, :]).copy())
 
@@ -122,13 +127,26 @@ class KIFMM:
     """One problem: tree, lists and the evaluation pass."""
 
     def __init__(self, kernel: int, mask: int, p: int, s: int, points: np.ndarray,
-                 rel_threshold: Optional[float] = None, box_length: float = 1.0):
+                 rel_threshold: Optional[float] = None, box_length: float = 1.0,
+                 targets: Optional[np.ndarray] = None):
+        """points: the sources (also the targets unless `targets` is given).  With separate
+        targets (Section 2's problem: T targets, S sources) the tree is built over the union of
+        both sets, points [0, S) being the sources and [S, S + T) the targets; a target-only point
+        carries zero density, so it adds nothing to any sum, and evaluate returns the potentials
+        at the targets alone."""
         if not periodic.supported(kernel, mask):
             raise NotImplementedError("unsupported kernel/periodicity")
         self.kernel, self.mask, self.p, self.s = kernel, mask, p, s
         self.k = kdim(kernel)
         self.L = float(box_length)
-        pts = np.asarray(points, dtype=np.float64)
+        pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+        self.n_src = pts.shape[0]
+        self.n_trg = 0
+        self.separate = targets is not None
+        if self.separate:
+            trg = np.asarray(targets, dtype=np.float64).reshape(-1, 3)
+            self.n_trg = trg.shape[0]
+            pts = np.concatenate([pts, trg])
         self.u = otree.wrap(pts / self.L, mask)
         self.tree = otree.build_tree(self.u, s)
         self.lists = otree.build_lists(self.tree, mask)
@@ -216,8 +234,10 @@ class KIFMM:
                  return_sorted: bool = False, step_d: bool = False):
         """Potentials at all points (input order), or at the points of the given leaves.
 
-        density: [N, k] (or [N] for Laplace) in input order.
-        With target_leaves, returns {leaf: potentials [count, k] in Morton order};
+        density: [N, k] (or [N] for Laplace) in input order, N the number of sources.
+        With separate targets the result holds the targets' potentials, in target order.
+        With target_leaves, returns {leaf: potentials [count, k] in Morton order} (every point of
+        the leaf, sources included);
         only the downward pass along those leaves' ancestors is computed.
 
         The far field of the images beyond the first layer enters as the root's downward check
@@ -230,6 +250,8 @@ class KIFMM:
         """
         t, ops, k, L = self.tree, self.ops, self.k, self.L
         dens = np.asarray(density, dtype=np.float64).reshape(-1, k)
+        if self.separate:
+            dens = np.concatenate([dens, np.zeros((self.n_trg, k))])
         ds = np.ascontiguousarray(dens[t.perm])
         phi_u = self.upward(ds)
         kn = k * ops.n
@@ -303,7 +325,7 @@ class KIFMM:
             return res
         full = np.zeros_like(res)
         full[t.perm] = res
-        return full
+        return full[self.n_src:] if self.separate else full
 
 
 def evaluate(kernel: int, mask: int, p: int, s: int, points: np.ndarray, density: np.ndarray,

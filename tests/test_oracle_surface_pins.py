@@ -122,3 +122,34 @@ def test_kifmm_tp_laplace_against_ewald():
     off = _NoBackground(K.LAPLACE, 7, 8, 20, pb.points).evaluate(pb.density[0]) - ex
     assert _rel(off + ex, ex) > 1e-2
     assert np.std(off) < 1e-5 * np.abs(np.mean(off))       # a constant
+
+
+@pytest.mark.parametrize("kernel,mask,tols", [(K.LAPLACE, 1, (2e-5, 5e-7)), (K.LAPLACE, 0, (1e-5, 2e-7)),
+                                              (K.STOKES, 3, (6e-4, None))])
+def test_separate_targets_against_the_periodic_sum(kernel, mask, tols):
+    """T targets apart from S sources (Section 2's problem statement): the union tree's KIFMM at
+    the targets against the periodic sum at the targets; the error falls with p."""
+    rng = np.random.default_rng(70)
+    src = rng.random((600, 3))
+    trg = rng.random((300, 3)) ** 2            # denser near a corner than the sources
+    d = rng.standard_normal((600, K.kdim(kernel)))
+    d -= d.mean(0)
+    ex = periodic.exact_potential(kernel, mask, trg, src, d)
+    for p, tol in zip((6, 8), tols):
+        if tol is None:
+            continue
+        f = kifmm.KIFMM(kernel, mask, p, 30, src, targets=trg)
+        q = f.evaluate(d)
+        assert q.shape == ex.shape
+        assert _rel(q, ex) < tol, (p, _rel(q, ex))
+
+
+def test_separate_targets_that_repeat_the_sources():
+    """Targets placed exactly on the sources give the sources' own potentials (a coincident pair
+    contributes nothing), to the KIFMM error of either tree; no targets give an empty result."""
+    pb = W.stokes_tp_uniform(n=500, seed=71, p=6, s=40)
+    same = kifmm.KIFMM(pb.kernel, 7, 6, 40, pb.points).evaluate(pb.density[0])
+    sep = kifmm.KIFMM(pb.kernel, 7, 6, 40, pb.points, targets=pb.points.copy()).evaluate(pb.density[0])
+    assert _rel(sep, same) < 2e-4
+    none = kifmm.KIFMM(pb.kernel, 7, 6, 40, pb.points, targets=np.zeros((0, 3))).evaluate(pb.density[0])
+    assert none.shape == (0, 3)
