@@ -147,6 +147,27 @@ def other_configs(pk, torch, W, steps=3, warmup=1):
     dens = torch.as_tensor(np.concatenate([q.density for q in probs], axis=1), device="cuda")
     run("laplace_sp_batch64_rhs16_p8_s2000", probs[0].kernel, probs[0].periodic_mask, probs[0].p, probs[0].s,
         lambda pl: pl.set_points_batch(counts, xyz), dens, int(sum(counts)))
+    # the same forest as one captured HIP graph: the points set once, then replays alone timed
+    plan = pk.Plan(probs[0].kernel, probs[0].periodic_mask, probs[0].p, probs[0].s, precision=pk.MIXED,
+                   flags=pk.GRAPH)
+    plan.set_points_batch(counts, xyz)
+    out = torch.empty_like(dens)
+    for _ in range(warmup + 1):                       # capture, then replays
+        plan.evaluate(dens, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.evaluate(dens, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    n_total = int(sum(counts))
+    res["laplace_sp_batch64_rhs16_p8_s2000"]["graph_replay"] = {
+        "ms_per_replay": ms, "targets_per_s": n_total / (ms * 1e-3),
+        "target_rhs_per_s": n_total * dens.shape[0] / (ms * 1e-3),
+        "note": "one hipGraph replay of the whole evaluation of 64 problems x 16 RHS (points set once)"}
+    log(f"batched forest, graph replay: {ms:.2f} ms, {n_total / (ms * 1e-3):.3e} targets/s")
+    plan.close()
+    del out
     del probs, xyz, dens
     pb = W.stokes_tp_clustered()
     xyz = torch.as_tensor(pb.points, device="cuda")
@@ -202,6 +223,30 @@ def paper_configs(pk, torch, W, ps, steps=2, warmup=1):
     return res
 
 
+def cpu_baseline_runs(pb, repeats=3, one_core_leaves=3):
+    """The oracle on the whole workload, `repeats` times on every host core (the median is the
+    reported value), and once on one core over a bounded sample (tree, lists and the whole upward
+    pass, then `one_core_leaves` random leaves, scaled to N)."""
+    from threadpoolctl import threadpool_limits
+    runs = []
+    first = None
+    for i in range(repeats):
+        cb, fs = cpu_baseline(pb)
+        runs.append(cb)
+        if first is None:
+            first = fs
+        log(f"cpu baseline run {i + 1}: {cb['value']:.4g} targets/s")
+    med = sorted(runs, key=lambda r: r["value"])[len(runs) // 2]
+    rec = dict(med)
+    rec["runs_targets_per_s"] = [r["value"] for r in runs]
+    rec["sample"] = f"median of {repeats} runs of " + med["sample"]
+    with threadpool_limits(limits=1):
+        one, _ = cpu_baseline(pb, n_leaves_sample=one_core_leaves)
+    rec["one_core"] = {"value": one["value"], "unit": "targets/s", "cores": 1, "sample": one["sample"]}
+    log(f"cpu baseline, one core: {one['value']:.4g} targets/s")
+    return rec, first
+
+
 def cpu_baseline(pb, n_leaves_sample=None):
     """The oracle (plain FP64 CPU KIFMM) on the same workload: every leaf by default (the whole job),
     else a bounded sample of n_leaves_sample random leaves scaled to N."""
@@ -231,7 +276,9 @@ def cpu_baseline(pb, n_leaves_sample=None):
     n_sample = sum(f.tree.end[b] - f.tree.begin[b] for b in pick)
     # whole-job time: tree + upward once, downward/leaf work (scaled by points for a sample)
     t_full = t_tree + t_up + max(t_sample, 0.0) * (pb.n / n_sample)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    from threadpoolctl import threadpool_info
+    cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or
+                [int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))])
     if whole:
         sample = (f"the whole workload: tree+lists and upward pass ({t_tree + t_up:.1f} s), downward pass and "
                   f"leaf sums for all {n_sample} targets ({t_sample:.1f} s); operator precompute "
@@ -317,6 +364,10 @@ def main():
                                     "near_pairs")},
         "accuracy": {},
         "roofline": roofline,
+        "launch_choices": {"near_workgroups_per_cu": st["tune_near_wpc"], "rhs_per_near_pass": st["tune_rb_near"],
+                           "rhs_per_s2m_pass": st["tune_rb_s2m"],
+                           "source": ("autotuner record in " + os.path.relpath(pk.TUNING_FILE, ROOT)
+                                      if os.path.exists(pk.TUNING_FILE) else "library defaults")},
     }
     if r64 is not None:
         rec["fp64"] = {"value": pb.n / (r64["s_total"] / args.steps), "ms_per_step": r64["s_total"] / args.steps * 1e3,
@@ -331,7 +382,7 @@ def main():
         rec["paper_configs"] = paper_configs(pk, torch, W, [int(x) for x in args.paper.split(",")])
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cb, (f, sub) = cpu_baseline(pb)
+        cb, (f, sub) = cpu_baseline_runs(pb)
         rec["cpu_baseline"] = cb
         num64 = nummx = den = 0.0
         for b, ref in sub.items():

@@ -13,8 +13,8 @@
  * paper's example kernels (Section 2, Eq. kexamples):
  *     PKIFMM_LAPLACE     K(r) = 1 / (4 pi |r|)                          k = 1
  *     PKIFMM_STOKES      K(r) = (1/(8 pi)) (I/|r| + r r^T / |r|^3)       k = 3
- * A pair at exactly zero separation contributes nothing.  Sources are also the
- * targets.  Periodic sums that only converge conditionally are taken in the
+ * A pair at exactly zero separation contributes nothing.  The targets are the
+ * sources unless a separate target set is given (pkifmm_set_points).  Periodic sums that only converge conditionally are taken in the
  * following sense: singly (SP) and doubly (DP) periodic -- the limit of
  * symmetric image truncations, which requires zero net density (Section 2,
  * Eq. compatcondition, neutrality); each image term is taken relative to the
@@ -26,7 +26,12 @@
  * tree: an octree covers the original box and its images with |p|_inf <= 1;
  * the far field (|p|_inf >= 2) is one precomputed periodic operator applied to
  * the root's upward equivalent density and added to the root's downward check
- * potential.
+ * potential.  For triply periodic Laplace the zero-mean sum carries a uniform
+ * neutralising background (the one-component-plasma remark of the paper's
+ * Discussions): its far kernel is harmonic plus |y - c|^2 / 6 in the source
+ * position, a part no equivalent density reproduces, so the constant it adds,
+ * (sum_s phi_s |y_s - c|^2 - sum_j phi^{B0,u}_j |y_j - c|^2) / 6 (c the box
+ * centre), is added to every target.
  *
  * Conventions for every call:
  *   * return value: 0 (PKIFMM_OK) or a negative status code below;
@@ -39,6 +44,7 @@
 #ifndef PKIFMM_H
 #define PKIFMM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -87,6 +93,8 @@ typedef struct pkifmm_plan pkifmm_plan;
 #define PKIFMM_ERR_NO_POINTS -7      /* evaluate before set_points */
 #define PKIFMM_ERR_NUMERICS -8       /* operator construction failed its self-check */
 #define PKIFMM_ERR_CAPACITY -9       /* pkifmm_evaluate_noalloc: the workspace exceeds its static array */
+#define PKIFMM_ERR_CACHE_CORRUPT -10 /* an operator cache file fails its checks (magic, version, key,
+                                        sizes, checksum, or the solves' backward-error check) */
 
 typedef struct {
     int kernel;                  /* PKIFMM_LAPLACE or PKIFMM_STOKES */
@@ -96,11 +104,42 @@ typedef struct {
     int precision;               /* PKIFMM_FP64 or PKIFMM_MIXED */
     double box_length;           /* L > 0 */
     double svd_rel_threshold;    /* singular values <= this * s_max are dropped from the
-                                    check-to-equivalent solves (Appendix B's (V S^+)(U^T q));
-                                    0 selects 2^-52 * dim(A), the numerical-rank criterion of
-                                    Table 1: a bare 2^-52 keeps directions at the rounding level
-                                    of A, along which the solution is noise */
+                                    check-to-equivalent solves (Appendix B's (V S^+)(U^T q), whose
+                                    cutoff the paper leaves free); 0 selects 1e-11.  Below it a
+                                    solve turns the rounding of its input (sums with cancellation,
+                                    tens of ulps) into equivalent-density noise and gains no
+                                    accuracy: against the exact periodic sums, Stokes TP p = 8
+                                    measures 5.2e-6 at 1e-11 and 1.9e-5 at Table 1's rank
+                                    criterion 2^-52 dim(A) (p = 10: 9.6e-8 and 1.3e-7; p = 12:
+                                    4.0e-9 and 3.1e-9), while rounding-level changes of the solve
+                                    inputs move the result 85, 20 and 5 times less */
     unsigned flags;              /* an OR of the PKIFMM_* flags below; other bits are invalid */
+    const char *operator_cache_dir;  /* NULL or "": no cache.  Else a writable directory holding the
+                                    costly Stage-1 operators (the solve factors U^T, V S^+ and the
+                                    periodic root operator, which depend on kernel, periodic axes, p
+                                    and the solve cutoff only; the paper computes them once for all
+                                    simulations, Section 2.2): pkifmm_plan_create loads them from
+                                    there when present (and re-checks the solves) and stores them
+                                    otherwise; one file per key, written under a temporary name and
+                                    renamed.  Read during pkifmm_plan_create only */
+    void *alloc_ctx;             /* passed to alloc and free */
+    void *(*alloc)(void *ctx, size_t bytes, void *stream);   /* NULL (with free NULL): hipMalloc;
+                                    else every device buffer the plan owns comes from it (operator
+                                    tables, tree, work lists, workspace), 256-byte aligned, usable on
+                                    any stream once returned; NULL return = out of memory.  stream is
+                                    the stream of the library call that asks (NULL in plan creation) */
+    void (*free)(void *ctx, void *ptr, void *stream);   /* releases what alloc returned, only once no
+                                    work of the plan uses it any more */
+    const char *tuning_file;     /* NULL or "": default launch choices.  Else a text file of records
+                                    written by pkifmm_autotune; the records of this device's
+                                    architecture, kernel, periodic axes, p and precision are used for
+                                    the evaluations with their n_rhs.  Read during plan creation only */
+    int near_layers;             /* 0 or 1: the tree covers the images |p|_inf <= 1 and the far-field
+                                    operator the rest.  2 or 3 (singly and triply periodic sums): the
+                                    near field of Algorithm 2 spans l layers of images (Section 3.6,
+                                    Table 4): the root's images with 2 <= |p|_inf <= l act on it by
+                                    M2L (they are the root's V list) and the far-field operator covers
+                                    |p|_inf > l.  The results agree with l = 1 to the FMM's accuracy */
 } pkifmm_config;
 
 #define PKIFMM_SKIP_CHECKS 1u    /* skip the SP/DP neutrality check (no device-to-host read) */
@@ -147,9 +186,14 @@ typedef struct {
     int close_points;            /* mixed form: 1 if pkifmm_set_points found points of different
                                     leaves or images closer than 2^-27 L in every coordinate (every
                                     near-field pair then guards zero separations), else 0 */
+    int tune_near_wpc;           /* launch choices of the last evaluation (pkifmm_autotune): near-field */
+    int tune_rb_near;            /* workgroups per compute unit; right-hand sides per geometry pass of */
+    int tune_rb_s2m;             /* the near field and of the points-to-surface sums (0: the most) */
+    double tune_ms;              /* pkifmm_autotune: the best evaluation time it measured */
 } pkifmm_stats;
 
-/* Fill `cfg` with defaults: Laplace, free space, p = 8, s = 64, FP64, L = 1. */
+/* Fill `cfg` with defaults: Laplace, free space, p = 8, s = 64, FP64, L = 1, no operator cache,
+ * hipMalloc. */
 int pkifmm_config_default(pkifmm_config *cfg);
 
 /*
@@ -159,17 +203,23 @@ int pkifmm_config_default(pkifmm_config *cfg);
  * periodic root operator K^{P,F} over images |p|_inf >= 2.  Runs on the
  * current HIP device; blocking.  *out receives a plan owned by the caller
  * (release with pkifmm_plan_destroy).
- * Errors (*out is then NULL): INVALID_ARG (NULL argument, a field out of range or
- * unknown flag bits), NUMERICS (an operator failed its backward-error self-check),
- * OOM, HIP.
+ * Errors (*out is then NULL): INVALID_ARG (NULL argument, a field out of range,
+ * unknown flag bits, only one of alloc and free), CACHE_CORRUPT (the operator cache file
+ * for this key exists but fails its checks; it is left as it is), NUMERICS (a solve failed its backward-error self-check: on the kept
+ * subspace, ||A (V S^+)(U^T A x) - A x|| must stay below 1e-13 s_max ||x||), OOM, HIP.
  */
 int pkifmm_plan_create(const pkifmm_config *cfg, pkifmm_plan **out);
 
 /*
  * Wrap, validate, Morton-sort the points and build the adaptive octree and
  * the periodic U/V/W/X lists.
- *   xyz: device, [n][3] float64, row-major, n >= 0 (copied; may be freed
- *        after the call returns).
+ *   src_xyz: device, [n_src][3] float64, row-major, n_src >= 0: the sources;
+ *   trg_xyz: NULL (with n_trg = 0): the targets are the sources; else device
+ *            [n_trg][3], n_trg >= 0 target points apart from the sources (Section 2's
+ *            problem statement: T targets, S sources).  The octree is then built over the
+ *            union (a box holding more than s points of either kind is split), a target
+ *            carries no density, and every leaf keeps its sources before its targets;
+ *   both are copied and may be freed after the call returns.
  * Waits for the plan's last evaluation to finish (on whatever stream it ran) and
  * synchronises `stream` (the tree topology is built on the host).  In the mixed form it
  * also looks for points of different leaves, or a point and another point's periodic
@@ -178,7 +228,8 @@ int pkifmm_plan_create(const pkifmm_config *cfg, pkifmm_plan **out);
  * cost of one instruction per pair).
  * Errors: OUT_OF_BOX (nothing is kept), INVALID_ARG, OOM, HIP.
  */
-int pkifmm_set_points(pkifmm_plan *plan, int64_t n, const double *xyz, void *stream);
+int pkifmm_set_points(pkifmm_plan *plan, int64_t n_src, const double *src_xyz, int64_t n_trg,
+                      const double *trg_xyz, void *stream);
 
 /*
  * Several independent problems in one plan (the batched form): problem i owns
@@ -187,8 +238,9 @@ int pkifmm_set_points(pkifmm_plan *plan, int64_t n, const double *xyz, void *str
  * its own octree and lists; pkifmm_evaluate then evaluates every problem in
  * one launch sequence, with densities and potentials packed the same way
  * ([n_rhs][sum counts][k]).  A problem's result does not depend on the other
- * problems in the batch (bitwise).  counts: host, n_problems entries >= 0.
- * pkifmm_set_points(plan, n, xyz, s) is this call with one problem.
+ * problems in the batch (bitwise).  counts: host, n_problems entries >= 0.  The targets
+ * are the sources.  pkifmm_set_points(plan, n, xyz, 0, NULL, s) is this call with one
+ * problem.
  * Errors: as pkifmm_set_points.
  */
 int pkifmm_set_points_batch(pkifmm_plan *plan, int n_problems, const int64_t *counts, const double *xyz,
@@ -196,8 +248,9 @@ int pkifmm_set_points_batch(pkifmm_plan *plan, int n_problems, const int64_t *co
 
 /*
  * Evaluate the periodic sum for n_rhs densities on the current points.
- *   density:   device, [n_rhs][n][k] float64 (k = 1 Laplace, 3 Stokes), input order
- *   potential: device, [n_rhs][n][k] float64, overwritten, input order
+ *   density:   device, [n_rhs][n_src][k] float64 (k = 1 Laplace, 3 Stokes), source order
+ *   potential: device, [n_rhs][n_trg][k] float64 (n_trg = n_src when the targets are the
+ *              sources), overwritten, target order
  * Work is enqueued on `stream` (the near field and the X list on two
  * library-owned streams that fork from and join back into `stream`, so
  * completion of `stream` covers all of it); the call returns after enqueueing
@@ -208,9 +261,9 @@ int pkifmm_set_points_batch(pkifmm_plan *plan, int n_problems, const int64_t *co
  * different n_rhs than the previous one first waits on the host for it to finish (its work
  * lists are rebuilt).  The output is float64 in every
  * precision mode.  Densities are not checked: a non-finite density makes non-finite
- * potentials wherever its terms reach.  density and potential may be the same
- * buffer (the first kernel reads every density into library storage, the last writes
- * the potentials); partly overlapping ranges are not supported.
+ * potentials wherever its terms reach.  When the targets are the sources, density and
+ * potential may be the same buffer (the first kernel reads every density into library
+ * storage, the last writes the potentials); partly overlapping ranges are not supported.
  * Errors: NO_POINTS, INVALID_ARG, INCOMPATIBLE, OOM, HIP.
  */
 int pkifmm_evaluate(pkifmm_plan *plan, int n_rhs, const double *density, double *potential,
@@ -240,6 +293,35 @@ int pkifmm_evaluate(pkifmm_plan *plan, int n_rhs, const double *density, double 
 int pkifmm_evaluate_noalloc(pkifmm_plan *plan, int n_rhs, const double *density, double *potential,
                             void *stream);
 
+/*
+ * Copy the factors of one check-to-equivalent solve (Section 3.1, Appendix B: the solution
+ * is (V S^+)(U^T q)) to host arrays, for inspection.
+ *   which: 0 upward (check: outer surface, equivalent: inner), 1 downward (check: inner,
+ *          equivalent: outer), both for the unit box centred at the origin, raw kernels
+ *          1/|r| and I/|r| + r r^T/|r|^3 (no 1/(4 pi), 1/(8 pi)), surface points ordered
+ *          lexicographically, k components per point;
+ *   rank:  out, the singular values kept (r);
+ *   Ut:    NULL or host [kn][r] column-major (= U^T, r x kn), VS: NULL or host [r][kn]
+ *          column-major (= V S^+, kn x r), kn = k n_surf.
+ * Errors: INVALID_ARG (NULL plan or rank, unknown `which`).
+ */
+int pkifmm_get_solve_factors(const pkifmm_plan *plan, int which, int *rank, double *Ut, double *VS);
+
+/*
+ * Choose the launch parameters of the evaluation for the current points and n_rhs by timing it
+ * (coordinate descent, median of 3 timed evaluations per candidate): the near field's
+ * workgroups per compute unit, and the right-hand sides that share one pass over the geometry
+ * in the near field and in the points-to-surface sums.  Only choices that leave every result
+ * bit unchanged are tuned (each sum is formed in the same order whichever is taken).  The plan
+ * keeps the best choice for this n_rhs; with tuning_file non-NULL its record (architecture,
+ * kernel, periodic axes, p, precision, n_rhs) is added to or replaced in that file, which
+ * pkifmm_config::tuning_file reads at plan creation.  density/potential as pkifmm_evaluate
+ * (potential is overwritten).  Synchronises `stream`.
+ * Errors: NO_POINTS, INVALID_ARG (also: the tuning file could not be written), OOM, HIP.
+ */
+int pkifmm_autotune(pkifmm_plan *plan, int n_rhs, const double *density, double *potential, void *stream,
+                    const char *tuning_file);
+
 /* Tree and list sizes of the current points and the last call timings.  With
  * PKIFMM_PHASE_TIMING this waits for the recorded events of every evaluation since
  * the previous call, reports their per-phase averages and starts a new window.
@@ -248,7 +330,9 @@ int pkifmm_get_stats(pkifmm_plan *plan, pkifmm_stats *out);
 
 /*
  * Copy the tree to host arrays for inspection (each may be NULL):
- *   perm   [n]        int64: sorted position -> input index
+ *   perm   [n]        int64: sorted position -> input index (with separate targets, n =
+ *                     n_src + n_trg and target i has index n_src + i; each leaf lists its
+ *                     sources first, then its targets, both in Morton-key order)
  *   boxes  [nbox][8]  int32: level, ix, iy, iz, begin, end, parent, first child or -1
  * Boxes are numbered level by level, in Morton order within a level (for a
  * batch: level by level, problems in order within a level, Morton order
@@ -284,7 +368,15 @@ int pkifmm_get_list(const pkifmm_plan *plan, char which, int64_t *offsets, int32
 int pkifmm_host_topology(const uint64_t *sorted_keys, int64_t n, int max_pts_per_leaf, unsigned periodic_mask,
                          char which, int64_t *n_boxes, int32_t *boxes, int64_t *offsets, int32_t *entries);
 
-/* Release the plan and every buffer it owns.  NULL is accepted. */
+/*
+ * Check an operator cache file (as pkifmm_plan_create reads it: magic, version, sizes,
+ * checksum) on the host alone; no GPU is touched.
+ * Errors: INVALID_ARG (NULL path or no such file), CACHE_CORRUPT.
+ */
+int pkifmm_operator_cache_check(const char *path);
+
+/* Release the plan and every buffer it owns (waiting for its last evaluation first).
+ * NULL is accepted. */
 int pkifmm_plan_destroy(pkifmm_plan *plan);
 
 /* Static text for a status code. */

@@ -90,7 +90,8 @@ M2L_OFFSETS = [d for d in itertools.product(range(-3, 4), repeat=3) if max(abs(c
 class Operators:
     """Unit-box operators for one (kernel, periodicity, p)."""
 
-    def __init__(self, kernel: int, mask: int, p: int, rel_threshold: Optional[float] = None):
+    def __init__(self, kernel: int, mask: int, p: int, rel_threshold: Optional[float] = None,
+                 near_layers: int = 1):
         self.kernel, self.mask, self.p = kernel, mask, p
         self.k = kdim(kernel)
         u = unit_surface(p)
@@ -103,7 +104,8 @@ class Operators:
         self.m2m = [K(self.outer, octant_offset(o) + 0.5 * self.inner) for o in range(8)]
         self.l2l = [K(octant_offset(o) + 0.5 * self.inner, self.outer) for o in range(8)]
         self._m2l: Dict[tuple, np.ndarray] = {}
-        self.mroot = periodic.far_kernel_matrix(kernel, mask, self.inner + 0.5, self.inner + 0.5)
+        self.mroot = periodic.far_kernel_matrix(kernel, mask, self.inner + 0.5, self.inner + 0.5,
+                                                near_layers=near_layers)
 
     def m2l(self, delta) -> np.ndarray:
         delta = tuple(int(c) for c in delta)
@@ -116,10 +118,11 @@ class Operators:
 _OPS_CACHE: Dict[tuple, Operators] = {}
 
 
-def operators(kernel: int, mask: int, p: int, rel_threshold: Optional[float] = None) -> Operators:
-    key = (kernel, mask, p, rel_threshold)
+def operators(kernel: int, mask: int, p: int, rel_threshold: Optional[float] = None,
+              near_layers: int = 1) -> Operators:
+    key = (kernel, mask, p, rel_threshold, near_layers)
     if key not in _OPS_CACHE:
-        _OPS_CACHE[key] = Operators(kernel, mask, p, rel_threshold)
+        _OPS_CACHE[key] = Operators(kernel, mask, p, rel_threshold, near_layers)
     return _OPS_CACHE[key]
 
 
@@ -128,7 +131,7 @@ class KIFMM:
 
     def __init__(self, kernel: int, mask: int, p: int, s: int, points: np.ndarray,
                  rel_threshold: Optional[float] = None, box_length: float = 1.0,
-                 targets: Optional[np.ndarray] = None):
+                 targets: Optional[np.ndarray] = None, near_layers: int = 1):
         """points: the sources (also the targets unless `targets` is given).  With separate
         targets (Section 2's problem: T targets, S sources) the tree is built over the union of
         both sets, points [0, S) being the sources and [S, S + T) the targets; a target-only point
@@ -149,8 +152,8 @@ class KIFMM:
             pts = np.concatenate([pts, trg])
         self.u = otree.wrap(pts / self.L, mask)
         self.tree = otree.build_tree(self.u, s)
-        self.lists = otree.build_lists(self.tree, mask)
-        self.ops = operators(kernel, mask, p, rel_threshold)
+        self.lists = otree.build_lists(self.tree, mask, near_layers)
+        self.ops = operators(kernel, mask, p, rel_threshold, near_layers)
         self.sorted_pts = self.u[self.tree.perm]
 
     # -- W/X lists: the cheaper of the surface operator and the direct sum
@@ -265,10 +268,8 @@ class KIFMM:
         qd = {b: np.zeros(kn) for b in need}
         groups: Dict[tuple, list] = {}
         for b in need:
-            if b == 0:
-                continue
             cb = np.array(t.coord[b])
-            for (a, p) in self.lists.V[b]:
+            for (a, p) in self.lists.V.get(b, []):   # the root's: its image ring (near_layers > 1)
                 delta = tuple(int(c) for c in np.array(t.coord[a]) + np.array(p) * (1 << t.level[b]) - cb)
                 groups.setdefault(delta, []).append((b, a))
         for delta, pairs in groups.items():

@@ -168,7 +168,10 @@ class Lists:
     X: Dict[int, List[Tuple[int, Tuple[int, int, int]]]]
 
 
-def build_lists(t: Tree, periodic_mask: int) -> Lists:
+def build_lists(t: Tree, periodic_mask: int, near_layers: int = 1) -> Lists:
+    """The adaptive lists.  With near_layers l > 1 (Section 3.6: the near field spans l layers of
+    images) the root also gets a V list: its own images with 2 <= |p|_inf <= l along the periodic
+    axes, which act on it through its upward equivalent density."""
     lookup = {(t.level[b],) + tuple(t.coord[b]): b for b in range(t.nbox)}
 
     def adj(a, p, b):
@@ -239,4 +242,7 @@ def build_lists(t: Tree, periodic_mask: int) -> Lists:
             X[b].append((a, (-p[0], -p[1], -p[2])))
     for b in X:
         X[b] = sorted(X[b])
+    if near_layers > 1 and periodic_mask:
+        rng = [range(-near_layers, near_layers + 1) if periodic_mask & (1 << c) else (0,) for c in range(3)]
+        V[0] = sorted((0, p) for p in itertools.product(*rng) if max(abs(c) for c in p) >= 2)
     return Lists(U=U, V=V, W=W, X=X)

@@ -14,6 +14,8 @@ from typing import Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpkifmm.so")
+# launch choices measured by pkifmm_autotune on this project's target device (committed records)
+TUNING_FILE = os.path.join(HERE, "tuning", "launch_choices.txt")
 
 LAPLACE, STOKES = 1, 2
 PERIODIC_X, PERIODIC_Y, PERIODIC_Z = 1, 2, 4
@@ -25,19 +27,25 @@ FAR_STEP_D = 8
 
 OK = 0
 ERR_INVALID_ARG, ERR_OUT_OF_BOX, ERR_INCOMPATIBLE, ERR_UNSUPPORTED = -1, -2, -3, -4
-ERR_OOM, ERR_HIP, ERR_NO_POINTS, ERR_NUMERICS, ERR_CAPACITY = -5, -6, -7, -8, -9
+ERR_OOM, ERR_HIP, ERR_NO_POINTS, ERR_NUMERICS, ERR_CAPACITY, ERR_CACHE_CORRUPT = -5, -6, -7, -8, -9, -10
 
 EXPORTED = ["pkifmm_config_default", "pkifmm_plan_create", "pkifmm_set_points", "pkifmm_set_points_batch",
             "pkifmm_evaluate", "pkifmm_evaluate_noalloc",
             "pkifmm_get_stats", "pkifmm_get_tree", "pkifmm_get_list", "pkifmm_plan_destroy",
-            "pkifmm_status_string", "pkifmm_last_error", "pkifmm_host_topology"]
+            "pkifmm_status_string", "pkifmm_last_error", "pkifmm_host_topology", "pkifmm_get_solve_factors", "pkifmm_operator_cache_check", "pkifmm_autotune"]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class pkifmm_config(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int), ("periodic_mask", ctypes.c_uint), ("p", ctypes.c_int),
                 ("max_pts_per_leaf", ctypes.c_int), ("precision", ctypes.c_int),
                 ("box_length", ctypes.c_double), ("svd_rel_threshold", ctypes.c_double),
-                ("flags", ctypes.c_uint)]
+                ("flags", ctypes.c_uint), ("operator_cache_dir", ctypes.c_char_p),
+                ("alloc_ctx", ctypes.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("tuning_file", ctypes.c_char_p), ("near_layers", ctypes.c_int)]
 
 
 class pkifmm_stats(ctypes.Structure):
@@ -49,7 +57,8 @@ class pkifmm_stats(ctypes.Structure):
                 ("svd_rank_up", ctypes.c_int), ("svd_rank_down", ctypes.c_int),
                 ("ms_set_points", ctypes.c_double), ("ms_evaluate", ctypes.c_double),
                 ("n_timed", ctypes.c_int), ("ms_phase", ctypes.c_double * 5),
-                ("close_points", ctypes.c_int)]
+                ("close_points", ctypes.c_int), ("tune_near_wpc", ctypes.c_int), ("tune_rb_near", ctypes.c_int),
+                ("tune_rb_s2m", ctypes.c_int), ("tune_ms", ctypes.c_double)]
 
 PHASES = ["near", "up", "m2l", "down", "leaf"]
 
@@ -68,7 +77,7 @@ def lib():
         sig = {
             "pkifmm_config_default": (i32, [ctypes.POINTER(pkifmm_config)]),
             "pkifmm_plan_create": (i32, [ctypes.POINTER(pkifmm_config), ctypes.POINTER(vp)]),
-            "pkifmm_set_points": (i32, [vp, i64, vp, vp]),
+            "pkifmm_set_points": (i32, [vp, i64, vp, i64, vp, vp]),
             "pkifmm_set_points_batch": (i32, [vp, i32, vp, vp, vp]),
             "pkifmm_evaluate": (i32, [vp, i32, vp, vp, vp]),
             "pkifmm_evaluate_noalloc": (i32, [vp, i32, vp, vp, vp]),
@@ -79,6 +88,9 @@ def lib():
             "pkifmm_status_string": (ctypes.c_char_p, [i32]),
             "pkifmm_last_error": (ctypes.c_char_p, [vp]),
             "pkifmm_host_topology": (i32, [vp, i64, i32, ctypes.c_uint, ctypes.c_char, vp, vp, vp, vp]),
+            "pkifmm_get_solve_factors": (i32, [vp, i32, ctypes.POINTER(i32), vp, vp]),
+            "pkifmm_operator_cache_check": (i32, [ctypes.c_char_p]),
+            "pkifmm_autotune": (i32, [vp, i32, vp, vp, vp, ctypes.c_char_p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -126,18 +138,44 @@ class Plan:
 
     def __init__(self, kernel: int, periodic_mask: int, p: int, max_pts_per_leaf: int,
                  precision: int = FP64, box_length: float = 1.0,
-                 svd_rel_threshold: float = 0.0, flags: int = 0):
+                 svd_rel_threshold: float = 0.0, flags: int = 0,
+                 operator_cache_dir: Optional[str] = None, torch_allocator: bool = False,
+                 tuning_file: Optional[str] = TUNING_FILE, near_layers: int = 1):
+        """torch_allocator: the plan's device buffers come from PyTorch's caching allocator
+        (through the C-ABI's alloc/free callbacks) instead of hipMalloc.  tuning_file: the
+        autotuner's records read at plan creation (None: the library's default choices)."""
         L = lib()
         cfg = pkifmm_config()
         _check(L.pkifmm_config_default(ctypes.byref(cfg)))
         cfg.kernel, cfg.periodic_mask, cfg.p = kernel, periodic_mask, p
         cfg.max_pts_per_leaf, cfg.precision = max_pts_per_leaf, precision
         cfg.box_length, cfg.svd_rel_threshold, cfg.flags = box_length, svd_rel_threshold, flags
+        cfg.near_layers = near_layers
+        if operator_cache_dir:
+            cfg.operator_cache_dir = os.fsencode(operator_cache_dir)
+        if tuning_file and os.path.exists(tuning_file):
+            cfg.tuning_file = os.fsencode(tuning_file)
+        self._callbacks = None
+        if torch_allocator:
+            import torch
+            dev = torch.cuda.current_device()
+
+            def _alloc(ctx, nbytes, stream):
+                try:
+                    return torch.cuda.caching_allocator_alloc(nbytes, dev, stream or 0)
+                except Exception:
+                    return None                  # the library reports out of memory
+
+            def _free(ctx, ptr, stream):
+                torch.cuda.caching_allocator_delete(ptr)
+            self._callbacks = (ALLOC_FN(_alloc), FREE_FN(_free))   # kept alive with the plan
+            cfg.alloc, cfg.free = self._callbacks
         h = ctypes.c_void_p()
         _check(L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
         self.k = 1 if kernel == LAPLACE else 3
-        self.n = 0
+        self.n_surf = 6 * (p - 1) ** 2 + 2
+        self.n = self.n_out = 0
 
     def close(self):
         if getattr(self, "_h", None):
@@ -150,16 +188,25 @@ class Plan:
         except Exception:
             pass
 
-    def set_points(self, xyz, stream=None):
-        """xyz: torch float64 CUDA tensor [n, 3] (input order)."""
+    def set_points(self, xyz, targets=None, stream=None):
+        """xyz: torch float64 CUDA tensor [n_src, 3], the sources (input order); targets: None (the
+        targets are the sources) or a float64 CUDA tensor [n_trg, 3] of separate targets."""
         import torch
         _check_points(torch, xyz)
         xyz = xyz.contiguous()
-        if stream is not None:   # the points (or their contiguous copy) come from torch's current stream
+        trg_ptr, n_trg = None, 0
+        if targets is not None:
+            _check_points(torch, targets)
+            targets = targets.contiguous()
+            trg_ptr, n_trg = ctypes.c_void_p(targets.data_ptr()), targets.shape[0]
+            if n_trg == 0:   # an empty separate target set still needs a non-NULL pointer
+                trg_ptr = ctypes.c_void_p(xyz.data_ptr() or 1)
+        if stream is not None:   # the points (or their contiguous copies) come from torch's current stream
             stream.wait_stream(torch.cuda.current_stream())
-        _check(lib().pkifmm_set_points(self._h, xyz.shape[0], ctypes.c_void_p(xyz.data_ptr()),
+        _check(lib().pkifmm_set_points(self._h, xyz.shape[0], ctypes.c_void_p(xyz.data_ptr()), n_trg, trg_ptr,
                                        _stream_ptr(stream)), self._h)
         self.n = xyz.shape[0]
+        self.n_out = n_trg if targets is not None else self.n
 
     def set_points_batch(self, counts, xyz, stream=None):
         """counts: point count of each problem; xyz: float64 CUDA [sum(counts), 3], problems packed."""
@@ -175,16 +222,17 @@ class Plan:
             stream.wait_stream(torch.cuda.current_stream())
         _check(lib().pkifmm_set_points_batch(self._h, len(c), c.ctypes.data, ctypes.c_void_p(xyz.data_ptr()),
                                              _stream_ptr(stream)), self._h)
-        self.n = xyz.shape[0]
+        self.n = self.n_out = xyz.shape[0]
 
     def evaluate(self, density, out=None, stream=None, noalloc=False):
-        """density: float64 CUDA [R, n, k] (or [n, k]); returns potentials of the same shape.
+        """density: float64 CUDA [R, n_src, k] (or [n_src, k]); returns the potentials at the targets,
+        [R, n_trg, k] (or [n_trg, k]; n_trg = n_src when the targets are the sources).
 
-        out, if given, is a contiguous float64 CUDA tensor of the density's shape; it may be the
-        density tensor itself (the pass reads every density before it writes a potential).
-        noalloc=True calls pkifmm_evaluate_noalloc (the library allocates nothing; its workspace is
-        a static device array): give a contiguous density and an `out` so that this binding
-        allocates nothing either."""
+        out, if given, is a contiguous float64 CUDA tensor of that shape; when the targets are the
+        sources it may be the density tensor itself (the pass reads every density before it writes
+        a potential).  noalloc=True calls pkifmm_evaluate_noalloc (the library allocates nothing;
+        its workspace is a static device array): give a contiguous density and an `out` so that
+        this binding allocates nothing either."""
         import torch
         if density.dim() not in (2, 3):
             raise ValueError("density must be [n, k] or [R, n, k]")
@@ -193,12 +241,13 @@ class Plan:
         if not (d.is_cuda and d.dtype == torch.float64 and d.shape[1] == self.n and d.shape[2] == self.k):
             raise ValueError(f"density must be float64 on the GPU with shape [R, {self.n}, {self.k}]")
         d = d.contiguous()
+        shape = (d.shape[0], self.n_out, self.k)
         if out is None:
-            res = torch.empty_like(d)
+            res = torch.empty(shape, dtype=torch.float64, device=d.device)
         else:
-            if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
-                    and tuple(out.shape) == tuple(density.shape)):
-                raise ValueError("out must be a contiguous float64 GPU tensor of the density's shape")
+            want = shape[1:] if squeeze else shape
+            if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and tuple(out.shape) == want):
+                raise ValueError(f"out must be a contiguous float64 GPU tensor of shape {want}")
             res = out[None] if squeeze else out
         if stream is not None:
             # the pass runs on `stream`: it starts after the work queued so far on torch's current
@@ -212,6 +261,20 @@ class Plan:
                   _stream_ptr(stream)), self._h)
         return res[0] if squeeze else res
 
+    def autotune(self, density, tuning_file: Optional[str] = None, stream=None):
+        """Time the evaluation of `density` ([R, n_src, k]) under the bit-neutral launch choices and
+        keep the fastest for this n_rhs (pkifmm_autotune); with tuning_file, record it there."""
+        import torch
+        d = density[None] if density.dim() == 2 else density
+        d = d.contiguous()
+        res = torch.empty((d.shape[0], self.n_out, self.k), dtype=torch.float64, device=d.device)
+        path = os.fsencode(tuning_file) if tuning_file else None
+        _check(lib().pkifmm_autotune(self._h, d.shape[0], ctypes.c_void_p(d.data_ptr()),
+                                     ctypes.c_void_p(res.data_ptr()), _stream_ptr(stream), path), self._h)
+        st = self.stats()
+        return {"near_wpc": st["tune_near_wpc"], "rb_near": st["tune_rb_near"], "rb_s2m": st["tune_rb_s2m"],
+                "ms": st["tune_ms"]}
+
     def stats(self) -> dict:
         st = pkifmm_stats()
         _check(lib().pkifmm_get_stats(self._h, ctypes.byref(st)), self._h)
@@ -219,14 +282,28 @@ class Plan:
         out["ms_phase"] = {PHASES[i]: st.ms_phase[i] for i in range(len(PHASES))}
         return out
 
+    def solve_factors(self, which: int):
+        """(U^T [r, kn], V S^+ [kn, r]) of the upward (0) or downward (1) check-to-equivalent solve."""
+        import numpy as np
+        r = ctypes.c_int()
+        L = lib()
+        _check(L.pkifmm_get_solve_factors(self._h, which, ctypes.byref(r), None, None), self._h)
+        kn = self.k * self.n_surf
+        ut = np.zeros((kn, r.value))          # column-major r x kn  = row-major kn x r
+        vs = np.zeros((r.value, kn))          # column-major kn x r  = row-major r x kn
+        _check(L.pkifmm_get_solve_factors(self._h, which, ctypes.byref(r), ut.ctypes.data, vs.ctypes.data), self._h)
+        return ut.T.copy(), vs.T.copy()
+
     def tree(self):
-        """(perm [n] int64, boxes [nbox, 8] int32) as numpy arrays."""
+        """(perm [n] int64, boxes [nbox, 8] int32) as numpy arrays; n counts every point the tree
+        holds (with separate targets: sources and targets)."""
         import numpy as np
         st = self.stats()
-        perm = np.zeros(max(self.n, 1), dtype=np.int64)
+        n = st["n_points"]
+        perm = np.zeros(max(n, 1), dtype=np.int64)
         boxes = np.zeros((st["n_boxes"], 8), dtype=np.int32)
         _check(lib().pkifmm_get_tree(self._h, perm.ctypes.data, boxes.ctypes.data), self._h)
-        return perm[:self.n], boxes
+        return perm[:n], boxes
 
     def lists(self, which: str):
         """(offsets [nbox+1] int64, entries [m, 4] int32) of the U, V, W or X list."""

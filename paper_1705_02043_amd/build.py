@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpkifmm.so")
 SOURCES = ["kernels_points.hip", "kernels_p2p.hip", "kernels_gemm.hip", "kernels_oz.hip", "kernels_ops.hip", "plan.hip",
-           "tree_host.cpp"]
+           "tree_host.cpp", "opcache.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions stay off: the compiler would otherwise form v_pk_* from scalar code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "pkifmm.h"
@@ -29,29 +30,62 @@ constexpr int kMaxLevel = 21;
 constexpr int kNumM2L = 316;   // offsets in [-3,3]^3 with |delta|_inf >= 2
 constexpr int kM2LGroups = 8;  // fixed groups of offsets per M2L launch (bounded temporary)
 
-// Device buffer owned by a plan.
+// A caller's device allocator (pkifmm_config::alloc/free), with the stream of the call in progress.
+struct Allocator {
+    void* ctx = nullptr;
+    void* (*alloc)(void*, size_t, void*) = nullptr;
+    void (*free)(void*, void*, void*) = nullptr;
+    void* stream = nullptr;
+};
+// The allocator of the plan whose entry point (or build thread) is running on this thread; NULL:
+// hipMalloc / hipFree.
+extern thread_local const Allocator* g_alloc;
+struct AllocScope {
+    const Allocator* prev;
+    explicit AllocScope(const Allocator* a) : prev(g_alloc) { g_alloc = (a && a->alloc) ? a : nullptr; }
+    ~AllocScope() { g_alloc = prev; }
+    AllocScope(const AllocScope&) = delete;
+    AllocScope& operator=(const AllocScope&) = delete;
+};
+
+// Device buffer owned by a plan: from the caller's allocator when one is in scope, else hipMalloc;
+// released through whichever made it.
 template <class T>
 struct DBuf {
     T* p = nullptr;
     size_t n = 0;
+    const Allocator* owner = nullptr;
     DBuf() = default;
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
     ~DBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (owner) owner->free(owner->ctx, p, owner->stream);
+            else (void)hipFree(p);
+        }
         p = nullptr;
         n = 0;
+        owner = nullptr;
     }
     void ensure(size_t count) {
         if (count <= n && p) return;
         release();
         size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-        if (hipMalloc(&p, bytes) != hipSuccess) {
+        if (g_alloc) {
+            p = static_cast<T*>(g_alloc->alloc(g_alloc->ctx, bytes, g_alloc->stream));
+            if (!p) throw Error(PKIFMM_ERR_OOM, "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes");
+            owner = g_alloc;
+        } else if (hipMalloc(&p, bytes) != hipSuccess) {
             p = nullptr;
             throw Error(PKIFMM_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
         }
         n = std::max<size_t>(count, 1);
+    }
+    void swap(DBuf& o) {
+        std::swap(p, o.p);
+        std::swap(n, o.n);
+        std::swap(owner, o.owner);
     }
     void upload(const std::vector<T>& h, hipStream_t s) {
         ensure(h.size());
@@ -122,6 +156,7 @@ struct HostLists {
 
 void build_tree_host(const uint64_t* sorted_keys, int64_t n, int s, HostTree& t);
 void build_lists_host(const HostTree& t, unsigned periodic_mask, HostLists& l);
+void add_root_ring(const HostTree& t, unsigned periodic_mask, int near_layers, HostLists& l);
 void merge_forest(const std::vector<HostTree>& trees, const std::vector<HostLists>& lists,
                   const std::vector<int64_t>& poff, HostTree& t, HostLists& l, std::vector<int>& box_prob);
 int m2l_offset_index(int dx, int dy, int dz);   // -> 0..315

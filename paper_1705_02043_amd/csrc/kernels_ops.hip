@@ -1,6 +1,7 @@
 // Operator construction (Algorithm 2, Stage 1) in float64 on the device:
 // kernel matrices between surface grids, the periodic far-field kernel
-// K^{P,F} over images |p|_inf >= 2, and the split SVD factors of the
+// K^{P,F} over images |p|_inf > l (l = 1 by default; 2 and 3 for singly and triply
+// periodic sums, Section 3.6's near-field layer), and the split SVD factors of the
 // check-to-equivalent solves.  Raw kernels throughout (1/|r| and
 // I/|r| + r r^T/|r|^3); the 1/(4 pi), 1/(8 pi) factors are applied to the
 // final potentials.
@@ -56,13 +57,13 @@ __global__ void k_kmat(int kernel, const double* __restrict__ X, int m, const do
 
 // ---- singly periodic Laplace
 __global__ void k_far_sp_laplace(int axis, const double* __restrict__ X, int m, const double* __restrict__ Y, int n,
-                                 double* __restrict__ out, int64_t ld, const double* __restrict__ zeta) {
+                                 double* __restrict__ out, int64_t ld, const double* __restrict__ zeta, int near) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y;
     if (i >= m) return;
     double r[3] = {X[3 * i] - Y[3 * j], X[3 * i + 1] - Y[3 * j + 1], X[3 * i + 2] - Y[3 * j + 2]};
     double acc = 0.0;
-    for (int k = kNear; k >= 2; --k) {   // small terms first
+    for (int k = kNear; k >= near + 1; --k) {   // small terms first
         double rp[3] = {r[0], r[1], r[2]}, rm[3] = {r[0], r[1], r[2]};
         rp[axis] -= k;
         rm[axis] += k;
@@ -94,13 +95,13 @@ __global__ void k_far_sp_laplace(int axis, const double* __restrict__ X, int m, 
 //   Q_m = I P_m rho^m + e e^T C_m rho^m - (e r^T + r e^T) C_{m-1} rho^(m-1) + r r^T C_{m-2} rho^(m-2)
 // (rho = |r|, u = r.e/rho), summed against zeta(m+1, kNear+1).
 __global__ void k_far_sp_stokes(int axis, const double* __restrict__ X, int m, const double* __restrict__ Y, int n,
-                                double* __restrict__ out, int64_t ld, const double* __restrict__ zeta) {
+                                double* __restrict__ out, int64_t ld, const double* __restrict__ zeta, int near) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y;
     if (i >= m) return;
     const double r[3] = {X[3 * i] - Y[3 * j], X[3 * i + 1] - Y[3 * j + 1], X[3 * i + 2] - Y[3 * j + 2]};
     double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int k = kNear; k >= 2; --k) {   // small terms first
+    for (int k = kNear; k >= near + 1; --k) {   // small terms first
         for (int sg = -1; sg <= 1; sg += 2) {
             double d[3] = {r[0], r[1], r[2]};
             d[axis] -= sg * k;
@@ -169,7 +170,7 @@ __device__ void hasimoto_smooth(const double d[3], double rn, double xi, double 
 
 __global__ void k_far_tp_stokes(const double* __restrict__ X, int m, const double* __restrict__ Y, int n,
                                 double* __restrict__ out, int64_t ld, const double4* __restrict__ kv, int nk,
-                                double rc, int P) {
+                                double rc, int P, int near) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y;
     if (i >= m) return;
@@ -183,7 +184,7 @@ __global__ void k_far_tp_stokes(const double* __restrict__ X, int m, const doubl
                 double d[3] = {r[0] - px, r[1] - py, r[2] - pz};
                 double rn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
                 int pin = max(abs(px), max(abs(py), abs(pz)));
-                if (pin <= 1) {
+                if (pin <= near) {
                     hasimoto_smooth(d, rn, xi, S);
                     for (int p = 0; p < 3; ++p)
                         for (int q = 0; q < 3; ++q) A[p][q] -= S[p][q];
@@ -214,7 +215,7 @@ __global__ void k_far_tp_stokes(const double* __restrict__ X, int m, const doubl
 // ---- triply periodic Laplace
 __global__ void k_far_tp_laplace(const double* __restrict__ X, int m, const double* __restrict__ Y, int n,
                                  double* __restrict__ out, int64_t ld, const double4* __restrict__ kv, int nk,
-                                 double rc, int P) {
+                                 double rc, int P, int near) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y;
     if (i >= m) return;
@@ -228,7 +229,7 @@ __global__ void k_far_tp_laplace(const double* __restrict__ X, int m, const doub
                 double d[3] = {r[0] - px, r[1] - py, r[2] - pz};
                 double rn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
                 int pin = max(abs(px), max(abs(py), abs(pz)));
-                if (pin <= 1) acc -= rn > 0.0 ? erf(xi * rn) / rn : c;
+                if (pin <= near) acc -= rn > 0.0 ? erf(xi * rn) / rn : c;
                 else if (rn < rc) acc += erfc(xi * rn) / rn;
             }
     double fs = 0.0;
@@ -438,7 +439,7 @@ void launch_kmat(int kernel, const double* X, int m, const double* Y, int n, dou
 }
 
 void launch_far_kmat(int kernel, unsigned mask, const double* X, int m, const double* Y, int n, double* out,
-                     int64_t ld, const double*, hipStream_t s) {
+                     int64_t ld, int near, hipStream_t s) {
     int naxes = __builtin_popcount(mask & 7u);
     dim3 grid((m + 127) / 128, n);
     if (naxes == 1) {
@@ -448,9 +449,9 @@ void launch_far_kmat(int kernel, unsigned mask, const double* X, int m, const do
         DBuf<double> dz;
         dz.upload(z, s);
         if (kernel == PKIFMM_LAPLACE)
-            hipLaunchKernelGGL(k_far_sp_laplace, grid, dim3(128), 0, s, axis, X, m, Y, n, out, ld, dz.p);
+            hipLaunchKernelGGL(k_far_sp_laplace, grid, dim3(128), 0, s, axis, X, m, Y, n, out, ld, dz.p, near);
         else
-            hipLaunchKernelGGL(k_far_sp_stokes, grid, dim3(128), 0, s, axis, X, m, Y, n, out, ld, dz.p);
+            hipLaunchKernelGGL(k_far_sp_stokes, grid, dim3(128), 0, s, axis, X, m, Y, n, out, ld, dz.p, near);
         PK_HIP(hipGetLastError());
         PK_HIP(hipStreamSynchronize(s));
         return;
@@ -470,17 +471,17 @@ void launch_far_kmat(int kernel, unsigned mask, const double* X, int m, const do
             for (int j = 0; j < n; ++j) { ylo = std::min(ylo, hy[3 * j + c]); yhi = std::max(yhi, hy[3 * j + c]); }
             rmax = std::max(rmax, std::max(std::fabs(xhi - ylo), std::fabs(xlo - yhi)));
         }
-        int P = (int)std::ceil(rmax + rc) + 1;
+        int P = std::max((int)std::ceil(rmax + rc) + 1, near);
         std::vector<double> kv = kvectors(kmax, kernel == PKIFMM_STOKES);
         DBuf<double> dk;
         dk.upload(kv, s);
         int nk = (int)(kv.size() / 4);
         if (kernel == PKIFMM_STOKES)
             hipLaunchKernelGGL(k_far_tp_stokes, grid, dim3(128), 0, s, X, m, Y, n, out, ld, (const double4*)dk.p, nk,
-                               rc, P);
+                               rc, P, near);
         else
             hipLaunchKernelGGL(k_far_tp_laplace, grid, dim3(128), 0, s, X, m, Y, n, out, ld, (const double4*)dk.p,
-                               nk, rc, P);
+                               nk, rc, P, near);
         PK_HIP(hipGetLastError());
         PK_HIP(hipStreamSynchronize(s));
         return;

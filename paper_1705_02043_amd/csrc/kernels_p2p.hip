@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
         int count, base = 0;
         if (pts) {
             base = a.box_begin[b];
-            count = a.box_end[b] - base;
+            count = a.box_send[b] - base;
         } else {
             count = a.n_surf;
         }
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(kThreads) void k_p2s(P2PArgs a, int r0) {
         const double shx = (double)(seg.shift / 9 - 1), shy = (double)((seg.shift / 3) % 3 - 1),
                      shz = (double)(seg.shift % 3 - 1);
         const double ux = tx - shx, uy = ty - shy, uz = tz - shz;
-        const int base = a.box_begin[b], count = a.box_end[b] - base;
+        const int base = a.box_begin[b], count = a.box_send[b] - base;
         for (int c0 = 0; c0 < count; c0 += kThreads) {
             const int cnt = min(kThreads, count - c0);
             __syncthreads();
@@ -505,10 +505,12 @@ void launch_block(const P2PArgs& a, int r0, hipStream_t s) {
 
 template <int KD, bool MIXED>
 void launch_rhs(const P2PArgs& a, hipStream_t s) {
-    // right-hand sides in blocks: up to 16 (Laplace) or 4 (Stokes) share one geometry pass
+    // right-hand sides in blocks: up to 16 (Laplace) or 4 (Stokes), capped by a.rb_max, share one
+    // geometry pass (each right-hand side's sums are formed in the same order whatever the block)
+    const int cap = a.rb_max > 0 ? a.rb_max : 16;
     int r0 = 0;
     while (r0 < a.R) {
-        const int left = a.R - r0;
+        const int left = std::min(a.R - r0, cap);
         if (KD == 1 && left >= 16) { launch_block<KD, MIXED, 16>(a, r0, s); r0 += 16; }
         else if (KD == 1 && left >= 8) { launch_block<KD, MIXED, 8>(a, r0, s); r0 += 8; }
         else if (left >= 4) { launch_block<KD, MIXED, 4>(a, r0, s); r0 += 4; }
@@ -527,9 +529,11 @@ void launch_p2s_block(const P2PArgs& a, int r0, hipStream_t s) {
 
 void launch_p2s(const P2PArgs& a, hipStream_t s) {
     if (a.n_work == 0) return;
-    // right-hand sides in blocks: up to 8 (Laplace) or 4 (Stokes) share one geometry pass
+    // right-hand sides in blocks: up to 8 (Laplace) or 4 (Stokes), capped by a.rb_max, share one
+    // geometry pass
+    const int cap = a.rb_max > 0 ? a.rb_max : 8;
     for (int r0 = 0; r0 < a.R;) {
-        const int left = a.R - r0;
+        const int left = std::min(a.R - r0, cap);
         if (a.kernel == PKIFMM_LAPLACE) {
             if (left >= 8) { launch_p2s_block<1, 8>(a, r0, s); r0 += 8; }
             else if (left >= 4) { launch_p2s_block<1, 4>(a, r0, s); r0 += 4; }

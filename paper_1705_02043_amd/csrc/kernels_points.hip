@@ -80,27 +80,54 @@ __global__ void k_leaf_offsets(const double* __restrict__ xs, int64_t n, const i
     }
 }
 
+// points j >= n_dens (separate targets) carry zero density
 __global__ void k_permute_density(const double* __restrict__ dens, const uint32_t* __restrict__ perm, int64_t n,
-                                  int R, int k, double* __restrict__ ds, float* __restrict__ ds32) {
+                                  int64_t n_dens, int R, int k, double* __restrict__ ds, float* __restrict__ ds32) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint32_t j = perm[i];
     for (int r = 0; r < R; ++r)
         for (int c = 0; c < k; ++c) {
-            double v = dens[((int64_t)r * n + j) * k + c];
+            double v = (int64_t)j < n_dens ? dens[((int64_t)r * n_dens + j) * k + c] : 0.0;
             ds[((int64_t)r * k + c) * n + i] = v;
             if (ds32) ds32[((int64_t)r * k + c) * n + i] = (float)v;
         }
 }
 
-__global__ void k_unpermute(const double* __restrict__ pot, const uint32_t* __restrict__ perm, int64_t n, int R,
-                            int k, double scale, double* __restrict__ out) {
+// only points j >= t_first are targets; target j is output row j - t_first of n_out
+__global__ void k_unpermute(const double* __restrict__ pot, const uint32_t* __restrict__ perm, int64_t n,
+                            int64_t t_first, int64_t n_out, int R, int k, double scale, double* __restrict__ out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint32_t j = perm[i];
+    const int64_t j = (int64_t)perm[i] - t_first;
+    if (j < 0) return;
     for (int r = 0; r < R; ++r)
         for (int c = 0; c < k; ++c)
-            out[((int64_t)r * n + j) * k + c] = scale * pot[((int64_t)r * k + c) * n + i];
+            out[((int64_t)r * n_out + j) * k + c] = scale * pot[((int64_t)r * k + c) * n + i];
+}
+
+// Separate targets: per leaf (one workgroup each), the key (leaf begin, is target) of each of its
+// sorted points, so that a stable sort by it puts each leaf's sources before its targets and
+// keeps both in (Morton key, index) order; and the leaf's source count.
+__global__ void k_role_keys(const int* __restrict__ leaves, const int* __restrict__ box_begin,
+                            const int* __restrict__ box_end, const uint32_t* __restrict__ perm, int64_t n_src,
+                            uint64_t* __restrict__ keys, int* __restrict__ n_sources) {
+    __shared__ int sh[256];
+    const int b = leaves[blockIdx.x];
+    const int b0 = box_begin[b], b1 = box_end[b];
+    int cnt = 0;
+    for (int i = b0 + threadIdx.x; i < b1; i += 256) {
+        const bool trg = (int64_t)perm[i] >= n_src;
+        keys[i] = ((uint64_t)b0 << 1) | (trg ? 1u : 0u);
+        cnt += trg ? 0 : 1;
+    }
+    sh[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) n_sources[blockIdx.x] = sh[0];
 }
 
 // one workgroup per (problem, rhs x component): the sum and the sum of magnitudes;
@@ -206,6 +233,39 @@ __global__ void k_close_pairs(const uint64_t* __restrict__ keys, const double* _
             }
 }
 
+// Triply periodic Laplace: the far-field term the root's equivalent density cannot carry.  The
+// zero-mean Ewald kernel (raw 1/r normalisation) has laplacian 4 pi away from its lattice
+// points, so as a function of the source position it is harmonic plus (2 pi / 3) |y - c|^2; the
+// equivalent density matches the sources on harmonic functions only, so the far field lacks
+// (2 pi / 3) (sum_s q_s |y_s - c|^2 - sum_j phi_j |y_j - c|^2), one constant per problem and
+// right-hand side, added to every potential.  One workgroup per (problem, right-hand side);
+// deterministic LDS reductions.  Root of problem q: box q; its equivalent points c + 0.525 u_j.
+__global__ void k_tp_background(const double* __restrict__ ds, const double* __restrict__ xs, int64_t n,
+                                const int64_t* __restrict__ off, const double* __restrict__ phi_u, int R,
+                                const double* __restrict__ usurf, int n_surf, double* __restrict__ pot) {
+    __shared__ double sh[256];
+    const int q = blockIdx.x, r = blockIdx.y;
+    const int64_t b0 = off[q], b1 = off[q + 1];
+    double acc = 0.0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) {
+        const double dx = xs[i] - 0.5, dy = xs[n + i] - 0.5, dz = xs[2 * n + i] - 0.5;
+        acc += ds[(int64_t)r * n + i] * (dx * dx + dy * dy + dz * dz);
+    }
+    const double* phi = phi_u + ((int64_t)q * R + r) * n_surf;
+    for (int j = threadIdx.x; j < n_surf; j += 256) {
+        const double ux = usurf[3 * j], uy = usurf[3 * j + 1], uz = usurf[3 * j + 2];
+        acc -= phi[j] * (0.525 * 0.525) * (ux * ux + uy * uy + uz * uz);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double c = (2.0 * M_PI / 3.0) * sh[0];
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) pot[(int64_t)r * n + i] += c;
+}
+
 __global__ void k_fill_zero(double* __restrict__ x, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         x[i] = 0.0;
@@ -279,7 +339,7 @@ void launch_keys(const double* xyz, int64_t n, double L, unsigned mask, uint64_t
 }
 
 void radix_sort_pairs(uint64_t* kin, uint64_t* kout, uint32_t* vin, uint32_t* vout, int64_t n, DBuf<char>& temp,
-                      hipStream_t s, int n_seg, const int64_t* off) {
+                      hipStream_t s, int n_seg, const int64_t* off, int end_bit) {
     if (n == 0) return;
     size_t bytes = 0;
     if (n_seg > 1) {
@@ -290,9 +350,9 @@ void radix_sort_pairs(uint64_t* kin, uint64_t* kout, uint32_t* vin, uint32_t* vo
                                                    off, off + 1, 0, 63, s));
         return;
     }
-    PK_HIP(rocprim::radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, (size_t)n, 0, 63, s));
+    PK_HIP(rocprim::radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, (size_t)n, 0, end_bit, s));
     temp.ensure(bytes);
-    PK_HIP(rocprim::radix_sort_pairs(temp.p, bytes, kin, kout, vin, vout, (size_t)n, 0, 63, s));
+    PK_HIP(rocprim::radix_sort_pairs(temp.p, bytes, kin, kout, vin, vout, (size_t)n, 0, end_bit, s));
 }
 
 void launch_gather_points(const double* u, const uint32_t* perm, int64_t n, double* xs, hipStream_t s) {
@@ -310,17 +370,26 @@ void launch_leaf_offsets(const double* xs, int64_t n, const int* leaves, int n_l
     PK_HIP(hipGetLastError());
 }
 
-void launch_permute_density(const double* dens, const uint32_t* perm, int64_t n, int R, int k, double* ds,
-                            float* ds32, hipStream_t s) {
+void launch_permute_density(const double* dens, const uint32_t* perm, int64_t n, int64_t n_dens, int R, int k,
+                            double* ds, float* ds32, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_permute_density, dim3(nblk(n, 256)), dim3(256), 0, s, dens, perm, n, R, k, ds, ds32);
+    hipLaunchKernelGGL(k_permute_density, dim3(nblk(n, 256)), dim3(256), 0, s, dens, perm, n, n_dens, R, k, ds, ds32);
     PK_HIP(hipGetLastError());
 }
 
-void launch_unpermute(const double* pot, const uint32_t* perm, int64_t n, int R, int k, double scale, double* out,
-                      hipStream_t s) {
+void launch_unpermute(const double* pot, const uint32_t* perm, int64_t n, int64_t t_first, int64_t n_out, int R,
+                      int k, double scale, double* out, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_unpermute, dim3(nblk(n, 256)), dim3(256), 0, s, pot, perm, n, R, k, scale, out);
+    hipLaunchKernelGGL(k_unpermute, dim3(nblk(n, 256)), dim3(256), 0, s, pot, perm, n, t_first, n_out, R, k, scale,
+                       out);
+    PK_HIP(hipGetLastError());
+}
+
+void launch_role_keys(const int* leaves, int n_leaves, const int* box_begin, const int* box_end, const uint32_t* perm,
+                      int64_t n_src, uint64_t* keys, int* n_sources, hipStream_t s) {
+    if (n_leaves == 0) return;
+    hipLaunchKernelGGL(k_role_keys, dim3(n_leaves), dim3(256), 0, s, leaves, box_begin, box_end, perm, n_src, keys,
+                       n_sources);
     PK_HIP(hipGetLastError());
 }
 
@@ -329,6 +398,14 @@ void launch_close_pairs(const uint64_t* keys, const double* xs, int64_t n, const
     if (n == 0) return;
     hipLaunchKernelGGL(k_close_pairs, dim3(nblk(n, 256)), dim3(256), 0, s, keys, xs, n, off, n_prob, mask, delta,
                        flag);
+    PK_HIP(hipGetLastError());
+}
+
+void launch_tp_background(const double* ds, const double* xs, int64_t n, const int64_t* off, int n_prob,
+                          const double* phi_u, int R, const double* usurf, int n_surf, double* pot, hipStream_t s) {
+    if (n == 0 || n_prob == 0) return;
+    hipLaunchKernelGGL(k_tp_background, dim3(n_prob, R), dim3(256), 0, s, ds, xs, n, off, phi_u, R, usurf, n_surf,
+                       pot);
     PK_HIP(hipGetLastError());
 }
 

@@ -12,22 +12,30 @@ namespace pk {
 // set for a coordinate outside the box or not finite.
 void launch_keys(const double* xyz, int64_t n, double L, unsigned mask, uint64_t* keys,
                  uint32_t* vals, double* u, int* err, hipStream_t s);
-// Stable radix sort of (key, index) pairs; temp storage is grown as needed.  With
-// n_seg > 1 each segment [off[i], off[i+1]) is sorted on its own (off: device, n_seg+1).
+// Stable radix sort of (key, index) pairs on key bits [0, end_bit); temp storage is grown as
+// needed.  With n_seg > 1 each segment [off[i], off[i+1]) is sorted on its own (off: device,
+// n_seg+1; all 63 key bits).
 void radix_sort_pairs(uint64_t* keys_in, uint64_t* keys_out, uint32_t* vals_in, uint32_t* vals_out,
-                      int64_t n, DBuf<char>& temp, hipStream_t s, int n_seg = 1, const int64_t* off = nullptr);
+                      int64_t n, DBuf<char>& temp, hipStream_t s, int n_seg = 1, const int64_t* off = nullptr,
+                      int end_bit = 63);
 // Sorted SoA coordinates xs[3][n] = u[:, perm]; per-point float offsets from the
 // centre of the point's leaf (every leaf box listed once in leaves).
 void launch_gather_points(const double* u, const uint32_t* perm, int64_t n, double* xs, hipStream_t s);
 void launch_leaf_offsets(const double* xs, int64_t n, const int* leaves, int n_leaves, const int* box_begin,
                          const int* box_end, const int* box_level, const int* box_ix, const int* box_iy,
                          const int* box_iz, int* ioff, hipStream_t s);
-// density [R][n][k] input order -> ds [R][k][n] sorted (double) and optionally float
-void launch_permute_density(const double* dens, const uint32_t* perm, int64_t n, int R, int k,
+// density [R][n_dens][k] input order -> ds [R][k][n] sorted (double) and optionally float; points
+// with input index >= n_dens (separate targets) get zero density
+void launch_permute_density(const double* dens, const uint32_t* perm, int64_t n, int64_t n_dens, int R, int k,
                             double* ds, float* ds32, hipStream_t s);
-// pot_sorted [R][k][n] -> out [R][n][k] input order, times scale
-void launch_unpermute(const double* pot, const uint32_t* perm, int64_t n, int R, int k, double scale,
-                      double* out, hipStream_t s);
+// pot_sorted [R][k][n] -> out [R][n_out][k], times scale: the point of input index j >= t_first is
+// output row j - t_first (t_first = 0: every point; separate targets: the first target's index)
+void launch_unpermute(const double* pot, const uint32_t* perm, int64_t n, int64_t t_first, int64_t n_out, int R,
+                      int k, double scale, double* out, hipStream_t s);
+// separate targets: keys[i] = (begin of i's leaf) << 1 | (perm[i] >= n_src) for the sorted points
+// of every listed leaf, and n_sources[j] = the source count of leaf j
+void launch_role_keys(const int* leaves, int n_leaves, const int* box_begin, const int* box_end, const uint32_t* perm,
+                      int64_t n_src, uint64_t* keys, int* n_sources, hipStream_t s);
 // x[0..n) = 0 with a kernel (no memset node under graph capture)
 void launch_fill_zero(double* x, int64_t n, hipStream_t s);
 // children key ranges of split boxes (box: [n_split][5] = begin, end, ix, iy, iz at level
@@ -41,6 +49,11 @@ void launch_add_into(double* y, const double* x, int64_t n, hipStream_t s);
 // (off: device)
 void launch_density_sums(const double* ds, int64_t n, int R, int k, const int64_t* off, int n_prob, double* out,
                          hipStream_t s);
+// triply periodic Laplace: adds to every sorted potential pot [R][n] (raw 1/r units) its problem's
+// far-field background constant (2 pi / 3)(sum_s q_s |y_s - c|^2 - sum_j phi_j |y_j - c|^2), c the
+// box centre, phi the root's upward equivalent density (root of problem q: column block q of phi_u)
+void launch_tp_background(const double* ds, const double* xs, int64_t n, const int64_t* off, int n_prob,
+                          const double* phi_u, int R, const double* usurf, int n_surf, double* pot, hipStream_t s);
 // sets *flag if two different points, or a point and another point's periodic image, lie in
 // different cells of the 2^-21 grid and closer than delta in every coordinate (keys and xs
 // sorted, per problem; xs the wrapped unit-box coordinates [3][n])
@@ -81,6 +94,8 @@ struct P2PArgs {
     const int* box_iz;
     const int* box_begin;
     const int* box_end;
+    const int* box_send; // end of the box's sources (a leaf with separate targets holds its sources
+                         // first, then its targets; otherwise box_end)
     const double* usurf; // [n_surf][3] unit surface grid on [-1,1]^3
     const Seg* segs;
     const Work* work;
@@ -91,6 +106,7 @@ struct P2PArgs {
     double* mpart;       // [k][n_slots] kind-3 partial sums (float64), written once each
     int64_t n_slots;
     int grid_cap;        // k_p2p with work_counter: this many workgroups take items from the counter
+    int rb_max;          // most right-hand sides sharing one pass over the geometry (0: the kernel's most)
     int guard_all;       // mixed form: guard zero separations in every segment (set when points of
                          // different leaves or images may round to one integer position)
     unsigned long long* work_counter;   // one word, cleared by launch_p2p before each launch of a
@@ -171,9 +187,10 @@ void launch_gemm_oz(const OzArgs& a, hipStream_t s);
 // out[(k*i+a) + (k*j+b)*ld] = K(X_i - Y_j)_{ab}; X, Y: [m][3], [n][3]
 void launch_kmat(int kernel, const double* X, int m, const double* Y, int n, double* out, int64_t ld,
                  hipStream_t s);
-// far-field periodic kernel over images |p|_inf >= 2 between point sets (same layout)
+// far-field periodic kernel over images |p|_inf > near (1, 2 or 3; 1 for doubly periodic sums)
+// between point sets (same layout)
 void launch_far_kmat(int kernel, unsigned mask, const double* X, int m, const double* Y, int n, double* out,
-                     int64_t ld, const double* host_zeta, hipStream_t s);
+                     int64_t ld, int near, hipStream_t s);
 // small helpers for the SVD factors
 void launch_pinv_factors(const double* U, const double* Vt, const double* S, int kn, int r, double* Ut_r,
                          double* VS, hipStream_t s);

@@ -36,13 +36,21 @@
 #include <type_traits>
 
 #include "launch.h"
+#include "opcache.h"
 
 using namespace pk;
+
+thread_local const Allocator* pk::g_alloc = nullptr;
 
 namespace {
 
 constexpr double kInnerHalf = 0.525;   // half edge of the 1.05 cube, in box edges
 constexpr double kNeutralRel = 1e-12;  // SP/DP neutrality: |sum phi| <= this * sum |phi|
+constexpr double kSolveCheckTol = 1e-13;   // normwise backward error of the solves on their kept subspace
+// default relative cutoff of the check-to-equivalent solves: singular values <= 1e-11 s_max are
+// dropped (below it the solve turns the tens-of-ulps rounding of its input into equivalent-density
+// noise without improving accuracy against the exact periodic sums)
+constexpr double kDefaultSvdCut = 1e-11;
 // mixed form: points closer than this (unit-box coordinates) in every coordinate may share an
 // integer position in the near field (at most 2 units of 2^-29 of a leaf edge <= 1 apart)
 constexpr double kCloseDelta = 1.0 / (1 << 27);
@@ -86,6 +94,18 @@ struct GemmRange {
 struct SegRange {
     int set = 0;            // 0: S2M and X items, 1: leaf items (near field, W + L2T)
     int work0 = 0, nwork = 0;
+};
+
+// Launch choices that change no result bit, chosen per (device architecture, kernel, periodic
+// axes, p, precision, n_rhs) by pkifmm_autotune and read from a tuning file at plan creation.
+struct Tuning {
+    int near_wpc = 4;       // near-field workgroups per compute unit taking items from the counter
+    int rb_near = 0;        // right-hand sides per near-field geometry pass (0: 16 Laplace, 4 Stokes)
+    int rb_s2m = 0;         // right-hand sides per points-to-surface pass (0: 8 Laplace, 4 Stokes)
+};
+struct TuneRec {
+    int R;
+    Tuning t;
 };
 
 struct GemmSet {            // device copy of one Gemm description
@@ -132,9 +152,11 @@ void* scratch_address(int dev) {
 }  // namespace
 
 struct pkifmm_plan {
+    Allocator allocator;                // first member: destroyed after every buffer it made
     pkifmm_config cfg{};
     int k = 1, n_surf = 0, kn = 0;
     int r_up = 0, r_dn = 0;
+    std::vector<double> f_up_Ut, f_up_VS, f_dn_Ut, f_dn_VS;   // host copies of the solve factors (inspection)
     std::string last_error;
     hipStream_t setup_stream = nullptr;
     hipStream_t setup_stream2 = nullptr;        // uploads of the M2L work lists (built on a second host thread)
@@ -167,8 +189,17 @@ struct pkifmm_plan {
     DBuf<int> phi_oz_e;                 // [nbox*R] column exponents
     DBuf<double> mroot;                 // [kn*kn]
 
-    // points and tree (a forest: one tree per problem, boxes numbered level-major)
+    // points and tree (a forest: one tree per problem, boxes numbered level-major).  With separate
+    // targets the points are the union: sources (input indices [0, n_src)) then targets; every leaf
+    // holds its sources first ([begin, box_send)), then its targets ([box_tbeg, end))
     int64_t n = 0;
+    int64_t n_src = 0;                  // density rows
+    int64_t t_first = 0, n_out = 0;     // input index of the first target, potential rows
+    bool separate = false;
+    std::vector<int> box_send, box_tbeg;
+    DBuf<int> b_send, leaf_nsrc;
+    PinnedBuf<int> leaf_nsrc_host;
+    DBuf<double> xyz_union;
     int n_problems = 1;
     std::vector<int64_t> prob_off_h;
     DBuf<int64_t> prob_off;
@@ -199,7 +230,10 @@ struct pkifmm_plan {
     DBuf<Work> work[2];
     // U-list pairs evaluated once (one right-hand side): partial slots and, per leaf that is
     // the other side of such pairs, its slots in a fixed order
-    int near_grid_cap = 0;              // near-field workgroups resident at once (0: one per item)
+    Tuning tune;                        // the choices of the evaluation being enqueued
+    std::vector<TuneRec> tune_table;    // tuned choices of this plan's key, per n_rhs
+    bool tune_fixed = false;            // pkifmm_autotune is timing `tune` itself
+    std::string arch;                   // device architecture name (gfx950, ...)
     DBuf<double> counter;               // near-field work counter (one 64-bit word)
     bool mutual = false;
     int64_t n_slots = 0;
@@ -233,6 +267,8 @@ int fail(pkifmm_plan* p, const Error& e) {
     return e.code;
 }
 
+int near_layers(const pkifmm_config& c) { return c.near_layers > 1 ? c.near_layers : 1; }
+
 void check_config(const pkifmm_config& c) {
     if (c.kernel != PKIFMM_LAPLACE && c.kernel != PKIFMM_STOKES) throw Error(PKIFMM_ERR_INVALID_ARG, "kernel");
     if (c.periodic_mask & ~7u) throw Error(PKIFMM_ERR_INVALID_ARG, "periodic_mask");
@@ -243,12 +279,20 @@ void check_config(const pkifmm_config& c) {
     if (c.svd_rel_threshold < 0.0 || c.svd_rel_threshold >= 1.0) throw Error(PKIFMM_ERR_INVALID_ARG, "svd_rel_threshold");
     const unsigned known = PKIFMM_SKIP_CHECKS | PKIFMM_PHASE_TIMING | PKIFMM_GRAPH | PKIFMM_FAR_STEP_D;
     if (c.flags & ~known) throw Error(PKIFMM_ERR_INVALID_ARG, "flags");
+    if ((c.alloc == nullptr) != (c.free == nullptr)) throw Error(PKIFMM_ERR_INVALID_ARG, "alloc and free go together");
+    if (c.near_layers < 0 || c.near_layers > 3) throw Error(PKIFMM_ERR_INVALID_ARG, "near_layers must be 0 .. 3");
+    if (c.near_layers > 1 && __builtin_popcount(c.periodic_mask) == 2)
+        throw Error(PKIFMM_ERR_UNSUPPORTED, "near_layers > 1 for doubly periodic sums");
 }
 
+void check_solve(const double* A_dev, int kn, int r, const std::vector<double>& hUt, const std::vector<double>& hVS,
+                 double s_max);
+
 // SVD of a kn x kn matrix on the device (rocSOLVER, one-sided bidiagonal QR);
-// drops singular values <= thr * s_max and stores U^T (r x kn) and V S^+ (kn x r).
+// drops singular values <= thr * s_max and stores U^T (r x kn) and V S^+ (kn x r), on the device
+// and in hUt, hVS; *s_max_out receives s_max.
 int pinv_build(rocblas_handle h, hipStream_t s, const double* A_dev, int kn, double thr, DBuf<double>& Ut,
-               DBuf<double>& VS) {
+               DBuf<double>& VS, std::vector<double>& hUt, std::vector<double>& hVS, double* s_max_out) {
     DBuf<double> A, S, U, Vt, E;
     DBuf<rocblas_int> info;
     A.ensure((size_t)kn * kn);
@@ -274,16 +318,28 @@ int pinv_build(rocblas_handle h, hipStream_t s, const double* A_dev, int kn, dou
     VS.ensure((size_t)kn * r);
     launch_pinv_factors(U.p, Vt.p, S.p, kn, r, Ut.p, VS.p, s);
     PK_HIP(hipStreamSynchronize(s));
-    // backward-stability self-check on q = A x for a fixed x, normwise (Appendix B's sense):
-    // ||A (V S^+ U^T q) - q|| small against ||A|| ||x|| = s_max ||x||.  (Against ||q|| it would
-    // also count the dropped directions, up to thr s_max ||x||, relative to ||A x||, which for a
-    // large graded A such as Stokes p = 16 is far below s_max ||x||.)
-    std::vector<double> hA((size_t)kn * kn), hUt((size_t)r * kn), hVS((size_t)kn * r);
-    PK_HIP(hipMemcpy(hA.data(), A_dev, sizeof(double) * kn * kn, hipMemcpyDeviceToHost));
+    hUt.assign((size_t)r * kn, 0.0);
+    hVS.assign((size_t)kn * r, 0.0);
     PK_HIP(hipMemcpy(hUt.data(), Ut.p, sizeof(double) * r * kn, hipMemcpyDeviceToHost));
     PK_HIP(hipMemcpy(hVS.data(), VS.p, sizeof(double) * kn * r, hipMemcpyDeviceToHost));
-    std::vector<double> x(kn), q(kn, 0.0), t(r, 0.0), ph(kn, 0.0), aq(kn, 0.0);
-    for (int i = 0; i < kn; ++i) x[i] = std::sin(1.0 + 0.37 * i);
+    *s_max_out = sv[0];
+    check_solve(A_dev, kn, r, hUt, hVS, sv[0]);
+    return r;
+}
+
+// Backward-stability self-check of a solve (Appendix B), normwise and on the kept subspace.
+    // backward-stability self-check (Appendix B), normwise and on the kept subspace: for x = (V S^+) z,
+    // which the truncation leaves intact, q = A x must come back with ||A (V S^+)(U^T q) - q|| at
+    // the rounding level of ||A|| ||x|| = s_max ||x||, whatever the cutoff (measured 3e-17 ..
+    // 3e-16 for Stokes p = 8 .. 16; a wrong factor gives order 1)
+void check_solve(const double* A_dev, int kn, int r, const std::vector<double>& hUt, const std::vector<double>& hVS,
+                 double s_max) {
+    std::vector<double> hA((size_t)kn * kn);
+    PK_HIP(hipMemcpy(hA.data(), A_dev, sizeof(double) * kn * kn, hipMemcpyDeviceToHost));
+    std::vector<double> z(r), x(kn, 0.0), q(kn, 0.0), t(r, 0.0), ph(kn, 0.0), aq(kn, 0.0);
+    for (int i = 0; i < r; ++i) z[i] = std::sin(1.0 + 0.37 * i);
+    for (int j = 0; j < r; ++j)
+        for (int i = 0; i < kn; ++i) x[i] += hVS[i + (size_t)j * kn] * z[j];
     for (int j = 0; j < kn; ++j)
         for (int i = 0; i < kn; ++i) q[i] += hA[i + (size_t)j * kn] * x[j];
     for (int j = 0; j < kn; ++j)
@@ -297,10 +353,8 @@ int pinv_build(rocblas_handle h, hipStream_t s, const double* A_dev, int kn, dou
         num += (aq[i] - q[i]) * (aq[i] - q[i]);
         xx += x[i] * x[i];
     }
-    double tol = std::max(1e-10, 100.0 * thr);
-    if (!(std::sqrt(num) < tol * sv[0] * std::sqrt(xx)))
+    if (!(std::sqrt(num) < kSolveCheckTol * s_max * std::sqrt(xx)))
         throw Error(PKIFMM_ERR_NUMERICS, "check-to-equivalent solve failed its backward-error check");
-    return r;
 }
 
 // in: nkb input columns per output column (K blocks), -1 for a zero block; ncols output columns
@@ -413,6 +467,7 @@ void build_stage_tree(pkifmm_plan* P, int R) {
     // S2M: leaf points -> own upward check surface
     P->w_s2m = SegRange{0, (int)work.size(), 0};
     for (int b : t.leaves) {
+        if (P->box_send[b] == t.begin[b]) continue;   // a leaf of targets only
         int s0 = (int)segs.size();
         segs.push_back(Seg{0, b, kSelf});
         for (int c0 = 0; c0 < ns; c0 += 64) work.push_back(Work{b, 2, c0, std::min(64, ns - c0), s0, s0 + 1});
@@ -580,8 +635,10 @@ void build_stage_near(pkifmm_plan* P, int R) {
     // with -p, and a small leaf A taken directly from W(B) is B taken directly from X(A) with
     // -p.  The leaf with more points (then the lower box index) owns the pair and holds the
     // targets; the other leaf's points get their sums through partial slots.
-    const bool mutual = R == 1;
+    const bool mutual = R == 1 && !P->separate;
     auto pts_of = [&](int b) { return t.end[b] - t.begin[b]; };
+    auto src_of = [&](int b) { return P->box_send[b] - t.begin[b]; };      // sources of a box
+    auto trg_of = [&](int b) { return t.end[b] - P->box_tbeg[b]; };        // targets of a leaf
     // is (src, shift code c) in box a's list?  Lists are sorted by (source, shift code).
     auto listed = [&](const std::vector<int64_t>& off, const std::vector<Entry>& v, int a, int s, int c) {
         auto lo = v.begin() + off[a], hi = v.begin() + off[a + 1];
@@ -629,10 +686,11 @@ void build_stage_near(pkifmm_plan* P, int R) {
                 std::vector<Seg> near;     // one leaf's direct segments (roles decided once per leaf)
                 for (int li = l0; li < l1; ++li) {
                     const int b = t.leaves[li];
-                    const int cnt = pts_of(b);
+                    const int cnt = trg_of(b);
                     if (cnt == 0) continue;
                     near.clear();
                     auto direct = [&](const Entry& en, int which) {
+                        if (src_of(en.src) == 0) return;
                         const int role = d_role(b, en, which);
                         if (role != 2) near.push_back(Seg{role == 1 ? 3 : 0, en.src, code(en)});
                     };
@@ -645,7 +703,7 @@ void build_stage_near(pkifmm_plan* P, int R) {
                         const int tc = std::min(512, cnt - c0);
                         if (c0 > 0 && !mutual) {   // without two-way segments the chunks share one list
                             const Work w0 = pt.work.back();
-                            pt.work.push_back(Work{b, 0, t.begin[b] + c0, tc, w0.seg0, w0.seg1});
+                            pt.work.push_back(Work{b, 0, P->box_tbeg[b] + c0, tc, w0.seg0, w0.seg1});
                             continue;
                         }
                         const int s0 = (int)pt.segs.size();
@@ -657,7 +715,7 @@ void build_stage_near(pkifmm_plan* P, int R) {
                             }
                             pt.segs.push_back(sg);
                         }
-                        pt.work.push_back(Work{b, 0, t.begin[b] + c0, tc, s0, (int)pt.segs.size()});
+                        pt.work.push_back(Work{b, 0, P->box_tbeg[b] + c0, tc, s0, (int)pt.segs.size()});
                     }
                 }
             } catch (...) {
@@ -691,7 +749,7 @@ void build_stage_near(pkifmm_plan* P, int R) {
         out.set = 1;
         out.work0 = (int)work.size();
         for (int b : t.leaves) {
-            const int cnt = t.end[b] - t.begin[b];
+            const int cnt = trg_of(b);
             if (cnt == 0) continue;
             const int s0 = (int)segs.size();
             for (int64_t e = L.w_off[b]; e < L.w_off[b + 1]; ++e)
@@ -704,7 +762,7 @@ void build_stage_near(pkifmm_plan* P, int R) {
             }
             const int s1 = (int)segs.size();
             for (int c0 = 0; c0 < cnt; c0 += 512)
-                work.push_back(Work{b, 0, t.begin[b] + c0, std::min(512, cnt - c0), s0, s1});
+                work.push_back(Work{b, 0, P->box_tbeg[b] + c0, std::min(512, cnt - c0), s0, s1});
         }
         out.nwork = (int)work.size() - out.work0;
     };
@@ -716,7 +774,7 @@ void build_stage_near(pkifmm_plan* P, int R) {
             const Work& w = work[w0 + i];
             int64_t c = 0;
             for (int sg = w.seg0; sg < w.seg1; ++sg)   // a two-way segment costs about 4/3 of a one-way one
-                c += (int64_t)(t.end[segs[sg].box] - t.begin[segs[sg].box]) * (segs[sg].kind == 3 ? 4 : 3);
+                c += (int64_t)src_of(segs[sg].box) * (segs[sg].kind == 3 ? 4 : 3);
             cost[i] = c * (int64_t)w.tcount;
         }
         std::vector<int> order(nw);
@@ -731,8 +789,7 @@ void build_stage_near(pkifmm_plan* P, int R) {
         int64_t np = 0;
         for (int i = P->w_leaf_u.work0; i < P->w_leaf_u.work0 + P->w_leaf_u.nwork; ++i)
             for (int sg = work[i].seg0; sg < work[i].seg1; ++sg)
-                np += (int64_t)work[i].tcount * (t.end[segs[sg].box] - t.begin[segs[sg].box]) *
-                      (segs[sg].kind == 3 ? 2 : 1);
+                np += (int64_t)work[i].tcount * src_of(segs[sg].box) * (segs[sg].kind == 3 ? 2 : 1);
         P->stats.near_pairs = np;
     }
     hipStream_t s = P->setup_stream3;
@@ -939,6 +996,7 @@ void run_p2p(pkifmm_plan* P, const Workspace& ws, const SegRange& w, double* out
     a.box_iz = P->b_iz.p;
     a.box_begin = P->b_begin.p;
     a.box_end = P->b_end.p;
+    a.box_send = P->b_send.p;
     a.usurf = P->usurf.p;
     a.segs = P->segs[w.set].p;
     a.work = P->work[w.set].p + w.work0;
@@ -949,6 +1007,7 @@ void run_p2p(pkifmm_plan* P, const Workspace& ws, const SegRange& w, double* out
     a.mpart = ws.mpart;
     a.n_slots = P->n_slots;
     a.grid_cap = grid_cap;
+    a.rb_max = to_surface ? P->tune.rb_s2m : P->tune.rb_near;
     a.guard_all = P->guard_all ? 1 : 0;
     a.work_counter = nullptr;
     if (grid_cap > 0 && grid_cap < w.nwork)     // cleared before each launch (launch_p2p)
@@ -1036,6 +1095,58 @@ size_t carve_workspace(const pkifmm_plan* P, int R, char* base, Workspace& w) {
     return off;
 }
 
+// Tuning files: one record per line, "arch kernel mask p precision n_rhs near_wpc rb_near rb_s2m";
+// '#' starts a comment.  A missing file is empty; a malformed line is skipped.
+struct TuneLine {
+    std::string arch;
+    int kernel = 0;
+    unsigned mask = 0;
+    int p = 0, precision = 0, R = 0;
+    Tuning t;
+};
+
+std::vector<TuneLine> read_tuning_file(const char* path) {
+    std::vector<TuneLine> out;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return out;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        if (char* c = std::strchr(line, '#')) *c = 0;
+        char arch[64];
+        TuneLine l;
+        if (std::sscanf(line, "%63s %d %u %d %d %d %d %d %d", arch, &l.kernel, &l.mask, &l.p, &l.precision, &l.R,
+                        &l.t.near_wpc, &l.t.rb_near, &l.t.rb_s2m) == 9 &&
+            l.R >= 1 && l.t.near_wpc >= 1 && l.t.near_wpc <= 16 && l.t.rb_near >= 0 && l.t.rb_s2m >= 0) {
+            l.arch = arch;
+            out.push_back(l);
+        }
+    }
+    std::fclose(f);
+    return out;
+}
+
+// replaces the record of the same key (arch, kernel, mask, p, precision, n_rhs) or adds it
+bool write_tuning_record(const char* path, const TuneLine& rec) {
+    std::vector<TuneLine> lines = read_tuning_file(path);
+    bool done = false;
+    for (TuneLine& l : lines)
+        if (l.arch == rec.arch && l.kernel == rec.kernel && l.mask == rec.mask && l.p == rec.p &&
+            l.precision == rec.precision && l.R == rec.R) {
+            l = rec;
+            done = true;
+        }
+    if (!done) lines.push_back(rec);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "# arch kernel mask p precision n_rhs near_wpc rb_near rb_s2m (pkifmm_autotune)\n");
+    for (const TuneLine& l : lines)
+        std::fprintf(f, "%s %d %u %d %d %d %d %d %d\n", l.arch.c_str(), l.kernel, l.mask, l.p, l.precision, l.R,
+                     l.t.near_wpc, l.t.rb_near, l.t.rb_s2m);
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
 // Wait until the last evaluation enqueued (on any stream) has finished: work lists, workspace and
 // point buffers are rewritten or reallocated only after that.
 void wait_idle(pkifmm_plan* P) { PK_HIP(hipEventSynchronize(P->ev_done)); }
@@ -1056,7 +1167,9 @@ class StageThread {
     void start(F f) {
         int dev = 0;
         PK_HIP(hipGetDevice(&dev));
-        th_ = std::thread([this, f, dev] {
+        const Allocator* al = g_alloc;
+        th_ = std::thread([this, f, dev, al] {
+            AllocScope scope(al);      // buffers sized here come from the caller's allocator too
             try {
                 PK_HIP(hipSetDevice(dev));
                 f();
@@ -1087,6 +1200,11 @@ class StageThread {
 // sizes them) or is given (the static array).
 void enqueue_evaluate(pkifmm_plan* P, Workspace& w, int R, const double* density, double* potential, hipStream_t s,
                       bool checks, bool allow_timing, bool build = false) {
+        if (!P->tune_fixed) {   // the tuned choices for this n_rhs, else the defaults
+            P->tune = Tuning();
+            for (const TuneRec& rec : P->tune_table)
+                if (rec.R == R) P->tune = rec.t;
+        }
         const int64_t n = P->n;
         const int k = P->k, kn = P->kn;
         const HostTree& t = P->tree;
@@ -1115,7 +1233,7 @@ void enqueue_evaluate(pkifmm_plan* P, Workspace& w, int R, const double* density
             bind_plan_workspace(P, w, kWsM2L);
             bind_plan_workspace(P, w, kWsNear);
         }
-        launch_permute_density(density, P->perm.p, n, R, k, w.ds, mixed ? w.ds32 : nullptr, s);
+        launch_permute_density(density, P->perm.p, n, P->n_src, R, k, w.ds, mixed ? w.ds32 : nullptr, s);
         const int naxes = __builtin_popcount(P->cfg.periodic_mask);
         if (checks && (naxes == 1 || naxes == 2) && !(P->cfg.flags & PKIFMM_SKIP_CHECKS)) {
             // zero net density (Section 2, the compatibility condition), relative to the density's
@@ -1181,7 +1299,7 @@ void enqueue_evaluate(pkifmm_plan* P, Workspace& w, int R, const double* density
         bind_plan_workspace(P, w, kWsNear);
         PK_HIP(hipStreamWaitEvent(sn, P->ev_fork, 0));
         mark_on(sn);
-        run_p2p(P, w, P->w_leaf_u, w.pot, nullptr, R, mixed, false, sn, false, P->near_grid_cap);
+        run_p2p(P, w, P->w_leaf_u, w.pot, nullptr, R, mixed, false, sn, false, P->tune.near_wpc * P->n_cu);
         if (P->mutual)
             launch_mutual_gather(w.mpart, P->n_slots, k, P->in_box.p, P->in_off.p, P->in_slot.p, P->n_in,
                                  P->b_begin.p, P->b_end.p, n, w.pot, sn);
@@ -1202,9 +1320,12 @@ void enqueue_evaluate(pkifmm_plan* P, Workspace& w, int R, const double* density
         mark();
         // 6. W list and L2T (float64: they consume equivalent densities)
         run_p2p(P, w, P->w_leaf_far, w.pot, nullptr, R, false, true, s);
+        if (P->cfg.kernel == PKIFMM_LAPLACE && P->cfg.periodic_mask == 7u)   // the zero-mean sum's background
+            launch_tp_background(w.ds, P->xs.p, n, P->prob_off.p, P->n_problems, w.phi_u, R, P->usurf.p, P->n_surf,
+                                 w.pot, s);
         // 7. output
         const double c = (P->cfg.kernel == PKIFMM_LAPLACE ? 1.0 / (4.0 * M_PI) : 1.0 / (8.0 * M_PI)) / P->cfg.box_length;
-        launch_unpermute(w.pot, P->perm.p, n, R, k, c, potential, s);
+        launch_unpermute(w.pot, P->perm.p, n, P->t_first, P->n_out, R, k, c, potential, s);
         mark();
         if (!P->capturing) PK_HIP(hipEventRecord(P->ev_done, s));
         if (timing) P->pending_events.push_back(ev);
@@ -1234,9 +1355,14 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
     *out = nullptr;
     std::unique_ptr<pkifmm_plan> P(new pkifmm_plan());
     rocblas_handle h = nullptr;
+    P->allocator.ctx = cfg->alloc_ctx;
+    P->allocator.alloc = cfg->alloc;
+    P->allocator.free = cfg->free;
+    AllocScope scope(&P->allocator);
     try {
         check_config(*cfg);
         P->cfg = *cfg;
+        P->cfg.operator_cache_dir = nullptr;   // the caller's string is read here only
         P->k = cfg->kernel == PKIFMM_LAPLACE ? 1 : 3;
         const int p = cfg->p;
         std::vector<double> u = unit_surface(p);
@@ -1263,10 +1389,13 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
             PK_HIP(hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
             P->dev = dev;
             P->scratch_base = scratch_address(dev);   // once per device, this device current
-            // near field: four workgroups per compute unit take items from a counter in list
-            // (longest-first) order
-            P->near_grid_cap = 4 * P->n_cu;
+            // near field: a few workgroups per compute unit (Tuning::near_wpc) take items from a
+            // counter in list (longest-first) order
             P->counter.ensure(1);
+            hipDeviceProp_t prop;
+            PK_HIP(hipGetDeviceProperties(&prop, dev));
+            P->arch = prop.gcnArchName;
+            P->arch = P->arch.substr(0, P->arch.find(':'));
         }
         if (rocblas_create_handle(&h) != rocblas_status_success) throw Error(PKIFMM_ERR_HIP, "rocblas handle");
         rocblas_set_stream(h, s);
@@ -1277,12 +1406,48 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
         d_out.upload(outer, s);
         A.ensure((size_t)kn * kn);
         double thr = cfg->svd_rel_threshold;
-        if (thr == 0.0) thr = std::ldexp(1.0, -52) * kn;   // numerical-rank criterion of Table 1
+        if (thr == 0.0) thr = kDefaultSvdCut;
+        // the solve factors and the root operator from the operator cache, when one is given and
+        // holds them; a file that fails its checks is an error, not silently rebuilt
+        std::string cache_file;
+        OpBlob blob;
+        bool cached = false;
+        if (cfg->operator_cache_dir && cfg->operator_cache_dir[0]) {
+            cache_file = opcache_path(cfg->operator_cache_dir, cfg->kernel, cfg->periodic_mask, p, thr,
+                                      near_layers(*cfg));
+            const int st = opcache_read(cache_file, &blob);
+            if (st == PKIFMM_ERR_CACHE_CORRUPT ||
+                (st == PKIFMM_OK && (blob.kernel != cfg->kernel || blob.mask != cfg->periodic_mask || blob.p != p ||
+                                     blob.kn != kn || blob.cutoff != thr || blob.near_layers != near_layers(*cfg))))
+                throw Error(PKIFMM_ERR_CACHE_CORRUPT, "operator cache file failed its checks: " + cache_file);
+            cached = st == PKIFMM_OK;
+        }
+        double smax_up = 0.0, smax_dn = 0.0;
         // upward: check = outer, equivalent = inner;  downward: check = inner, equivalent = outer
         launch_kmat(cfg->kernel, d_out.p, ns, d_in.p, ns, A.p, kn, s);
-        P->r_up = pinv_build(h, s, A.p, kn, thr, P->up_Ut, P->up_VS);
+        if (cached) {
+            P->r_up = blob.r_up;
+            P->f_up_Ut = blob.up_Ut;
+            P->f_up_VS = blob.up_VS;
+            P->up_Ut.upload(P->f_up_Ut, s);
+            P->up_VS.upload(P->f_up_VS, s);
+            PK_HIP(hipStreamSynchronize(s));
+            check_solve(A.p, kn, P->r_up, P->f_up_Ut, P->f_up_VS, blob.smax_up);
+        } else {
+            P->r_up = pinv_build(h, s, A.p, kn, thr, P->up_Ut, P->up_VS, P->f_up_Ut, P->f_up_VS, &smax_up);
+        }
         launch_kmat(cfg->kernel, d_in.p, ns, d_out.p, ns, A.p, kn, s);
-        P->r_dn = pinv_build(h, s, A.p, kn, thr, P->dn_Ut, P->dn_VS);
+        if (cached) {
+            P->r_dn = blob.r_dn;
+            P->f_dn_Ut = blob.dn_Ut;
+            P->f_dn_VS = blob.dn_VS;
+            P->dn_Ut.upload(P->f_dn_Ut, s);
+            P->dn_VS.upload(P->f_dn_VS, s);
+            PK_HIP(hipStreamSynchronize(s));
+            check_solve(A.p, kn, P->r_dn, P->f_dn_Ut, P->f_dn_VS, blob.smax_dn);
+        } else {
+            P->r_dn = pinv_build(h, s, A.p, kn, thr, P->dn_Ut, P->dn_VS, P->f_dn_Ut, P->f_dn_VS, &smax_dn);
+        }
         // M2M / L2L: parent edge 1 centred at 0, child o centred at +-1/4
         P->m2m.ensure((size_t)8 * kn * kn);
         P->l2l.ensure((size_t)8 * kn * kn);
@@ -1304,11 +1469,35 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
         }
         // root far field: K^{P,F}(x^{B0,d}, y^{B0,u}), both the 1.05 cube of the unit box
         P->mroot.ensure((size_t)kn * kn);
-        if (cfg->periodic_mask == 0) {
+        if (cached) {
+            P->mroot.upload(blob.mroot, s);
+        } else if (cfg->periodic_mask == 0) {
             PK_HIP(hipMemsetAsync(P->mroot.p, 0, sizeof(double) * kn * kn, s));
         } else {
             d_tmp.upload(scaled(u, kInnerHalf, 0.5, 0.5, 0.5), s);
-            launch_far_kmat(cfg->kernel, cfg->periodic_mask, d_tmp.p, ns, d_tmp.p, ns, P->mroot.p, kn, nullptr, s);
+            launch_far_kmat(cfg->kernel, cfg->periodic_mask, d_tmp.p, ns, d_tmp.p, ns, P->mroot.p, kn,
+                            near_layers(P->cfg), s);
+        }
+        if (!cache_file.empty() && !cached) {   // store what was built (a failed write leaves no file)
+            OpBlob b;
+            b.kernel = cfg->kernel;
+            b.mask = cfg->periodic_mask;
+            b.p = p;
+            b.kn = kn;
+            b.r_up = P->r_up;
+            b.r_dn = P->r_dn;
+            b.cutoff = thr;
+            b.near_layers = near_layers(*cfg);
+            b.smax_up = smax_up;
+            b.smax_dn = smax_dn;
+            b.up_Ut = P->f_up_Ut;
+            b.up_VS = P->f_up_VS;
+            b.dn_Ut = P->f_dn_Ut;
+            b.dn_VS = P->f_dn_VS;
+            b.mroot.resize((size_t)kn * kn);
+            PK_HIP(hipMemcpyAsync(b.mroot.data(), P->mroot.p, sizeof(double) * kn * kn, hipMemcpyDeviceToHost, s));
+            PK_HIP(hipStreamSynchronize(s));
+            opcache_write(cache_file, b);
         }
         if (cfg->precision == PKIFMM_MIXED) {   // M2L of the mixed form runs on int8 slices
             const int kp = oz_padded(kn);
@@ -1317,6 +1506,12 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
             launch_oz_slice_operators(P->m2l.p, kNumM2L, kn, kn, P->m2l_oz.p, P->m2l_oz_e.p, s);
         }
         P->err_flag.ensure(2);
+        if (cfg->tuning_file && cfg->tuning_file[0])
+            for (const TuneLine& l : read_tuning_file(cfg->tuning_file))
+                if (l.arch == P->arch && l.kernel == cfg->kernel && l.mask == cfg->periodic_mask && l.p == p &&
+                    l.precision == cfg->precision)
+                    P->tune_table.push_back(TuneRec{l.R, l.t});
+        P->cfg.tuning_file = nullptr;
         PK_HIP(hipStreamSynchronize(s));
         rocblas_destroy_handle(h);
         h = nullptr;
@@ -1343,12 +1538,13 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
     return PKIFMM_OK;
 }
 
-int pkifmm_set_points(pkifmm_plan* P, int64_t n, const double* xyz, void* stream) {
-    if (n < 0) return P ? fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n")) : PKIFMM_ERR_INVALID_ARG;
-    return pkifmm_set_points_batch(P, 1, &n, xyz, stream);
-}
+}  // extern "C"
 
-int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* counts, const double* xyz, void* stream) {
+namespace {
+
+// Point set-up of one problem (with separate targets when trg != nullptr) or of a batch.
+int set_points_impl(pkifmm_plan* P, int n_problems, const int64_t* counts, const double* xyz, int64_t n_trg,
+                    const double* trg, void* stream) {
     if (!P) return PKIFMM_ERR_INVALID_ARG;
     if (n_problems < 1 || !counts) return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n_problems or counts"));
     std::vector<int64_t> poff(n_problems + 1, 0);
@@ -1356,16 +1552,35 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
         if (counts[i] < 0) return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "negative count"));
         poff[i + 1] = poff[i] + counts[i];
     }
+    const bool separate = trg != nullptr;
+    if (n_trg < 0 || (!separate && n_trg != 0) || (separate && n_problems != 1))
+        return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n_trg or trg_xyz"));
+    const int64_t n_src = poff[n_problems];
+    if (separate) poff[1] += n_trg;      // one problem: the union of sources and targets
     const int64_t n = poff[n_problems];
-    if (n > (int64_t)INT32_MAX || (n > 0 && !xyz)) return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n or xyz"));
+    if (n > (int64_t)INT32_MAX || (n_src > 0 && !xyz)) return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n or xyz"));
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
+    P->allocator.stream = stream;
+    AllocScope scope(&P->allocator);
     try {
         wait_idle(P);   // an evaluation in flight still reads the current points and lists
         P->have_points = false;
         P->R_built = -1;
         ++P->generation;
         drop_graph(P);
+        P->separate = separate;
+        P->n_src = n_src;
+        P->t_first = separate ? n_src : 0;
+        P->n_out = separate ? n_trg : n;
+        if (separate && n > 0) {   // the union, sources first (input indices [0, n_src))
+            P->xyz_union.ensure((size_t)3 * n);
+            if (n_src) PK_HIP(hipMemcpyAsync(P->xyz_union.p, xyz, sizeof(double) * 3 * n_src, hipMemcpyDeviceToDevice, s));
+            if (n_trg)
+                PK_HIP(hipMemcpyAsync(P->xyz_union.p + 3 * n_src, trg, sizeof(double) * 3 * n_trg,
+                                      hipMemcpyDeviceToDevice, s));
+            xyz = P->xyz_union.p;
+        }
         P->n = n;
         P->n_problems = n_problems;
         P->prob_off_h = poff;
@@ -1402,6 +1617,7 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
         if (n_problems == 1) {
             build_tree_device(P, P->keys_b.p, n, P->cfg.max_pts_per_leaf, P->tree, s);
             build_lists_host(P->tree, P->cfg.periodic_mask, P->lists);
+            add_root_ring(P->tree, P->cfg.periodic_mask, near_layers(P->cfg), P->lists);
             P->box_prob.assign(P->tree.nbox(), 0);
         } else {
             std::vector<HostTree> trees(n_problems);
@@ -1410,10 +1626,35 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
             for (int q = 0; q < n_problems; ++q) {
                 build_tree_host(keys + poff[q], poff[q + 1] - poff[q], P->cfg.max_pts_per_leaf, trees[q]);
                 build_lists_host(trees[q], P->cfg.periodic_mask, lists[q]);
+                add_root_ring(trees[q], P->cfg.periodic_mask, near_layers(P->cfg), lists[q]);
             }
             merge_forest(trees, lists, poff, P->tree, P->lists, P->box_prob);
         }
         const HostTree& t = P->tree;
+        P->box_send = t.end;
+        P->box_tbeg = t.begin;
+        if (separate && n > 0) {
+            // every leaf's sources first, then its targets, each in (key, index) order: a stable sort
+            // of the sorted points by (leaf begin, is target); then the leaves' source counts
+            const int nl = (int)t.leaves.size();
+            P->leaf_boxes.upload(t.leaves, s);
+            P->b_begin.upload(t.begin, s);
+            P->b_end.upload(t.end, s);
+            P->leaf_nsrc.ensure(nl);
+            P->leaf_nsrc_host.ensure(nl);
+            launch_role_keys(P->leaf_boxes.p, nl, P->b_begin.p, P->b_end.p, P->perm.p, n_src, P->keys_a.p,
+                             P->leaf_nsrc.p, s);
+            radix_sort_pairs(P->keys_a.p, P->keys_b.p, P->perm.p, P->vals_a.p, n, P->sort_temp, s, 1, nullptr, 33);
+            P->perm.swap(P->vals_a);
+            launch_gather_points(P->u_wrapped.p, P->perm.p, n, P->xs.p, s);
+            PK_HIP(hipMemcpyAsync(P->leaf_nsrc_host.p, P->leaf_nsrc.p, sizeof(int) * nl, hipMemcpyDeviceToHost, s));
+            PK_HIP(hipStreamSynchronize(s));
+            for (int i = 0; i < nl; ++i) {
+                const int b = t.leaves[i];
+                P->box_send[b] = P->box_tbeg[b] = t.begin[b] + P->leaf_nsrc_host.p[i];
+            }
+        }
+        P->b_send.upload(P->box_send, s);
         P->b_level.upload(t.level, s);
         P->b_ix.upload(t.ix, s);
         P->b_iy.upload(t.iy, s);
@@ -1448,7 +1689,7 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
         for (int b : t.leaves)
             for (int64_t e = P->lists.u_off[b]; e < P->lists.u_off[b + 1]; ++e) {
                 int a = P->lists.u[e].src;
-                up += (int64_t)(t.end[b] - t.begin[b]) * (t.end[a] - t.begin[a]);
+                up += (int64_t)(t.end[b] - P->box_tbeg[b]) * (P->box_send[a] - t.begin[a]);
             }
         st.u_pairs = up;
     } catch (const Error& e) {
@@ -1460,14 +1701,31 @@ int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* count
     return PKIFMM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int pkifmm_set_points(pkifmm_plan* P, int64_t n_src, const double* src_xyz, int64_t n_trg, const double* trg_xyz,
+                      void* stream) {
+    if (n_src < 0) return P ? fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n_src")) : PKIFMM_ERR_INVALID_ARG;
+    return set_points_impl(P, 1, &n_src, src_xyz, n_trg, trg_xyz, stream);
+}
+
+int pkifmm_set_points_batch(pkifmm_plan* P, int n_problems, const int64_t* counts, const double* xyz, void* stream) {
+    return set_points_impl(P, n_problems, counts, xyz, 0, nullptr, stream);
+}
+
 int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potential, void* stream) {
     if (!P) return PKIFMM_ERR_INVALID_ARG;
     if (!P->have_points) return fail(P, Error(PKIFMM_ERR_NO_POINTS, "set_points has not succeeded"));
-    if (R < 1 || (P->n > 0 && (!density || !potential))) return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n_rhs or pointers"));
+    if (R < 1 || (P->n_src > 0 && !density) || (P->n_out > 0 && !potential))
+        return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n_rhs or pointers"));
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
+    P->allocator.stream = stream;
+    AllocScope scope(&P->allocator);
     try {
-        if (P->n == 0) return PKIFMM_OK;
+        if (P->n == 0 || P->n_out == 0) return PKIFMM_OK;
         // new work lists (another n_rhs) overwrite lists and workspace that an evaluation still in
         // flight may read: wait for it first.  Otherwise the stream is ordered after the previous
         // evaluation on the device, whichever stream that ran on.
@@ -1522,10 +1780,11 @@ int pkifmm_evaluate(pkifmm_plan* P, int R, const double* density, double* potent
 int pkifmm_evaluate_noalloc(pkifmm_plan* P, int R, const double* density, double* potential, void* stream) {
     if (!P) return PKIFMM_ERR_INVALID_ARG;
     if (!P->have_points) return fail(P, Error(PKIFMM_ERR_NO_POINTS, "set_points has not succeeded"));
-    if (R < 1 || (P->n > 0 && (!density || !potential))) return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n_rhs or pointers"));
+    if (R < 1 || (P->n_src > 0 && !density) || (P->n_out > 0 && !potential))
+        return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n_rhs or pointers"));
     hipStream_t s = (hipStream_t)stream;
     try {
-        if (P->n == 0) return PKIFMM_OK;
+        if (P->n == 0 || P->n_out == 0) return PKIFMM_OK;
         // the work lists live in plan buffers, made by pkifmm_evaluate for this n_rhs
         if (P->R_built != R)
             throw Error(PKIFMM_ERR_INVALID_ARG, "no work lists for this n_rhs on these points: call pkifmm_evaluate "
@@ -1551,6 +1810,99 @@ int pkifmm_evaluate_noalloc(pkifmm_plan* P, int R, const double* density, double
         }
         P->capturing = false;
     } catch (const Error& e) {
+        return fail(P, e);
+    }
+    return PKIFMM_OK;
+}
+
+int pkifmm_autotune(pkifmm_plan* P, int R, const double* density, double* potential, void* stream,
+                    const char* tuning_file) {
+    if (!P) return PKIFMM_ERR_INVALID_ARG;
+    if (!P->have_points) return fail(P, Error(PKIFMM_ERR_NO_POINTS, "set_points has not succeeded"));
+    if (R < 1 || (P->n_src > 0 && !density) || (P->n_out > 0 && !potential))
+        return fail(P, Error(PKIFMM_ERR_INVALID_ARG, "n_rhs or pointers"));
+    hipStream_t s = (hipStream_t)stream;
+    P->allocator.stream = stream;
+    AllocScope scope(&P->allocator);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    try {
+        if (P->n == 0 || P->n_out == 0) return PKIFMM_OK;
+        wait_idle(P);
+        PK_HIP(hipEventCreate(&e0));
+        PK_HIP(hipEventCreate(&e1));
+        Tuning start;
+        for (const TuneRec& rec : P->tune_table)
+            if (rec.R == R) start = rec.t;
+        P->tune_fixed = true;
+        // median of 3 timed evaluations (after one untimed) with the choices t
+        auto timed = [&](const Tuning& t) {
+            P->tune = t;
+            std::vector<float> ms;
+            for (int rep = 0; rep < 4; ++rep) {
+                Workspace w;
+                PK_HIP(hipEventRecord(e0, s));
+                enqueue_evaluate(P, w, R, density, potential, s, false, false, P->R_built != R);
+                PK_HIP(hipEventRecord(e1, s));
+                PK_HIP(hipEventSynchronize(e1));
+                float m = 0.f;
+                PK_HIP(hipEventElapsedTime(&m, e0, e1));
+                if (rep > 0) ms.push_back(m);
+            }
+            std::sort(ms.begin(), ms.end());
+            return (double)ms[ms.size() / 2];
+        };
+        Tuning best = start;
+        double t_best = timed(best);
+        auto descend = [&](int Tuning::*field, std::initializer_list<int> values) {
+            for (int v : values) {
+                if (v == best.*field) continue;
+                Tuning t = best;
+                t.*field = v;
+                const double tt = timed(t);
+                if (tt < 0.99 * t_best) {   // a change must win by more than the timing noise
+                    best = t;
+                    t_best = tt;
+                }
+            }
+        };
+        descend(&Tuning::near_wpc, {2, 3, 4, 6});
+        if (R > 1) {
+            if (P->k == 1) {
+                descend(&Tuning::rb_near, {2, 4, 8, 16});
+                descend(&Tuning::rb_s2m, {2, 4, 8});
+            } else {
+                descend(&Tuning::rb_near, {2, 4});
+                descend(&Tuning::rb_s2m, {2, 4});
+            }
+        }
+        P->tune_fixed = false;
+        P->tune = best;
+        bool found = false;
+        for (TuneRec& rec : P->tune_table)
+            if (rec.R == R) {
+                rec.t = best;
+                found = true;
+            }
+        if (!found) P->tune_table.push_back(TuneRec{R, best});
+        ++P->generation;              // a captured graph of the old choices is recaptured
+        P->stats.tune_ms = t_best;
+        if (tuning_file && tuning_file[0]) {
+            TuneLine l;
+            l.arch = P->arch;
+            l.kernel = P->cfg.kernel;
+            l.mask = P->cfg.periodic_mask;
+            l.p = P->cfg.p;
+            l.precision = P->cfg.precision;
+            l.R = R;
+            l.t = best;
+            if (!write_tuning_record(tuning_file, l)) throw Error(PKIFMM_ERR_INVALID_ARG, "tuning file not writable");
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    } catch (const Error& e) {
+        P->tune_fixed = false;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
         return fail(P, e);
     }
     return PKIFMM_OK;
@@ -1582,7 +1934,20 @@ int pkifmm_get_stats(pkifmm_plan* P, pkifmm_stats* out) {
         P->stats.n_timed = cnt;
         for (int i = 0; i < PKIFMM_NUM_PHASES; ++i) P->stats.ms_phase[i] = cnt ? sum[i] / cnt : 0.0;
     }
+    P->stats.tune_near_wpc = P->tune.near_wpc;
+    P->stats.tune_rb_near = P->tune.rb_near;
+    P->stats.tune_rb_s2m = P->tune.rb_s2m;
     *out = P->stats;
+    return PKIFMM_OK;
+}
+
+int pkifmm_get_solve_factors(const pkifmm_plan* P, int which, int* rank, double* Ut, double* VS) {
+    if (!P || !rank || (which != 0 && which != 1)) return PKIFMM_ERR_INVALID_ARG;
+    const std::vector<double>& u = which == 0 ? P->f_up_Ut : P->f_dn_Ut;
+    const std::vector<double>& v = which == 0 ? P->f_up_VS : P->f_dn_VS;
+    *rank = which == 0 ? P->r_up : P->r_dn;
+    if (Ut) std::memcpy(Ut, u.data(), sizeof(double) * u.size());
+    if (VS) std::memcpy(VS, v.data(), sizeof(double) * v.size());
     return PKIFMM_OK;
 }
 
@@ -1663,6 +2028,7 @@ const char* pkifmm_status_string(int s) {
         case PKIFMM_ERR_NO_POINTS: return "no points set";
         case PKIFMM_ERR_NUMERICS: return "operator construction failed its self-check";
         case PKIFMM_ERR_CAPACITY: return "workspace exceeds the static array";
+        case PKIFMM_ERR_CACHE_CORRUPT: return "operator cache file fails its checks";
         default: return "unknown status";
     }
 }

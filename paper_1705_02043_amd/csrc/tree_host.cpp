@@ -19,6 +19,7 @@
 //   X(B)  all (A, p) with (B, -p) in W(A)
 // The root has no V list; its far field is the periodic root operator.
 #include <algorithm>
+#include <cstdlib>
 #include <unordered_map>
 
 #include "internal.h"
@@ -301,6 +302,31 @@ extern "C" int pkifmm_host_topology(const uint64_t* keys, int64_t n, int s, unsi
 }
 
 namespace pk {
+
+// Near-field layer l > 1 (Section 3.6): the root's images with 2 <= |p|_inf <= l along the periodic
+// axes act on the root through its upward equivalent density (M2L by the offset p at level 0),
+// leaving the images |p|_inf > l to the far-field operator.  They become the root's V list, in
+// (source, shift) order.
+void add_root_ring(const HostTree& t, unsigned mask, int layers, HostLists& L) {
+    if (layers <= 1 || mask == 0 || t.nbox() == 0) return;
+    std::vector<Entry> ring;
+    const int lim[3] = {mask & 1u ? layers : 0, mask & 2u ? layers : 0, mask & 4u ? layers : 0};
+    for (int x = -lim[0]; x <= lim[0]; ++x)
+        for (int y = -lim[1]; y <= lim[1]; ++y)
+            for (int z = -lim[2]; z <= lim[2]; ++z)
+                if (std::max(std::abs(x), std::max(std::abs(y), std::abs(z))) >= 2)
+                    ring.push_back(Entry{0, (int8_t)x, (int8_t)y, (int8_t)z});
+    std::sort(ring.begin(), ring.end());
+    const int root = t.level_start[0];
+    std::vector<Entry> v;
+    v.reserve(L.v.size() + ring.size());
+    v.insert(v.end(), L.v.begin(), L.v.begin() + L.v_off[root]);
+    v.insert(v.end(), L.v.begin() + L.v_off[root], L.v.begin() + L.v_off[root + 1]);
+    v.insert(v.end(), ring.begin(), ring.end());
+    v.insert(v.end(), L.v.begin() + L.v_off[root + 1], L.v.end());
+    for (size_t b = root + 1; b < L.v_off.size(); ++b) L.v_off[b] += (int64_t)ring.size();
+    L.v.swap(v);
+}
 
 // Several independent trees as one forest: boxes renumbered level-major (all
 // problems' level-0 boxes, then level 1, ...), problems in order within a

@@ -38,6 +38,10 @@ def test_status_strings_and_bad_config():
     assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_INVALID_ARG
     cfg.periodic_mask, cfg.flags = 7, 16           # no such flag
     assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_INVALID_ARG
+    cfg.flags = 0
+    cfg.alloc = pk.ALLOC_FN(lambda ctx, n, s: None)   # an allocator without its free
+    assert L.pkifmm_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == pk.ERR_INVALID_ARG
+    assert L.pkifmm_status_string(pk.ERR_CACHE_CORRUPT).startswith(b"operator cache")
     assert L.pkifmm_plan_destroy(None) == 0
 
 
@@ -104,3 +108,42 @@ def test_binding_refuses_density_arguments_before_any_library_call():
                 torch.zeros(2, 1, 10, 3, dtype=torch.float64)):          # wrong rank
         with pytest.raises(ValueError):
             plan.evaluate(bad)
+
+
+def _fnv1a(data: bytes) -> int:
+    h = 1469598103934665603
+    for b in data:
+        h = ((h ^ b) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def _cache_file(path, kn=6, r_up=5, r_dn=4, seed=0):
+    """An operator cache file in the library's layout (header, five arrays, FNV-1a checksum)."""
+    import struct
+    rng = np.random.default_rng(seed)
+    head = b"PKIFMMOP" + struct.pack("<IiIiiiiiddd", 1, 2, 7, 4, kn, r_up, r_dn, 0, 1e-11, 3.0, 2.0)
+    assert len(head) == 64
+    body = b"".join(rng.random(n).tobytes() for n in (r_up * kn, kn * r_up, r_dn * kn, kn * r_dn, kn * kn))
+    data = head + body
+    with open(path, "wb") as f:
+        f.write(data + _fnv1a(data).to_bytes(8, "little"))
+    return data
+
+
+def test_operator_cache_check_on_the_host(tmp_path):
+    """The cache file checks run on the CPU: a well-formed file passes; a flipped bit, a truncated
+    file, a wrong magic or a missing file are refused."""
+    L = pk.lib()
+    good = str(tmp_path / "ops.bin")
+    data = _cache_file(good)
+    assert L.pkifmm_operator_cache_check(good.encode()) == pk.OK
+    for name, mutate in (("flip", lambda d: d[:100] + bytes([d[100] ^ 4]) + d[101:]),
+                         ("short", lambda d: d[:-9]),
+                         ("magic", lambda d: b"PKIFMMOX" + d[8:])):
+        full = open(good, "rb").read()
+        bad = str(tmp_path / f"{name}.bin")
+        with open(bad, "wb") as f:
+            f.write(mutate(full))
+        assert L.pkifmm_operator_cache_check(bad.encode()) == pk.ERR_CACHE_CORRUPT, name
+    assert L.pkifmm_operator_cache_check(str(tmp_path / "none.bin").encode()) == pk.ERR_INVALID_ARG
+    assert len(data) == 64 + 8 * (2 * 5 * 6 + 2 * 4 * 6 + 36)

@@ -153,3 +153,21 @@ def test_separate_targets_that_repeat_the_sources():
     assert _rel(sep, same) < 2e-4
     none = kifmm.KIFMM(pb.kernel, 7, 6, 40, pb.points, targets=np.zeros((0, 3))).evaluate(pb.density[0])
     assert none.shape == (0, 3)
+
+
+@pytest.mark.parametrize("kernel,mask,agree", [(K.STOKES, 7, 1e-10), (K.LAPLACE, 1, 1e-9), (K.LAPLACE, 7, 1e-12)])
+def test_near_layer_option(kernel, mask, agree):
+    """Section 3.6: a near field of l = 1, 2 or 3 layers of images (the root's image ring
+    2 <= |p|_inf <= l as its V list, the far-field operator over |p|_inf > l) gives the same result
+    to the FMM's accuracy (Table 4: "almost indistinguishable"); each against the periodic sum."""
+    pb = (W.stokes_tp_uniform(n=300, seed=14, s=30, p=6) if kernel == K.STOKES
+          else W.laplace_sp_uniform(n=400, seed=16, s=30, mask=mask))
+    ex = periodic.exact_potential(kernel, mask, pb.points, pb.points, pb.density[0])
+    res = {}
+    for lay in (1, 2, 3):
+        f = kifmm.KIFMM(kernel, mask, pb.p, 30, pb.points, near_layers=lay)
+        ring = len(f.lists.V.get(0, []))
+        assert ring == (0 if lay == 1 else ((2 * lay + 1) ** 3 - 27 if mask == 7 else 2 * (lay - 1)))
+        res[lay] = f.evaluate(pb.density[0])
+        assert _rel(res[lay], ex) < (5e-4 if kernel == K.STOKES else 1e-6)
+    assert _rel(res[2], res[1]) < agree and _rel(res[3], res[1]) < agree
