@@ -604,3 +604,58 @@ def test_clustered_stokes_p12_sampled():
     err = np.sqrt(num / den)
     print(f"clustered p=12 mixed sampled rel L2 {err:.3e} over {len(pick)} leaves x 4 RHS", flush=True)
     assert err < 1e-6
+    # against the periodic sum itself (structure-factor Ewald at 1000 sampled targets, 4 RHS): the
+    # configuration aims at 1e-8; the float32 near field rounds at ~1e-7 of the potentials
+    idx, val = _exact_subsample("c5")
+    err_exact = _rel(out[:, idx], val)
+    print(f"clustered p=12 mixed against the exact sum at {len(idx)} targets x 4 RHS: rel L2 {err_exact:.3e}",
+          flush=True)
+    assert err_exact < 1e-6
+
+
+@pytest.mark.timeout(1100)
+def test_clustered_stokes_p12_fp64_against_the_exact_sum():
+    """The same clustered configuration in the float64 form against the exact sum at the 1000
+    sampled targets: the KIFMM error of p = 12 alone, set against the configuration's 1e-8 aim."""
+    pk = _pk()
+    pb = W.stokes_tp_clustered()
+    plan = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=0)
+    plan.set_points(_dev(pb.points))
+    out = plan.evaluate(_dev(pb.density)).cpu().numpy()
+    idx, val = _exact_subsample("c5")
+    err = _rel(out[:, idx], val)
+    print(f"clustered p=12 fp64 against the exact sum at {len(idx)} targets x 4 RHS: rel L2 {err:.3e}", flush=True)
+    assert err < 1e-7
+
+
+@pytest.mark.parametrize("kernel,mask,layers", [(2, 7, 2), (2, 7, 3), (1, 1, 2), (1, 7, 3)])
+def test_near_layers_parity(kernel, mask, layers):
+    """Section 3.6's near-field layer l = 2, 3: the root's image ring (its V list, bit-exact) by
+    M2L, the far-field operator over |p|_inf > l; both forms against the oracle with the same l,
+    and within the FMM's accuracy of l = 1 (Table 4)."""
+    pk = _pk()
+    pb = (W.stokes_tp_uniform(n=20000, seed=21, p=8, s=600) if kernel == pk.STOKES
+          else W.laplace_sp_uniform(n=3000, seed=23, p=6, s=60, mask=mask))
+    f = okifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points, near_layers=layers)
+    ref = np.stack([f.evaluate(d) for d in pb.density])
+    base = None
+    for precision, tol in ((0, FP64_TOL), (1, 1e-6)):
+        plan = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=precision, near_layers=layers)
+        plan.set_points(_dev(pb.points))
+        off, ent = plan.lists("V")
+        assert [(int(e[0]), (int(e[1]), int(e[2]), int(e[3]))) for e in ent[off[0]:off[1]]] == list(f.lists.V[0])
+        out = plan.evaluate(_dev(pb.density)).cpu().numpy()
+        err = _rel(out, ref)
+        print(f"layers={layers} kernel={kernel} mask={mask} precision={precision}: rel L2 {err:.3e}", flush=True)
+        assert err < tol
+        if precision == 0:
+            base = out
+    one = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=0)
+    one.set_points(_dev(pb.points))
+    # moving the root's ring from the near sums to M2L changes the result by the truncation error
+    # of the order-p expansions: ~1e-7 at p = 6 (the Laplace cases), below 1e-8 at p = 8
+    assert _rel(base, one.evaluate(_dev(pb.density)).cpu().numpy()) < (1e-8 if pb.p >= 8 else 1e-6)
+    if kernel == pk.STOKES:
+        with pytest.raises(pk.PkifmmError) as e:
+            pk.Plan(pk.STOKES, 3, 6, 64, near_layers=2)
+        assert e.value.status == pk.ERR_UNSUPPORTED
