@@ -366,6 +366,8 @@ def main():
         "roofline": roofline,
         "launch_choices": {"near_workgroups_per_cu": st["tune_near_wpc"], "rhs_per_near_pass": st["tune_rb_near"],
                            "rhs_per_s2m_pass": st["tune_rb_s2m"],
+                           "m2l_int8_tile": f'{st["tune_m2l_rows"]}x64',
+                           "near_tile": "2 targets per thread x 256 threads, 256-source LDS tiles",
                            "source": ("autotuner record in " + os.path.relpath(pk.TUNING_FILE, ROOT)
                                       if os.path.exists(pk.TUNING_FILE) else "library defaults")},
     }

@@ -190,6 +190,7 @@ typedef struct {
     int tune_rb_near;            /* workgroups per compute unit; right-hand sides per geometry pass of */
     int tune_rb_s2m;             /* the near field and of the points-to-surface sums (0: the most) */
     double tune_ms;              /* pkifmm_autotune: the best evaluation time it measured */
+    int tune_m2l_rows;           /* mixed form: operator rows per tile of the int8 M2L (64 or 128) */
 } pkifmm_stats;
 
 /* Fill `cfg` with defaults: Laplace, free space, p = 8, s = 64, FP64, L = 1, no operator cache,
@@ -309,9 +310,11 @@ int pkifmm_get_solve_factors(const pkifmm_plan *plan, int which, int *rank, doub
 
 /*
  * Choose the launch parameters of the evaluation for the current points and n_rhs by timing it
- * (coordinate descent, median of 3 timed evaluations per candidate): the near field's
- * workgroups per compute unit, and the right-hand sides that share one pass over the geometry
- * in the near field and in the points-to-surface sums.  Only choices that leave every result
+ * (coordinate descent, median of 5 timed evaluations per candidate, a change kept only if it
+ * wins by more than 2 %): the near field's
+ * workgroups per compute unit, the right-hand sides that share one pass over the geometry
+ * in the near field and in the points-to-surface sums, and (mixed form) the operator rows per
+ * tile of the int8 M2L (64 or 128; the int32 sums are exact either way).  Only choices that leave every result
  * bit unchanged are tuned (each sum is formed in the same order whichever is taken).  The plan
  * keeps the best choice for this n_rhs; with tuning_file non-NULL its record (architecture,
  * kernel, periodic axes, p, precision, n_rhs) is added to or replaced in that file, which

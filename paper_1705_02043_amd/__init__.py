@@ -58,7 +58,7 @@ class pkifmm_stats(ctypes.Structure):
                 ("ms_set_points", ctypes.c_double), ("ms_evaluate", ctypes.c_double),
                 ("n_timed", ctypes.c_int), ("ms_phase", ctypes.c_double * 5),
                 ("close_points", ctypes.c_int), ("tune_near_wpc", ctypes.c_int), ("tune_rb_near", ctypes.c_int),
-                ("tune_rb_s2m", ctypes.c_int), ("tune_ms", ctypes.c_double)]
+                ("tune_rb_s2m", ctypes.c_int), ("tune_ms", ctypes.c_double), ("tune_m2l_rows", ctypes.c_int)]
 
 PHASES = ["near", "up", "m2l", "down", "leaf"]
 
@@ -273,7 +273,7 @@ class Plan:
                                      ctypes.c_void_p(res.data_ptr()), _stream_ptr(stream), path), self._h)
         st = self.stats()
         return {"near_wpc": st["tune_near_wpc"], "rb_near": st["tune_rb_near"], "rb_s2m": st["tune_rb_s2m"],
-                "ms": st["tune_ms"]}
+                "m2l_rows": st["tune_m2l_rows"], "ms": st["tune_ms"]}
 
     def stats(self) -> dict:
         st = pkifmm_stats()

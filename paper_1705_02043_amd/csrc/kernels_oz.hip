@@ -14,10 +14,15 @@
 // shift).  The float64 form keeps its float64 GEMM.
 //
 // Layouts (int8): operator slices [op][S][Mp][Kp], row-major, K contiguous; column slices
-// [S][col][Kp].  Mp and Kp are kn rounded up to 64 and the padding is zero, so the GEMM has no
-// bounds checks in its K loop.  Output tiles, gathered input columns, output columns and
-// scales are those of the float64 grouped GEMM (Tile lists of 64 x 64, per-entry column lists
-// with the right-hand side expanded on the device).
+// [S][col][Kp].  Mp is kn rounded up to 128 (the tile's rows) and Kp to 64, and the padding is
+// zero, so the GEMM has no bounds checks in its K loop.  Gathered input columns, output columns
+// and scales are those of the float64 grouped GEMM (per-entry column lists with the right-hand
+// side expanded on the device).  Two tilings give the same bits (the int32 sums are exact and
+// the epilogue is the same): 64 x 64 tiles (the float64 GEMM's list, column block outer), and
+// 128 x 64 tiles in operator, row block, column block order, so that the workgroups of one XCD
+// that run together share an operator row block in L2 (half the L2 misses, at one workgroup
+// per compute unit).  Which one is faster depends on the workload and on what runs beside it;
+// it is a tuning choice.
 #include "launch.h"
 
 namespace pk {
@@ -115,12 +120,12 @@ __global__ __launch_bounds__(256) void k_oz_col_slices(const double* __restrict_
     }
 }
 
-// Grouped gather GEMM on the sliced operands.  A 64 x 64 output tile per workgroup: four waves,
+// Grouped gather GEMM on the sliced operands, 64-row tiles.  A 64 x 64 output tile per workgroup: four waves,
 // 32 x 32 each = 2 x 2 blocks of 16 x 16; K staged through LDS 64 at a time (all S slices of
 // the A rows and the gathered B columns), the next stage loaded into registers while the
 // current one is multiplied.  Rows of LDS are padded to 80 bytes.
 template <int S>
-__global__ __launch_bounds__(256) void k_gemm_oz(OzArgs a) {
+__global__ __launch_bounds__(256) void k_gemm_oz64(OzArgs a) {
     const int per = (a.n_tiles + 7) / 8;                  // XCD-aware order, as the float64 GEMM
     const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (logical >= a.n_tiles) return;
@@ -215,12 +220,151 @@ __global__ __launch_bounds__(256) void k_gemm_oz(OzArgs a) {
     }
 }
 
+
+// LDS position (in 16-byte chunks) of chunk c of staged row r: the four chunks of a 64-byte row
+// are permuted by XOR with ((r / 2) XOR (r / 8)) mod 4.  A 16-byte LDS read is served eight
+// lanes at a time, 128 bytes per clock: the eight consecutive rows that eight lanes read for
+// one fragment (one chunk each), and the two rows that eight lanes write, then fall into eight
+// distinct 16-byte bank groups, with no padding.
+__device__ __forceinline__ int oz_swz(int r, int c) { return r * 4 + (c ^ (((r >> 1) ^ (r >> 3)) & 3)); }
+
+// Grouped gather GEMM on the sliced operands, 128-row tiles.  A 128 x 64 output tile per workgroup of eight
+// waves, two per SIMD, each 32 x 32 (2 x 2 blocks of 16 x 16, S x 4 int32 accumulator blocks).
+// K is staged through LDS 64 at a time (all S slices of the 128 operator rows and of the 64
+// gathered columns) in two buffers, one barrier per stage: during stage k a wave multiplies
+// from one buffer, writes stage k + 1 (loaded into registers during stage k - 1) to the other
+// and loads stage k + 2, and reads the fragments of slice ta + 1 while slice ta is multiplied.
+// Per stage a wave reads (2 + 2) x S fragments for 4 x S(S+1)/2 matrix instructions; the two
+// waves of a SIMD overlap each other's reads and matrix instructions.
+template <int S>
+__global__ __launch_bounds__(512, 1) void k_gemm_oz128(OzArgs a) {
+    constexpr int BM = kOzRows, BN = kTile, ROWS = BM + BN;
+    constexpr int kStage = S * ROWS * 4;                  // one stage buffer, in 16-byte chunks
+    static_assert(S % 2 == 0, "the column staging splits the slices in two halves");
+    const int per = (a.n_tiles + 7) / 8;                  // XCD-aware order, as the float64 GEMM
+    const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (logical >= a.n_tiles) return;
+    const Tile t = a.tiles[logical];
+    const int8_t* __restrict__ A = a.a_sl + (int64_t)t.op * S * a.Mp * a.Kp;
+    __shared__ v4i sm[2 * kStage];
+    __shared__ int s_in[BN];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 3) * 32, wn = (wave >> 2) * 32;
+    if (tid < BN) {
+        const int j = t.col0 + tid, e = j / a.rhs;
+        s_in[tid] = tid < t.ncol ? a.in_col[e] * a.rhs + (j - e * a.rhs) : -1;
+    }
+    __syncthreads();
+    // staging: thread tid moves 16-byte chunk c = tid % 4 of operator row r = tid / 4 for every
+    // slice, and of gathered column r % 64 for slices (r / 64) S/2 .. (r / 64) S/2 + S/2 - 1;
+    // four consecutive lanes read one row's 64 contiguous bytes.  A padding column reads column
+    // 0 of the slices (in bounds); its outputs are never stored.
+    const int c = tid & 3, r = tid >> 2, rb = r & 63;
+    const int sb0 = __builtin_amdgcn_readfirstlane((tid >> 8) * (S / 2));   // uniform per wave
+    const int bcol = s_in[rb];
+    // per-lane 32-bit offsets from wave-uniform slice bases (the scalar-base load form)
+    const unsigned oa = (unsigned)(r * a.Kp + c * 16);
+    const unsigned ob = (unsigned)((bcol >= 0 ? bcol : 0) * a.Kp + c * 16);
+    const int8_t* ar = A + (int64_t)t.row0 * a.Kp;
+    const int64_t astride = (int64_t)a.Mp * a.Kp;
+    const int wa = oz_swz(r, c), wb = oz_swz(BM + rb, c);
+    v4i ra[S], rbv[S / 2];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) ra[s] = *(const v4i*)(ar + s * astride + k0 + oa);
+        const int8_t* bs = a.b_sl + sb0 * a.b_slice_stride + k0;
+#pragma unroll
+        for (int h = 0; h < S / 2; ++h) rbv[h] = *(const v4i*)(bs + h * a.b_slice_stride + ob);
+    };
+    auto store = [&](v4i* buf) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) buf[s * ROWS * 4 + wa] = ra[s];
+#pragma unroll
+        for (int h = 0; h < S / 2; ++h) buf[(sb0 + h) * ROWS * 4 + wb] = rbv[h];
+    };
+    // fragment positions: A block i (rows wm + 16 i + lane % 16), B block j (columns
+    // wn + 16 j + lane % 16), K chunk lane / 16
+    int fa[2], fb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) fa[i] = oz_swz(wm + 16 * i + (lane & 15), lane >> 4);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) fb[j] = oz_swz(BM + wn + 16 * j + (lane & 15), lane >> 4);
+    v4i acc[S][2][2];
+#pragma unroll
+    for (int g = 0; g < S; ++g)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[g][i][j] = v4i{0, 0, 0, 0};
+    const int nk = a.Kp / kTile;
+    load(0);
+    store(sm);
+    if (nk > 1) load(kTile);
+    __syncthreads();
+    for (int k = 0; k < nk; ++k) {
+        const v4i* cur = sm + (k & 1) * kStage;
+        v4i* nxt = sm + ((k + 1) & 1) * kStage;
+        v4i bf[S][2], af[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) af[0][i] = cur[fa[i]];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bf[s][j] = cur[s * ROWS * 4 + fb[j]];
+#pragma unroll
+        for (int ta = 0; ta < S; ++ta) {
+            if (ta + 1 < S) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) af[(ta + 1) & 1][i] = cur[(ta + 1) * ROWS * 4 + fa[i]];
+            }
+#pragma unroll
+            for (int ub = 0; ub < S - ta; ++ub)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[ta + ub][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[ta & 1][i], bf[ub][j],
+                                                                                   acc[ta + ub][i][j], 0, 0, 0);
+            if (ta == 1 && k + 1 < nk) {            // stage k + 1 to the other buffer, stage k + 2 in flight
+                store(nxt);
+                if (k + 2 < nk) load((k + 2) * kTile);
+            }
+        }
+        __syncthreads();
+    }
+    // D layout of a 16 x 16 block: lane holds column (lane & 15) and rows (lane >> 4) * 4 + v
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int n = wn + 16 * j + (lane & 15);
+        if (n >= t.ncol) continue;
+        const int fe = a.b_exp[s_in[n]];
+        const int jj = t.col0 + n, e = jj / a.rhs;
+        const int oc = a.out_col[e] * a.rhs + (jj - e * a.rhs);
+        const double sc = a.scale[e];
+        double* C = a.C + (int64_t)oc * a.ldc;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = t.row0 + wm + 16 * i + (lane >> 4) * 4 + v;
+                if (row >= a.M) continue;
+                double val = 0.0;
+#pragma unroll
+                for (int g = S - 1; g >= 0; --g) val += ldexp((double)acc[g][i][j][v], -7 * (g + 2));
+                const double res = sc * ldexp(val, a.a_exp[(int64_t)t.op * a.Mp + row] + fe);
+                C[row] = a.accumulate ? C[row] + res : res;
+            }
+    }
+}
+
 }  // namespace
 
 int oz_padded(int n) { return (n + kTile - 1) / kTile * kTile; }
+int oz_rows_padded(int n) { return (n + kOzRows - 1) / kOzRows * kOzRows; }
 
 void launch_oz_slice_operators(const double* ops, int n_ops, int M, int K, int8_t* out, int* e, hipStream_t s) {
-    const int Mp = oz_padded(M), Kp = oz_padded(K);
+    const int Mp = oz_rows_padded(M), Kp = oz_padded(K);
     const int64_t nr = (int64_t)n_ops * Mp;
     hipLaunchKernelGGL(k_oz_row_exp, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, ops, n_ops, M, K, Mp, e);
     PK_HIP(hipGetLastError());
@@ -237,9 +381,12 @@ void launch_oz_slice_columns(const double* B, int64_t ldb, int K, int64_t ncols,
     PK_HIP(hipGetLastError());
 }
 
-void launch_gemm_oz(const OzArgs& a, hipStream_t s) {
+void launch_gemm_oz(const OzArgs& a, int rows, hipStream_t s) {
     if (a.n_tiles == 0) return;
-    hipLaunchKernelGGL(k_gemm_oz<kOzSlices>, dim3((unsigned)((a.n_tiles + 7) / 8 * 8)), dim3(256), 0, s, a);
+    if (rows == kOzRows)
+        hipLaunchKernelGGL(k_gemm_oz128<kOzSlices>, dim3((unsigned)((a.n_tiles + 7) / 8 * 8)), dim3(512), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_gemm_oz64<kOzSlices>, dim3((unsigned)((a.n_tiles + 7) / 8 * 8)), dim3(256), 0, s, a);
     PK_HIP(hipGetLastError());
 }
 

@@ -159,10 +159,11 @@ void launch_segment_reduce(const double* temp, const int64_t* off, const int* bo
 
 // ---- M2L on the int8 matrix cores with exact accumulation (kernels_oz.hip), mixed form
 constexpr int kOzSlices = 6;          // base-2^7 digits per operand entry
+constexpr int kOzRows = 128;          // output rows per tile of the int8 GEMM (columns: 64)
 struct OzArgs {
     const int8_t* a_sl;   // operator slices [op][kOzSlices][Mp][Kp]
     const int* a_exp;     // [op][Mp] row exponents
-    int Mp, Kp, M;        // padded rows and K (multiples of 64), real rows
+    int Mp, Kp, M;        // padded rows (multiple of kOzRows) and K (of 64), real rows
     const int8_t* b_sl;   // column slices [kOzSlices][ncols][Kp]
     const int* b_exp;     // [ncols] column exponents
     int64_t b_slice_stride;   // ncols * Kp
@@ -176,12 +177,14 @@ struct OzArgs {
     int rhs;              // right-hand sides (>= 1)
     int accumulate;
 };
-int oz_padded(int n);     // n rounded up to the GEMM's 64
+int oz_padded(int n);          // n rounded up to the GEMM's K stage (64)
+int oz_rows_padded(int n);     // n rounded up to kOzRows
 // operators: n_ops column-major M x K float64 matrices, consecutive
 void launch_oz_slice_operators(const double* ops, int n_ops, int M, int K, int8_t* out, int* e, hipStream_t s);
 // columns c < ncols of B (at B + c * ldb, K rows)
 void launch_oz_slice_columns(const double* B, int64_t ldb, int K, int64_t ncols, int8_t* out, int* e, hipStream_t s);
-void launch_gemm_oz(const OzArgs& a, hipStream_t s);
+// rows: 64 (tiles of the float64 GEMM's list) or kOzRows (the 128-row list); the same bits
+void launch_gemm_oz(const OzArgs& a, int rows, hipStream_t s);
 
 // ---- operator construction (kernels_ops.hip), raw kernels (no 1/(4pi), 1/(8pi))
 // out[(k*i+a) + (k*j+b)*ld] = K(X_i - Y_j)_{ab}; X, Y: [m][3], [n][3]

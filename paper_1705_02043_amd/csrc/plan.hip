@@ -102,6 +102,7 @@ struct Tuning {
     int near_wpc = 4;       // near-field workgroups per compute unit taking items from the counter
     int rb_near = 0;        // right-hand sides per near-field geometry pass (0: 16 Laplace, 4 Stokes)
     int rb_s2m = 0;         // right-hand sides per points-to-surface pass (0: 8 Laplace, 4 Stokes)
+    int m2l_rows = 64;      // operator rows per tile of the mixed form's int8 M2L (64 or 128)
 };
 struct TuneRec {
     int R;
@@ -245,6 +246,7 @@ struct pkifmm_plan {
     std::vector<GemmRange> g_up1, g_up2, g_dn1, g_dn2, g_l2l;   // per level
     GemmRange g_root;
     std::vector<GemmRange> g_m2l;                        // per offset group
+    std::vector<GemmRange> g_m2l_wide;                   // the same, 128-row tiles (mixed form)
     std::vector<std::pair<int, int>> m2l_targets;        // per group: (first, count) in v_gtargets
     DBuf<int64_t> v_goff;                                // per group: CSR over boxes of temp slots
     DBuf<int> v_gtargets;
@@ -822,6 +824,7 @@ void build_stage_m2l(pkifmm_plan* P, int R) {
     const HostLists& L = P->lists;
     const int nb = t.nbox();
     const int kn = P->kn;
+    const bool mixed = P->cfg.precision == PKIFMM_MIXED;
     hipStream_t s = P->setup_stream2;
     Gemm g;
     auto range = [&](auto&& fill) {
@@ -879,6 +882,7 @@ void build_stage_m2l(pkifmm_plan* P, int R) {
         }
         for (int q = 0; q < kM2LGroups; ++q) goff[(size_t)q * (nb + 1) + nb] = slot_count[q];
         P->g_m2l.assign(kM2LGroups, GemmRange());
+        P->g_m2l_wide.assign(kM2LGroups, GemmRange());
         P->m2l_targets.assign(kM2LGroups, {});
         if ((int64_t)nv * R >= (int64_t)INT32_MAX) throw Error(PKIFMM_ERR_INVALID_ARG, "too many V-list columns");
         g.in = std::move(in_c);
@@ -896,6 +900,16 @@ void build_stage_m2l(pkifmm_plan* P, int R) {
                             g.tiles.push_back(Tile{d, (int)j, (int)std::min<int64_t>(64, c1 - j), r0});
                 }
             });
+            if (mixed)     // the int8 GEMM's 128-row tiles: operator, row block, column block
+                P->g_m2l_wide[q] = range([&] {
+                    for (int d = 0; d < kNumM2L; ++d) {
+                        if (d * kM2LGroups / kNumM2L != q || per_idx[d + 1] == per_idx[d]) continue;
+                        const int64_t c0 = per_idx[d] * R, c1 = per_idx[d + 1] * R;
+                        for (int r0 = 0; r0 < kn; r0 += kOzRows)
+                            for (int64_t j = c0; j < c1; j += 64)
+                                g.tiles.push_back(Tile{d, (int)j, (int)std::min<int64_t>(64, c1 - j), r0});
+                    }
+                });
             P->m2l_targets[q] = {(int)all_targets.size(), (int)gtarg[q].size()};
             all_targets.insert(all_targets.end(), gtarg[q].begin(), gtarg[q].end());
             max_slots = std::max(max_slots, slot_count[q]);
@@ -951,13 +965,13 @@ void run_gemm(pkifmm_plan* P, const Workspace& w, const GemmRange& gr, const dou
 // M2L of the mixed form: the same tiles and column lists on the int8 slices of the operators
 // and of the upward densities (sliced once per evaluation, all nbox*R columns)
 void run_gemm_oz(pkifmm_plan* P, const Workspace& w, const GemmRange& gr, int R, double* C, int64_t ldc,
-                 hipStream_t s) {
+                 hipStream_t s, int rows) {
     if (gr.ntile == 0) return;
     const int kp = oz_padded(P->kn);
     OzArgs a{};
     a.a_sl = P->m2l_oz.p;
     a.a_exp = P->m2l_oz_e.p;
-    a.Mp = kp;
+    a.Mp = oz_rows_padded(P->kn);
     a.Kp = kp;
     a.M = P->kn;
     a.b_sl = w.phi_oz;
@@ -973,7 +987,7 @@ void run_gemm_oz(pkifmm_plan* P, const Workspace& w, const GemmRange& gr, int R,
     a.scale = G.col_scale.p;
     a.rhs = R;
     a.accumulate = 0;
-    launch_gemm_oz(a, s);
+    launch_gemm_oz(a, rows, s);
 }
 
 void run_p2p(pkifmm_plan* P, const Workspace& ws, const SegRange& w, double* out_pts, double* out_surf, int R, bool f32,
@@ -1095,8 +1109,9 @@ size_t carve_workspace(const pkifmm_plan* P, int R, char* base, Workspace& w) {
     return off;
 }
 
-// Tuning files: one record per line, "arch kernel mask p precision n_rhs near_wpc rb_near rb_s2m";
-// '#' starts a comment.  A missing file is empty; a malformed line is skipped.
+// Tuning files: one record per line, "arch kernel mask p precision n_rhs near_wpc rb_near rb_s2m
+// m2l_rows" (a record without m2l_rows takes 64); '#' starts a comment.  A missing file is empty;
+// a malformed line is skipped.
 struct TuneLine {
     std::string arch;
     int kernel = 0;
@@ -1114,9 +1129,10 @@ std::vector<TuneLine> read_tuning_file(const char* path) {
         if (char* c = std::strchr(line, '#')) *c = 0;
         char arch[64];
         TuneLine l;
-        if (std::sscanf(line, "%63s %d %u %d %d %d %d %d %d", arch, &l.kernel, &l.mask, &l.p, &l.precision, &l.R,
-                        &l.t.near_wpc, &l.t.rb_near, &l.t.rb_s2m) == 9 &&
-            l.R >= 1 && l.t.near_wpc >= 1 && l.t.near_wpc <= 16 && l.t.rb_near >= 0 && l.t.rb_s2m >= 0) {
+        const int nf = std::sscanf(line, "%63s %d %u %d %d %d %d %d %d %d", arch, &l.kernel, &l.mask, &l.p,
+                                   &l.precision, &l.R, &l.t.near_wpc, &l.t.rb_near, &l.t.rb_s2m, &l.t.m2l_rows);
+        if ((nf == 9 || nf == 10) && l.R >= 1 && l.t.near_wpc >= 1 && l.t.near_wpc <= 16 && l.t.rb_near >= 0 &&
+            l.t.rb_s2m >= 0 && (l.t.m2l_rows == 64 || l.t.m2l_rows == kOzRows)) {
             l.arch = arch;
             out.push_back(l);
         }
@@ -1139,10 +1155,10 @@ bool write_tuning_record(const char* path, const TuneLine& rec) {
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "w");
     if (!f) return false;
-    std::fprintf(f, "# arch kernel mask p precision n_rhs near_wpc rb_near rb_s2m (pkifmm_autotune)\n");
+    std::fprintf(f, "# arch kernel mask p precision n_rhs near_wpc rb_near rb_s2m m2l_rows (pkifmm_autotune)\n");
     for (const TuneLine& l : lines)
-        std::fprintf(f, "%s %d %u %d %d %d %d %d %d\n", l.arch.c_str(), l.kernel, l.mask, l.p, l.precision, l.R,
-                     l.t.near_wpc, l.t.rb_near, l.t.rb_s2m);
+        std::fprintf(f, "%s %d %u %d %d %d %d %d %d %d\n", l.arch.c_str(), l.kernel, l.mask, l.p, l.precision, l.R,
+                     l.t.near_wpc, l.t.rb_near, l.t.rb_s2m, l.t.m2l_rows);
     const bool ok = std::fclose(f) == 0;
     return ok && std::rename(tmp.c_str(), path) == 0;
 }
@@ -1285,7 +1301,8 @@ void enqueue_evaluate(pkifmm_plan* P, Workspace& w, int R, const double* density
         for (int q = 0; q < kM2LGroups; ++q) {
             if (P->g_m2l[q].ntile == 0) continue;
             if (mixed)
-                run_gemm_oz(P, w, P->g_m2l[q], R, w.m2l_tmp, kn, s);
+                run_gemm_oz(P, w, P->tune.m2l_rows == kOzRows ? P->g_m2l_wide[q] : P->g_m2l[q], R, w.m2l_tmp, kn, s,
+                            P->tune.m2l_rows == kOzRows ? kOzRows : 64);
             else
                 run_gemm(P, w, P->g_m2l[q], P->m2l.p, kk, kn, kn, w.phi_u, kn, w.m2l_tmp, kn, false, s, 1, false, R);
             launch_segment_reduce(w.m2l_tmp, P->v_goff.p + (size_t)q * (t.nbox() + 1),
@@ -1500,9 +1517,9 @@ int pkifmm_plan_create(const pkifmm_config* cfg, pkifmm_plan** out) {
             opcache_write(cache_file, b);
         }
         if (cfg->precision == PKIFMM_MIXED) {   // M2L of the mixed form runs on int8 slices
-            const int kp = oz_padded(kn);
-            P->m2l_oz.ensure((size_t)kNumM2L * kOzSlices * kp * kp);
-            P->m2l_oz_e.ensure((size_t)kNumM2L * kp);
+            const int kp = oz_padded(kn), mp = oz_rows_padded(kn);
+            P->m2l_oz.ensure((size_t)kNumM2L * kOzSlices * mp * kp);
+            P->m2l_oz_e.ensure((size_t)kNumM2L * mp);
             launch_oz_slice_operators(P->m2l.p, kNumM2L, kn, kn, P->m2l_oz.p, P->m2l_oz_e.p, s);
         }
         P->err_flag.ensure(2);
@@ -1834,11 +1851,11 @@ int pkifmm_autotune(pkifmm_plan* P, int R, const double* density, double* potent
         for (const TuneRec& rec : P->tune_table)
             if (rec.R == R) start = rec.t;
         P->tune_fixed = true;
-        // median of 3 timed evaluations (after one untimed) with the choices t
+        // median of 5 timed evaluations (after one untimed) with the choices t
         auto timed = [&](const Tuning& t) {
             P->tune = t;
             std::vector<float> ms;
-            for (int rep = 0; rep < 4; ++rep) {
+            for (int rep = 0; rep < 6; ++rep) {
                 Workspace w;
                 PK_HIP(hipEventRecord(e0, s));
                 enqueue_evaluate(P, w, R, density, potential, s, false, false, P->R_built != R);
@@ -1859,13 +1876,14 @@ int pkifmm_autotune(pkifmm_plan* P, int R, const double* density, double* potent
                 Tuning t = best;
                 t.*field = v;
                 const double tt = timed(t);
-                if (tt < 0.99 * t_best) {   // a change must win by more than the timing noise
+                if (tt < 0.98 * t_best) {   // a change must win by more than the timing noise (~1-2 %)
                     best = t;
                     t_best = tt;
                 }
             }
         };
         descend(&Tuning::near_wpc, {2, 3, 4, 6});
+        if (P->cfg.precision == PKIFMM_MIXED) descend(&Tuning::m2l_rows, {64, kOzRows});
         if (R > 1) {
             if (P->k == 1) {
                 descend(&Tuning::rb_near, {2, 4, 8, 16});
@@ -1937,6 +1955,7 @@ int pkifmm_get_stats(pkifmm_plan* P, pkifmm_stats* out) {
     P->stats.tune_near_wpc = P->tune.near_wpc;
     P->stats.tune_rb_near = P->tune.rb_near;
     P->stats.tune_rb_s2m = P->tune.rb_s2m;
+    P->stats.tune_m2l_rows = P->tune.m2l_rows;
     *out = P->stats;
     return PKIFMM_OK;
 }

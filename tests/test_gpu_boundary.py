@@ -149,24 +149,28 @@ def test_autotune_records_and_reuses_bit_neutral_choices(tmp_path, kernel, n_rhs
     dens = _dev(pb.density)
     ref = base.evaluate(dens).cpu().numpy()
     st0 = base.stats()
-    assert (st0["tune_near_wpc"], st0["tune_rb_near"], st0["tune_rb_s2m"]) == (4, 0, 0)   # the defaults
+    assert (st0["tune_near_wpc"], st0["tune_rb_near"], st0["tune_rb_s2m"], st0["tune_m2l_rows"]) == (4, 0, 0, 64)
     choice = base.autotune(dens, tuning_file=path)
     print(f"kernel {kernel}, {n_rhs} RHS: tuned {choice}", flush=True)
     lines = [l.split() for l in open(path) if not l.startswith("#")]
     assert len(lines) == 1 and lines[0][0].startswith("gfx") and int(lines[0][5]) == n_rhs
-    assert [int(v) for v in lines[0][6:]] == [choice["near_wpc"], choice["rb_near"], choice["rb_s2m"]]
+    assert [int(v) for v in lines[0][6:]] == [choice["near_wpc"], choice["rb_near"], choice["rb_s2m"],
+                                              choice["m2l_rows"]]
     assert np.array_equal(base.evaluate(dens).cpu().numpy(), ref)
     tuned = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=1, tuning_file=path)
     tuned.set_points(_dev(pb.points))
     assert np.array_equal(tuned.evaluate(dens).cpu().numpy(), ref)
     st = tuned.stats()
-    assert (st["tune_near_wpc"], st["tune_rb_near"], st["tune_rb_s2m"]) == \
-        (choice["near_wpc"], choice["rb_near"], choice["rb_s2m"])
-    # every candidate of the near-field residency and of the block caps gives the same bits
-    odd = str(tmp_path / "odd.txt")
-    with open(odd, "w") as f:
-        f.write(f"{lines[0][0]} {pb.kernel} {pb.periodic_mask} {pb.p} 1 {n_rhs} 2 2 1\n")
-    other = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=1, tuning_file=odd)
-    other.set_points(_dev(pb.points))
-    assert np.array_equal(other.evaluate(dens).cpu().numpy(), ref)
-    assert other.stats()["tune_near_wpc"] == 2
+    assert (st["tune_near_wpc"], st["tune_rb_near"], st["tune_rb_s2m"], st["tune_m2l_rows"]) == \
+        (choice["near_wpc"], choice["rb_near"], choice["rb_s2m"], choice["m2l_rows"])
+    # every candidate of the near-field residency, of the block caps and of the int8 M2L tiling
+    # gives the same bits (a record without the tiling column takes 64 rows)
+    for rec, rows in ((f"2 2 1", 64), (f"3 1 2 128", 128), (f"4 0 0 64", 64)):
+        odd = str(tmp_path / "odd.txt")
+        with open(odd, "w") as f:
+            f.write(f"{lines[0][0]} {pb.kernel} {pb.periodic_mask} {pb.p} 1 {n_rhs} {rec}\n")
+        other = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=1, tuning_file=odd)
+        other.set_points(_dev(pb.points))
+        assert np.array_equal(other.evaluate(dens).cpu().numpy(), ref), rec
+        so = other.stats()
+        assert (so["tune_near_wpc"], so["tune_m2l_rows"]) == (int(rec.split()[0]), rows)

@@ -659,3 +659,44 @@ def test_near_layers_parity(kernel, mask, layers):
         with pytest.raises(pk.PkifmmError) as e:
             pk.Plan(pk.STOKES, 3, 6, 64, near_layers=2)
         assert e.value.status == pk.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("case", ["laplace_sp_p8", "stokes_dp_slab_p10", "stokes_tp_p6_batch_rhs3"])
+def test_int8_m2l_tilings_give_the_same_bits(tmp_path, case):
+    """The mixed form's int8 M2L with 64-row tiles (the float64 GEMM's list) and with 128-row
+    tiles (operator rows padded to 128: 384 for Laplace p = 8, 1536 for Stokes p = 10) gives the
+    same bits: its int32 digit sums are exact whichever tiling forms them, and the epilogue is
+    the same.  Includes a batch of uneven problems with 3 right-hand sides."""
+    pk = _pk()
+    if case == "laplace_sp_p8":
+        probs = [W.laplace_sp_uniform(n=20000, seed=61, p=8, s=100)]
+    elif case == "stokes_dp_slab_p10":
+        probs = [W.stokes_dp_slab(n=30000, seed=62, p=10, s=600)]
+    else:
+        probs = [W.stokes_tp_uniform(n=n, seed=63 + i, p=6, s=300, n_rhs=3) for i, n in enumerate((9000, 2500, 40))]
+    pb = probs[0]
+    xyz = _dev(np.concatenate([q.points for q in probs]))
+    dens = _dev(np.concatenate([q.density for q in probs], axis=1))
+    outs = []
+    for rows in (64, 128):
+        path = str(tmp_path / f"t{rows}.txt")
+        with open(path, "w") as f:
+            arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+            f.write(f"{arch} {pb.kernel} {pb.periodic_mask} {pb.p} 1 {dens.shape[0]} 4 0 0 {rows}\n")
+        plan = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=1, tuning_file=path)
+        if len(probs) == 1:
+            plan.set_points(xyz)
+        else:
+            plan.set_points_batch([q.n for q in probs], xyz)
+        outs.append(plan.evaluate(dens).cpu().numpy())
+        assert plan.stats()["tune_m2l_rows"] == rows
+        plan.close()
+    assert np.array_equal(outs[0], outs[1])
+    if case == "laplace_sp_p8":        # and against the oracle (the 64-row path is checked everywhere else)
+        f = okifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
+        leaves = f.tree.leaves()
+        pick = [leaves[i] for i in sorted(np.random.default_rng(5).choice(len(leaves), 2, replace=False))]
+        sub = f.evaluate(pb.density[0], target_leaves=pick)
+        idx = np.concatenate([f.tree.perm[f.tree.begin[b]:f.tree.end[b]] for b in pick])
+        ref = np.concatenate([sub[b] for b in pick])
+        assert _rel(outs[1][0][idx], ref) < 1e-6
