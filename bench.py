@@ -65,9 +65,10 @@ def near_traffic():
     return float(vals["near phase HBM bytes per launch"]), vals.get("source", "")
 
 
-def time_form(pk, torch, pb, precision, steps, warmup):
+def time_form(pk, torch, pb, precision, steps, warmup, tuning_file=None):
     t_plan = time.perf_counter()
-    plan = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=precision, flags=pk.PHASE_TIMING)
+    plan = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=precision, flags=pk.PHASE_TIMING,
+                   tuning_file=tuning_file or pk.TUNING_FILE)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t_plan
     xyz = torch.as_tensor(pb.points, device="cuda")
@@ -223,6 +224,70 @@ def paper_configs(pk, torch, W, ps, steps=2, warmup=1):
     return res
 
 
+def layer_configs(pk, torch, W, ps, steps=3, warmup=1):
+    """Section 3.6, Table 4 (context): the 97^3 Chebyshev points, Stokes, triply periodic,
+    s = 1000, with the near-field layer l = 1, 2, 3 (the root's image ring by M2L, the far-field
+    operator over |p|_inf > l), both forms; set_points + evaluate per step and the device phase
+    times.  The paper's tau_N and tau_F stay almost constant in l; so should these."""
+    res = []
+    pb = None
+    for p in ps:
+        pb = W.stokes_paper_points("chebyshev", 7, p)
+        xyz = torch.as_tensor(pb.points, device="cuda")
+        dens = torch.as_tensor(pb.density, device="cuda")
+        for prec in (pk.MIXED, pk.FP64):
+            for layers in (1, 2, 3):
+                plan = pk.Plan(pk.STOKES, 7, p, 1000, precision=prec, flags=pk.PHASE_TIMING, near_layers=layers)
+                out = torch.empty_like(dens)
+                for _ in range(warmup):
+                    plan.set_points(xyz)
+                    plan.evaluate(dens, out=out)
+                torch.cuda.synchronize()
+                plan.stats()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    plan.set_points(xyz)
+                    plan.evaluate(dens, out=out)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) / steps * 1e3
+                st = plan.stats()
+                rec = {"p": p, "near_layers": layers, "precision": "mixed" if prec == pk.MIXED else "fp64",
+                       "ms_per_step": ms, "ms_phase": st["ms_phase"], "n_v": st["n_v"]}
+                res.append(rec)
+                log(f"layers p={p} l={layers} {rec['precision']}: {ms:.1f} ms/step, near {st['ms_phase']['near']:.1f} ms")
+                plan.close()
+        del xyz, dens
+    return res
+
+
+def precompute_configs(pk, torch, ps):
+    """Section 3.7, Tables 5 and 6 (context): operator precompute (plan creation: kernel
+    matrices, the two check-to-equivalent SVDs, M2M/L2L/M2L operators, the periodic far-field
+    operator by lattice and Ewald sums, and for the mixed form the int8 slices) for Laplace DP and
+    Stokes TP at l = 1, 2, 3 (Laplace DP: l = 1 only), float64 form; and the same plan loaded
+    from the operator cache."""
+    import tempfile
+    res = []
+    with tempfile.TemporaryDirectory() as d:
+        for kern, mask, name, layers in ((pk.LAPLACE, 3, "laplace_dp", (1,)), (pk.STOKES, 7, "stokes_tp", (1, 2, 3))):
+            for p in ps:
+                for l in layers:
+                    t0 = time.perf_counter()
+                    plan = pk.Plan(kern, mask, p, 1000, precision=pk.FP64, near_layers=l, operator_cache_dir=d)
+                    torch.cuda.synchronize()
+                    t_build = time.perf_counter() - t0
+                    plan.close()
+                    t0 = time.perf_counter()
+                    plan = pk.Plan(kern, mask, p, 1000, precision=pk.FP64, near_layers=l, operator_cache_dir=d)
+                    torch.cuda.synchronize()
+                    t_cache = time.perf_counter() - t0
+                    plan.close()
+                    rec = {"kernel": name, "p": p, "near_layers": l, "s_build": t_build, "s_from_cache": t_cache}
+                    res.append(rec)
+                    log(f"precompute {name} p={p} l={l}: built {t_build:.2f} s, from the cache {t_cache:.2f} s")
+    return res
+
+
 def cpu_baseline_runs(pb, repeats=3, one_core_leaves=3):
     """The oracle on the whole workload, `repeats` times on every host core (the median is the
     reported value), and once on one core over a bounded sample (tree, lists and the whole upward
@@ -304,6 +369,14 @@ def main():
                     help="comma-separated p values (6..16): also time the paper's 97^3 Chebyshev and "
                          "lognormal Stokes workloads (free, SP, DP, TP; s = 1000) and add them under "
                          "'paper_configs'")
+    ap.add_argument("--layers", default="",
+                    help="comma-separated p values: also time the 97^3 Chebyshev TP Stokes workload at near-field "
+                         "layers l = 1, 2, 3 (both forms) and add them under 'layer_configs'")
+    ap.add_argument("--precompute", default="",
+                    help="comma-separated p values: also time operator precompute (plan creation) for Laplace DP "
+                         "and Stokes TP (l = 1, 2, 3) and from the operator cache; under 'precompute'")
+    ap.add_argument("--tuning-file", default="",
+                    help="launch choices for the N = 1M line (default: the package's tuning file)")
     ap.add_argument("--forms", default="fp64,mixed",
                     help="forms to time: 'fp64,mixed' (default) or 'mixed' alone (for counter passes)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -328,9 +401,9 @@ def main():
     forms = args.forms.split(",")
     r64 = out64 = None
     if "fp64" in forms:
-        r64, out64 = time_form(pk, torch, pb, pk.FP64, args.steps, args.warmup)
+        r64, out64 = time_form(pk, torch, pb, pk.FP64, args.steps, args.warmup, args.tuning_file)
         log(f"fp64: {r64['s_total'] / args.steps * 1e3:.2f} ms/step")
-    rmx, outmx = time_form(pk, torch, pb, pk.MIXED, args.steps, args.warmup)
+    rmx, outmx = time_form(pk, torch, pb, pk.MIXED, args.steps, args.warmup, args.tuning_file)
     log(f"mixed: {rmx['s_total'] / args.steps * 1e3:.2f} ms/step")
     ms_step = rmx["s_total"] / args.steps * 1e3
     st = rmx["stats"]
@@ -368,7 +441,8 @@ def main():
                            "rhs_per_s2m_pass": st["tune_rb_s2m"],
                            "m2l_int8_tile": f'{st["tune_m2l_rows"]}x64',
                            "near_tile": "2 targets per thread x 256 threads, 256-source LDS tiles",
-                           "source": ("autotuner record in " + os.path.relpath(pk.TUNING_FILE, ROOT)
+                           "source": (args.tuning_file if args.tuning_file else
+                                      "autotuner record in " + os.path.relpath(pk.TUNING_FILE, ROOT)
                                       if os.path.exists(pk.TUNING_FILE) else "library defaults")},
     }
     if r64 is not None:
@@ -382,6 +456,10 @@ def main():
         rec["other_configs"] = other_configs(pk, torch, W)
     if args.paper:
         rec["paper_configs"] = paper_configs(pk, torch, W, [int(x) for x in args.paper.split(",")])
+    if args.layers:
+        rec["layer_configs"] = layer_configs(pk, torch, W, [int(x) for x in args.layers.split(",")])
+    if args.precompute:
+        rec["precompute"] = precompute_configs(pk, torch, [int(x) for x in args.precompute.split(",")])
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb, (f, sub) = cpu_baseline_runs(pb)
