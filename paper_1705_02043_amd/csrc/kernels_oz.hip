@@ -120,10 +120,18 @@ __global__ __launch_bounds__(256) void k_oz_col_slices(const double* __restrict_
     }
 }
 
+// LDS position (in 16-byte chunks) of chunk c of staged row r: the four 16-byte chunks of a
+// 64-byte row are permuted by XOR with (r / 2) mod 4.  Measured on gfx950 with a probe of 16
+// waves: 16-byte reads of one chunk from 16 consecutive rows (a fragment) and 16-byte writes of
+// four consecutive lanes to one row's four chunks run at the conflict-free rate with this
+// permutation, while rows padded to 80 bytes, plain 64-byte rows and the XOR with (r / 4) mod 4
+// or ((r / 2) XOR (r / 8)) mod 4 read at half of it.
+__device__ __forceinline__ int oz_swz(int r, int c) { return r * 4 + (c ^ ((r >> 1) & 3)); }
+
 // Grouped gather GEMM on the sliced operands, 64-row tiles.  A 64 x 64 output tile per workgroup: four waves,
 // 32 x 32 each = 2 x 2 blocks of 16 x 16; K staged through LDS 64 at a time (all S slices of
-// the A rows and the gathered B columns), the next stage loaded into registers while the
-// current one is multiplied.  Rows of LDS are padded to 80 bytes.
+// the A rows and the gathered B columns, swizzled as oz_swz), the next stage loaded into
+// registers while the current one is multiplied.
 template <int S>
 __global__ __launch_bounds__(256) void k_gemm_oz64(OzArgs a) {
     const int per = (a.n_tiles + 7) / 8;                  // XCD-aware order, as the float64 GEMM
@@ -131,8 +139,8 @@ __global__ __launch_bounds__(256) void k_gemm_oz64(OzArgs a) {
     if (logical >= a.n_tiles) return;
     const Tile t = a.tiles[logical];
     const int8_t* __restrict__ A = a.a_sl + (int64_t)t.op * S * a.Mp * a.Kp;
-    __shared__ v4i sA[S][kTile][5];
-    __shared__ v4i sB[S][kTile][5];
+    __shared__ v4i sA[S][kTile * 4];
+    __shared__ v4i sB[S][kTile * 4];
     __shared__ int s_in[kTile];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -142,11 +150,10 @@ __global__ __launch_bounds__(256) void k_gemm_oz64(OzArgs a) {
         s_in[tid] = tid < t.ncol ? a.in_col[e] * a.rhs + (j - e * a.rhs) : -1;
     }
     __syncthreads();
-    // this thread's share of a stage: 16 bytes at (lane % 4) * 16 of row/column
-    // 16 * wave + 4 * ((lane / 4) % 4) + lane / 16: four consecutive lanes load one row's 64
-    // contiguous bytes, and the 16 lanes of a quarter-wave store rows r, r+4, r+8, r+12, which the
-    // 80-byte row stride places in distinct LDS banks
-    const int sr = 16 * wave + 4 * ((lane >> 2) & 3) + (lane >> 4), sq = lane & 3;
+    // this thread's share of a stage: 16-byte chunk tid % 4 of row/column tid / 4, for every
+    // slice: four consecutive lanes load one row's 64 contiguous bytes
+    const int sr = tid >> 2, sq = tid & 3;
+    const int ws = oz_swz(sr, sq);
     const int bcol = s_in[sr];
     const int8_t* ap = A + (int64_t)(t.row0 + sr) * a.Kp + sq * 16;
     // a padding column reads column 0 of the slices (in bounds) and is masked to zero
@@ -167,8 +174,8 @@ __global__ __launch_bounds__(256) void k_gemm_oz64(OzArgs a) {
     for (int k0 = 0; k0 < a.Kp; k0 += kTile) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            sA[s][sr][sq] = ra[s];
-            sB[s][sr][sq] = rb[s] & bmask;
+            sA[s][ws] = ra[s];
+            sB[s][ws] = rb[s] & bmask;
         }
         __syncthreads();
         if (k0 + kTile < a.Kp) {                          // next stage in flight
@@ -183,8 +190,8 @@ __global__ __launch_bounds__(256) void k_gemm_oz64(OzArgs a) {
 #pragma unroll
         for (int s = 0; s < S; ++s)
             for (int i = 0; i < 2; ++i) {
-                af[s][i] = sA[s][wm + 16 * i + (lane & 15)][lane >> 4];
-                bf[s][i] = sB[s][wn + 16 * i + (lane & 15)][lane >> 4];
+                af[s][i] = sA[s][oz_swz(wm + 16 * i + (lane & 15), lane >> 4)];
+                bf[s][i] = sB[s][oz_swz(wn + 16 * i + (lane & 15), lane >> 4)];
             }
 #pragma unroll
         for (int ta = 0; ta < S; ++ta)
@@ -221,12 +228,6 @@ __global__ __launch_bounds__(256) void k_gemm_oz64(OzArgs a) {
 }
 
 
-// LDS position (in 16-byte chunks) of chunk c of staged row r: the four chunks of a 64-byte row
-// are permuted by XOR with ((r / 2) XOR (r / 8)) mod 4.  A 16-byte LDS read is served eight
-// lanes at a time, 128 bytes per clock: the eight consecutive rows that eight lanes read for
-// one fragment (one chunk each), and the two rows that eight lanes write, then fall into eight
-// distinct 16-byte bank groups, with no padding.
-__device__ __forceinline__ int oz_swz(int r, int c) { return r * 4 + (c ^ (((r >> 1) ^ (r >> 3)) & 3)); }
 
 // Grouped gather GEMM on the sliced operands, 128-row tiles.  A 128 x 64 output tile per workgroup of eight
 // waves, two per SIMD, each 32 x 32 (2 x 2 blocks of 16 x 16, S x 4 int32 accumulator blocks).

@@ -5,8 +5,10 @@ python -m paper_1705_02043_amd.tune [--out FILE]
 Runs pkifmm_autotune (bit-neutral launch choices: near-field workgroups per compute unit and the
 right-hand sides per geometry pass) on the Stokes triply periodic workload (N = 1M, p = 8,
 s = 2000; both forms), the 64-problem singly periodic Laplace forest (16 right-hand sides,
-p = 8, s = 2000; mixed form) and the doubly periodic Stokes slab (N = 4M, p = 10, s = 2000; mixed
-form), and writes their records to FILE (default: the package's tuning file, which Plan reads).
+p = 8, s = 2000; mixed form), the doubly periodic Stokes slab (N = 4M, p = 10, s = 2000; mixed
+form) and the clustered triply periodic Stokes points (N = 16M, p = 12, 4 right-hand sides;
+mixed form), and writes their records to FILE (default: the package's tuning file, which Plan
+reads).
 """
 from __future__ import annotations
 
@@ -25,7 +27,7 @@ def main():
     import workloads as W
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=pk.TUNING_FILE)
-    ap.add_argument("--skip-large", action="store_true", help="skip the 4M-point slab")
+    ap.add_argument("--skip-large", action="store_true", help="skip the 4M-point slab and the 16M clustered points")
     args = ap.parse_args()
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
 
@@ -52,6 +54,11 @@ def main():
         pb = W.stokes_dp_slab()
         xyz, dens = torch.as_tensor(pb.points, device="cuda"), torch.as_tensor(pb.density, device="cuda")
         tune("stokes_dp_slab_n4m_p10", pb.kernel, pb.periodic_mask, pb.p, pb.s, pk.MIXED,
+             lambda pl: pl.set_points(xyz), dens)
+        del xyz, dens
+        pb = W.stokes_tp_clustered()
+        xyz, dens = torch.as_tensor(pb.points, device="cuda"), torch.as_tensor(pb.density, device="cuda")
+        tune("stokes_tp_clustered_n16m_p12_rhs4", pb.kernel, pb.periodic_mask, pb.p, pb.s, pk.MIXED,
              lambda pl: pl.set_points(xyz), dens)
     print(open(args.out).read(), flush=True)
 
