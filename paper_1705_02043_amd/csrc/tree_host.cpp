@@ -22,7 +22,8 @@
 #include <cstdlib>
 #include <unordered_map>
 
-#include "internal.h"
+#include "pkifmm.h"
+#include "topology.h"
 
 namespace pk {
 
