@@ -1,10 +1,11 @@
-"""Write the exact triply periodic Stokes sums at sampled targets of the two triply periodic
-workloads (uniform N = 1M; 200 Gaussian clusters + 20 % uniform, N = 16M, 4 right-hand sides),
+"""Write the exact triply periodic Stokes sums at sampled targets of the triply periodic
+workloads (uniform N = 1M; 200 Gaussian clusters + 20 % uniform, N = 16M, 4 right-hand sides;
+the paper's 97^3 Chebyshev points of Section 3.5, whose density does not depend on p),
 by the oracle's structure-factor Ewald sum alone (oracle/_native.tp_ewald_targets, pinned against
 the pairwise Ewald sum in tests/test_oracle_targets_ewald.py).  The GPU tests read them to state
 the method's error against the definition at full size.
 
-python tests/golden/make_tp_exact_subsample.py [c2|c5 ...]   (c5 takes tens of minutes on 8 cores)
+python tests/golden/make_tp_exact_subsample.py [c2|c5|paper_cheb ...]   (c5 takes tens of minutes on 8 cores)
 """
 import os
 import sys
@@ -21,6 +22,7 @@ from oracle import _native                 # noqa: E402
 CASES = {
     "c2": (lambda: W.stokes_tp_uniform(), 1000, 20),
     "c5": (lambda: W.stokes_tp_clustered(), 1000, 21),
+    "paper_cheb": (lambda: W.stokes_paper_points("chebyshev", W.TP), 300, 22),
 }
 
 

@@ -700,3 +700,35 @@ def test_int8_m2l_tilings_give_the_same_bits(tmp_path, case):
         idx = np.concatenate([f.tree.perm[f.tree.begin[b]:f.tree.end[b]] for b in pick])
         ref = np.concatenate([sub[b] for b in pick])
         assert _rel(outs[1][0][idx], ref) < 1e-6
+
+
+# about twice the measured error (float64: 3.7e-6, 6.8e-8, 3.3e-9, 5.2e-10, 7.7e-11 for p = 8 ... 16;
+# mixed: 3.8e-6 at p = 8, then the float32 near field's floor of 1.1e-7)
+PAPER_CHEB_BOUNDS = {(8, 0): 8e-6, (10, 0): 2e-7, (12, 0): 1e-8, (14, 0): 1.5e-9, (16, 0): 2.5e-10,
+                     (8, 1): 8e-6, (10, 1): 3e-7, (12, 1): 3e-7, (14, 1): 3e-7, (16, 1): 3e-7}
+
+
+@pytest.mark.timeout(1100)
+def test_paper_chebyshev_tp_high_p_against_the_exact_sum():
+    """The paper's 97^3 Chebyshev workload (Section 3.5, Stokes TP, s = 1000) at p = 8 ... 16, both
+    forms, against the periodic sum itself (structure-factor Ewald, k = 0 removed) at 300 sampled
+    targets: the error falls with p, as in Fig. 6 (the oracle's KIFMM cannot run p = 14, 16: its
+    float64 M2L operators alone are 24 and 42 GB)."""
+    pk = _pk()
+    pb = W.stokes_paper_points("chebyshev", W.TP)
+    idx, val = _exact_subsample("paper_cheb")
+    xyz, dens = _dev(pb.points), _dev(pb.density)
+    errs = {}
+    for p in (8, 10, 12, 14, 16):
+        for precision in (0, 1):
+            plan = pk.Plan(pb.kernel, pb.periodic_mask, p, pb.s, precision=precision)
+            plan.set_points(xyz)
+            out = plan.evaluate(dens).cpu().numpy()
+            plan.close()
+            errs[(p, precision)] = _rel(out[0][idx], val[0])
+            print(f"paper Chebyshev TP p={p} precision={precision}: rel L2 against the exact sum "
+                  f"{errs[(p, precision)]:.3e}", flush=True)
+    for (p, precision), e in errs.items():
+        assert e < PAPER_CHEB_BOUNDS[(p, precision)], (p, precision, e)
+    f64 = [errs[(p, 0)] for p in (8, 10, 12, 14, 16)]
+    assert all(b < a for a, b in zip(f64, f64[1:])), f64          # falls with every step of p
