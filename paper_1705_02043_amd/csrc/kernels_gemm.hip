@@ -10,7 +10,7 @@
 //
 // Float64 on the matrix cores: v_mfma_f64_16x16x4f64.  A 64x64 output tile
 // per workgroup (four waves, 32x32 each = 2x2 MFMA blocks), K staged through
-// LDS 16 at a time with the next slice prefetched into registers while the
+// LDS 32 at a time with the next slice prefetched into registers while the
 // current one is multiplied.  Tiles are laid out operator-major and mapped so
 // that the tiles of one operator run on the same XCD (its L2 keeps the
 // operator rows).  Launches with few tiles (the upper tree levels) split K
@@ -24,7 +24,8 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int TM = 64, TN = 64, TK = 16, PAD = 2;
+constexpr int TM = 64, TN = 64, TK = 32, PAD = 2;
+constexpr int kPerThread = TM * TK / 256;    // elements of A (and of B) per thread per K slice
 
 // column j of a tile: its input column (K block kb), output column and scale
 __device__ __forceinline__ int gemm_in(const GemmArgs& a, int j, int kb) {
@@ -45,19 +46,19 @@ __device__ __forceinline__ double gemm_scale(const GemmArgs& a, int j) {
     return a.scale[a.rhs > 0 ? j / a.rhs : j];
 }
 
-struct Stage {     // one thread's share of a K slice: 4 elements of A and 4 of B
-    double a[4], b[4];
+struct Stage {     // one thread's share of a K slice: kPerThread elements of A and of B
+    double a[kPerThread], b[kPerThread];
 };
 
 __device__ __forceinline__ void load_stage(const GemmArgs& a, const Tile& t, const double* __restrict__ A,
                                            const int* s_in, int nkb, int k0, int k_end, int tid, Stage& st) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < kPerThread; ++e) {
         const int idx = tid + 256 * e;
-        const int m = idx & (TM - 1), kk = idx >> 6;
+        const int m = idx & (TM - 1), kk = idx / TM;
         const int row = t.row0 + m, k = k0 + kk;
         st.a[e] = (row < a.M && k < k_end) ? A[row + (int64_t)k * a.M] : 0.0;
-        const int kk2 = idx & (TK - 1), nn = idx >> 4;
+        const int kk2 = idx & (TK - 1), nn = idx / TK;
         const int k2 = k0 + kk2;
         double v = 0.0;
         if (k2 < k_end) {
@@ -99,10 +100,10 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_f64(GemmArgs a, int split, do
     if (k_begin < k_end) load_stage(a, t, A, s_in, nkb, k_begin, k_end, tid, st);
     for (int k0 = k_begin; k0 < k_end; k0 += TK) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < kPerThread; ++e) {
             const int idx = tid + 256 * e;
-            sA[idx >> 6][idx & (TM - 1)] = st.a[e];
-            sB[idx & (TK - 1)][idx >> 4] = st.b[e];
+            sA[idx / TM][idx & (TM - 1)] = st.a[e];
+            sB[idx & (TK - 1)][idx / TK] = st.b[e];
         }
         __syncthreads();
         if (k0 + TK < k_end) load_stage(a, t, A, s_in, nkb, k0 + TK, k_end, tid, st);   // next slice in flight
