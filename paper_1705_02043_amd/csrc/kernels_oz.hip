@@ -128,6 +128,90 @@ __global__ __launch_bounds__(256) void k_oz_col_slices(const double* __restrict_
 // or ((r / 2) XOR (r / 8)) mod 4 read at half of it.
 __device__ __forceinline__ int oz_swz(int r, int c) { return r * 4 + (c ^ ((r >> 1) & 3)); }
 
+// Per-tile epilogue data: the exponents of the tile's rows and, per column, its exponent, output
+// column and scale.  Fetched right after the column list, before the first stage's loads, and
+// parked in LDS once those are in, so that the epilogue reads LDS instead of waiting on a chain
+// of dependent global loads.
+template <int BM>
+struct OzEpi {
+    int ae[BM];
+    int fe[kTile], oc[kTile];
+    double sc[kTile];
+};
+
+// thread tid < BM fetches the exponent of row tid, BM <= tid < BM + 64 the data of column tid - BM
+template <int BM>
+__device__ __forceinline__ void oz_epi_fetch(const OzArgs& a, const Tile& t, const int* s_in, int tid, int& qi,
+                                             int& qo, double& qs) {
+    if (tid < BM) {
+        const int row = t.row0 + tid;
+        qi = row < a.M ? a.a_exp[(int64_t)t.op * a.Mp + row] : 0;
+    } else if (tid < BM + kTile) {
+        const int n = tid - BM;
+        if (n < t.ncol) {
+            const int jj = t.col0 + n, e = jj / a.rhs;
+            qi = a.b_exp[s_in[n]];
+            qo = a.out_col[e] * a.rhs + (jj - e * a.rhs);
+            qs = a.scale[e];
+        }
+    }
+}
+
+template <int BM>
+__device__ __forceinline__ void oz_epi_park(OzEpi<BM>& p, int tid, int qi, int qo, double qs) {
+    if (tid < BM) {
+        p.ae[tid] = qi;
+    } else if (tid < BM + kTile) {
+        p.fe[tid - BM] = qi;
+        p.oc[tid - BM] = qo;
+        p.sc[tid - BM] = qs;
+    }
+}
+
+// A wave's 32 x 32 block of the tile (rows wm.., columns wn..) from its S diagonals: the D layout
+// of a 16 x 16 block gives a lane column lane % 16 and rows 4 (lane / 16) + v, v < 4, so each lane
+// writes four consecutive rows of a column (two 16-byte stores where aligned and in range).
+template <int S, int BM>
+__device__ __forceinline__ void oz_epilogue(const OzArgs& a, const Tile& t, const OzEpi<BM>& p,
+                                            const v4i (&acc)[S][2][2], int wm, int wn, int lane) {
+    typedef double v2d __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int n = wn + 16 * j + (lane & 15);
+        if (n >= t.ncol) continue;
+        const int fe = p.fe[n];
+        const double sc = p.sc[n];
+        double* C = a.C + (int64_t)p.oc[n] * a.ldc;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int lr = wm + 16 * i + (lane >> 4) * 4;
+            const int row = t.row0 + lr;
+            double o[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double val = 0.0;
+#pragma unroll
+                for (int g = S - 1; g >= 0; --g) val += ldexp((double)acc[g][i][j][v], -7 * (g + 2));
+                o[v] = sc * ldexp(val, p.ae[lr + v] + fe);
+            }
+            double* c = C + row;
+            if (row + 3 < a.M && ((uintptr_t)c & 15) == 0) {
+                v2d lo = v2d{o[0], o[1]}, hi = v2d{o[2], o[3]};
+                if (a.accumulate) {
+                    lo = ((const v2d*)c)[0] + lo;
+                    hi = ((const v2d*)c)[1] + hi;
+                }
+                ((v2d*)c)[0] = lo;
+                ((v2d*)c)[1] = hi;
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (row + v < a.M) c[v] = a.accumulate ? c[v] + o[v] : o[v];
+            }
+        }
+    }
+}
+
 // Grouped gather GEMM on the sliced operands, 64-row tiles.  A 64 x 64 output tile per workgroup: four waves,
 // 32 x 32 each = 2 x 2 blocks of 16 x 16; K staged through LDS 64 at a time (all S slices of
 // the A rows and the gathered B columns, swizzled as oz_swz), the next stage loaded into
@@ -142,6 +226,7 @@ __global__ __launch_bounds__(256) void k_gemm_oz64(OzArgs a) {
     __shared__ v4i sA[S][kTile * 4];
     __shared__ v4i sB[S][kTile * 4];
     __shared__ int s_in[kTile];
+    __shared__ OzEpi<kTile> s_epi;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
@@ -150,6 +235,9 @@ __global__ __launch_bounds__(256) void k_gemm_oz64(OzArgs a) {
         s_in[tid] = tid < t.ncol ? a.in_col[e] * a.rhs + (j - e * a.rhs) : -1;
     }
     __syncthreads();
+    int qi = 0, qo = 0;
+    double qs = 0.0;
+    oz_epi_fetch<kTile>(a, t, s_in, tid, qi, qo, qs);
     // this thread's share of a stage: 16-byte chunk tid % 4 of row/column tid / 4, for every
     // slice: four consecutive lanes load one row's 64 contiguous bytes
     const int sr = tid >> 2, sq = tid & 3;
@@ -166,6 +254,7 @@ __global__ __launch_bounds__(256) void k_gemm_oz64(OzArgs a) {
         ra[s] = *(const v4i*)(ap + s * astride);
         rb[s] = *(const v4i*)(bp + s * a.b_slice_stride);
     }
+    oz_epi_park<kTile>(s_epi, tid, qi, qo, qs);           // read after the first barrier below
     v4i acc[S][2][2];
 #pragma unroll
     for (int g = 0; g < S; ++g)
@@ -205,26 +294,7 @@ __global__ __launch_bounds__(256) void k_gemm_oz64(OzArgs a) {
                             __builtin_amdgcn_mfma_i32_16x16x64_i8(af[ta][i], bf[ub][j], acc[ta + ub][i][j], 0, 0, 0);
         __syncthreads();
     }
-    // D layout of a 16 x 16 block: lane holds column (lane & 15) and rows (lane >> 4) * 4 + v
-    for (int j = 0; j < 2; ++j) {
-        const int n = wn + 16 * j + (lane & 15);
-        if (n >= t.ncol) continue;
-        const int fe = s_in[n] >= 0 ? a.b_exp[s_in[n]] : 0;
-        const int jj = t.col0 + n, e = jj / a.rhs;
-        const int oc = a.out_col[e] * a.rhs + (jj - e * a.rhs);
-        const double sc = a.scale[e];
-        double* C = a.C + (int64_t)oc * a.ldc;
-        for (int i = 0; i < 2; ++i)
-            for (int v = 0; v < 4; ++v) {
-                const int row = t.row0 + wm + 16 * i + (lane >> 4) * 4 + v;
-                if (row >= a.M) continue;
-                double val = 0.0;
-#pragma unroll
-                for (int g = S - 1; g >= 0; --g) val += ldexp((double)acc[g][i][j][v], -7 * (g + 2));
-                const double r = sc * ldexp(val, a.a_exp[(int64_t)t.op * a.Mp + row] + fe);
-                C[row] = a.accumulate ? C[row] + r : r;
-            }
-    }
+    oz_epilogue<S, kTile>(a, t, s_epi, acc, wm, wn, lane);
 }
 
 
@@ -249,6 +319,7 @@ __global__ __launch_bounds__(512, 1) void k_gemm_oz128(OzArgs a) {
     const int8_t* __restrict__ A = a.a_sl + (int64_t)t.op * S * a.Mp * a.Kp;
     __shared__ v4i sm[2 * kStage];
     __shared__ int s_in[BN];
+    __shared__ OzEpi<BM> s_epi;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = (wave & 3) * 32, wn = (wave >> 2) * 32;
@@ -257,6 +328,9 @@ __global__ __launch_bounds__(512, 1) void k_gemm_oz128(OzArgs a) {
         s_in[tid] = tid < t.ncol ? a.in_col[e] * a.rhs + (j - e * a.rhs) : -1;
     }
     __syncthreads();
+    int qi = 0, qo = 0;
+    double qs = 0.0;
+    oz_epi_fetch<BM>(a, t, s_in, tid, qi, qo, qs);
     // staging: thread tid moves 16-byte chunk c = tid % 4 of operator row r = tid / 4 for every
     // slice, and of gathered column r % 64 for slices (r / 64) S/2 .. (r / 64) S/2 + S/2 - 1;
     // four consecutive lanes read one row's 64 contiguous bytes.  A padding column reads column
@@ -301,6 +375,7 @@ __global__ __launch_bounds__(512, 1) void k_gemm_oz128(OzArgs a) {
     const int nk = a.Kp / kTile;
     load(0);
     store(sm);
+    oz_epi_park<BM>(s_epi, tid, qi, qo, qs);
     if (nk > 1) load(kTile);
     __syncthreads();
     for (int k = 0; k < nk; ++k) {
@@ -334,29 +409,7 @@ __global__ __launch_bounds__(512, 1) void k_gemm_oz128(OzArgs a) {
         }
         __syncthreads();
     }
-    // D layout of a 16 x 16 block: lane holds column (lane & 15) and rows (lane >> 4) * 4 + v
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int n = wn + 16 * j + (lane & 15);
-        if (n >= t.ncol) continue;
-        const int fe = a.b_exp[s_in[n]];
-        const int jj = t.col0 + n, e = jj / a.rhs;
-        const int oc = a.out_col[e] * a.rhs + (jj - e * a.rhs);
-        const double sc = a.scale[e];
-        double* C = a.C + (int64_t)oc * a.ldc;
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = t.row0 + wm + 16 * i + (lane >> 4) * 4 + v;
-                if (row >= a.M) continue;
-                double val = 0.0;
-#pragma unroll
-                for (int g = S - 1; g >= 0; --g) val += ldexp((double)acc[g][i][j][v], -7 * (g + 2));
-                const double res = sc * ldexp(val, a.a_exp[(int64_t)t.op * a.Mp + row] + fe);
-                C[row] = a.accumulate ? C[row] + res : res;
-            }
-    }
+    oz_epilogue<S, BM>(a, t, s_epi, acc, wm, wn, lane);
 }
 
 }  // namespace
