@@ -202,6 +202,16 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
     }
     if (wi >= a.n_work) break;
     const Work w = a.work[wi];
+    // Target slots: thread tid holds slots s and s + 256, s = 64 ((wave + item) mod 4) + lane.
+    // In the pair-once sweep a wave whose second slots all lie past the item's targets skips
+    // them (two == false); rotating the slot blocks with the item index spreads those lighter
+    // waves over the SIMDs.  A target keeps its lane, and so the order in which it meets its
+    // sources.  The rotation is a per-wave scalar added to tid wherever a slot is formed: one
+    // more vector register live across the item would cost the 4-RHS Stokes variant (168
+    // VGPRs, three waves per SIMD) a third of its residency.
+    const int wv0 = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tshift = (((wv0 + wi) & 3) - wv0) << 6;
+    const bool two = ((wv0 + wi) & 3) * 64 + kThreads < w.tcount;   // uniform per wave
     // target box centre and edge
     const int tlev = a.box_level[w.tbox];
     const double th = ldexp(1.0, -tlev);
@@ -213,8 +223,8 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
     T dt[kTPT][KD];                        // the targets' own densities (kind-3 reverse terms); 0 for padding
     for (int j = 0; j < kTPT; ++j) {
         for (int c = 0; c < ND; ++c) acc[j][c] = 0.0;
-        const int t = w.t0 + min(tid + j * kThreads, max(w.tcount - 1, 0));
-        const bool real = tid + j * kThreads < w.tcount;
+        const int t = w.t0 + min(tid + tshift + j * kThreads, max(w.tcount - 1, 0));
+        const bool real = tid + tshift + j * kThreads < w.tcount;
         for (int c = 0; c < KD; ++c) {
             const int64_t di = ((int64_t)r0 * KD + c) * n + t;
             dt[j][c] = real ? (MIXED ? (T)a.ds32[di] : (T)a.ds[di]) : T(0);
@@ -250,7 +260,7 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
         const double inv_u = MIXED ? ldexp(1.0, lc + 29) : 1.0;
         C ux[kTPT], uy[kTPT], uz[kTPT];
         for (int j = 0; j < kTPT; ++j) {
-            const int t = w.t0 + min(tid + j * kThreads, max(w.tcount - 1, 0));
+            const int t = w.t0 + min(tid + tshift + j * kThreads, max(w.tcount - 1, 0));
             if constexpr (MIXED) {
                 const int e = lc + 29;
                 ux[j] = shr_round(a.ioff[t], kt) + (int)ldexp(tcx - scx, e);
@@ -308,13 +318,14 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
             if constexpr (RB == 1) {
                 if (seg.kind == 3) {
                     const int lane = tid & 63, wv = tid >> 6;
-                    auto sweep = [&](auto guard) {
+                    auto sweep = [&](auto guard, auto slots) {
                         constexpr bool G = decltype(guard)::value;
+                        constexpr int NT = decltype(slots)::value;   // target slots in use
                         for (int g0 = 0; g0 < cnt; g0 += 64) {
                             const int gs = 2 * g0;              // slot of the group's first copy
                             for (int h = 0; h < 64; h += 32) {
-                                T part[kTPT][KD];
-                                for (int j = 0; j < kTPT; ++j)
+                                T part[NT][KD];
+                                for (int j = 0; j < NT; ++j)
                                     for (int c = 0; c < KD; ++c) part[j][c] = T(0);
                                 const int q0 = gs + lane + h;   // this lane's source at step 0 of the half
                                 double* dacc = &s_dacc[wv][0][lane + h];
@@ -325,14 +336,14 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
                                     C sx, sy, sz;
                                     get(q, sx, sy, sz, d);
                                     for (int c = 0; c < KD; ++c) cs[c] = T(0);
-                                    for (int j = 0; j < kTPT; ++j)
+                                    for (int j = 0; j < NT; ++j)
                                         interact_both<KD, G, T>(sep<MIXED>(ux[j], sx), sep<MIXED>(uy[j], sy),
                                                                 sep<MIXED>(uz[j], sz), d, part[j], dt[j], cs);
                                     for (int c = 0; c < KD; ++c)
                                         __hip_atomic_fetch_add(dacc + c * 128 + jj, (double)cs[c], __ATOMIC_RELAXED,
                                                                __HIP_MEMORY_SCOPE_WAVEFRONT);
                                 }
-                                for (int j = 0; j < kTPT; ++j)
+                                for (int j = 0; j < NT; ++j)
                                     for (int c = 0; c < KD; ++c) acc[j][c] += (double)part[j][c] * inv_u;
                             }
                             __syncthreads();
@@ -349,11 +360,15 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
                             __asm__ volatile("" ::: "memory");
                         }
                     };
+                    auto go = [&](auto guard) {
+                        if (two) sweep(guard, std::integral_constant<int, 2>{});
+                        else sweep(guard, std::integral_constant<int, 1>{});
+                    };
                     if constexpr (MIXED) {
-                        if (a.guard_all) sweep(std::true_type{});
-                        else sweep(std::false_type{});
+                        if (a.guard_all) go(std::true_type{});
+                        else go(std::false_type{});
                     } else {
-                        sweep(std::false_type{});
+                        go(std::false_type{});
                     }
                     continue;
                 }
@@ -397,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
         }
     }
     for (int j = 0; j < kTPT; ++j) {
-        const int lt = tid + j * kThreads;
+        const int lt = tid + tshift + j * kThreads;
         if (lt >= w.tcount) continue;
         const int t = w.t0 + lt;
         for (int c = 0; c < ND; ++c) {
