@@ -132,10 +132,32 @@ void m2l_offset_vector(int idx, int& dx, int& dy, int& dz) {
 
 void build_lists_host(const HostTree& t, unsigned mask, HostLists& L) {
     const int nb = t.nbox();
-    // per-level lookup of (ix, iy, iz) -> box
-    std::vector<std::unordered_map<uint64_t, int>> at(t.depth + 1);
-    for (int b = 0; b < nb; ++b)
-        at[t.level[b]][morton3(t.ix[b], t.iy[b], t.iz[b])] = b;
+    // (level, ix, iy, iz) -> box.  The boxes of a level are numbered in Morton order, so the
+    // lookup is a binary search over the level's keys; a tree not in that order (none is built
+    // here) would fall back to hash maps
+    std::vector<uint64_t> key(nb);
+    for (int b = 0; b < nb; ++b) key[b] = morton3(t.ix[b], t.iy[b], t.iz[b]);
+    const int nlev = (int)t.level_start.size() - 1;
+    bool ordered = nlev >= 0 && t.level_start.back() == nb;
+    for (int lv = 0; ordered && lv < nlev; ++lv)
+        for (int b = t.level_start[lv]; b < t.level_start[lv + 1]; ++b)
+            if (t.level[b] != lv || (b > t.level_start[lv] && key[b] <= key[b - 1])) {
+                ordered = false;
+                break;
+            }
+    std::vector<std::unordered_map<uint64_t, int>> at(ordered ? 0 : t.depth + 1);
+    if (!ordered)
+        for (int b = 0; b < nb; ++b) at[t.level[b]][key[b]] = b;
+    auto find = [&](int lv, uint64_t k) -> int {
+        if (!ordered) {
+            auto it = at[lv].find(k);
+            return it == at[lv].end() ? -1 : it->second;
+        }
+        if (lv >= nlev) return -1;
+        const auto lo = key.begin() + t.level_start[lv], hi = key.begin() + t.level_start[lv + 1];
+        const auto it = std::lower_bound(lo, hi, k);
+        return it != hi && *it == k ? (int)(it - key.begin()) : -1;
+    };
 
     auto coord = [&](int b, int c) { return c == 0 ? t.ix[b] : (c == 1 ? t.iy[b] : t.iz[b]); };
     // closed boxes A+p and B touch or overlap
@@ -156,6 +178,7 @@ void build_lists_host(const HostTree& t, unsigned mask, HostLists& L) {
     for (int b = 0; b < nb; ++b) {
         const int lv = t.level[b];
         const int side = 1 << lv;
+        coll[b].reserve(27);
         for (int ox = -1; ox <= 1; ++ox)
             for (int oy = -1; oy <= 1; ++oy)
                 for (int oz = -1; oz <= 1; ++oz) {
@@ -172,8 +195,8 @@ void build_lists_host(const HostTree& t, unsigned mask, HostLists& L) {
                         }
                     }
                     if (!ok) continue;
-                    auto it = at[lv].find(morton3(g[0], g[1], g[2]));
-                    if (it != at[lv].end()) coll[b].push_back({it->second, {p[0], p[1], p[2]}});
+                    const int a = find(lv, morton3(g[0], g[1], g[2]));
+                    if (a >= 0) coll[b].push_back({a, {p[0], p[1], p[2]}});
                 }
         // ordered by (box, shift code): the V lists built from them then come out ordered
         // (children are numbered in their parents' order), and need no sort below
@@ -184,24 +207,26 @@ void build_lists_host(const HostTree& t, unsigned mask, HostLists& L) {
     }
     auto mk = [](int a, const int p[3]) { return Entry{a, (int8_t)p[0], (int8_t)p[1], (int8_t)p[2]}; };
     // sort by (source, shift) through a packed 64-bit key (the shift code is lexicographic)
-    auto sort_entries = [](std::vector<Entry>& v) {
-        thread_local std::vector<int64_t> key;   // reused: no allocation per list
-        key.resize(v.size());
-        bool ordered = true;   // strictly increasing: already sorted, no duplicates
-        for (size_t i = 0; i < v.size(); ++i) {
-            key[i] = ((int64_t)v[i].src << 8) | ((v[i].sx + 1) * 9 + (v[i].sy + 1) * 3 + (v[i].sz + 1));
-            if (i > 0 && key[i] <= key[i - 1]) ordered = false;
+    // n entries at v in place: returns the count left after removing duplicates
+    auto sort_span = [](Entry* v, size_t n) -> size_t {
+        thread_local std::vector<int64_t> sk;    // reused: no allocation per list
+        sk.resize(n);
+        bool inc = true;   // strictly increasing: already sorted, no duplicates
+        for (size_t i = 0; i < n; ++i) {
+            sk[i] = ((int64_t)v[i].src << 8) | ((v[i].sx + 1) * 9 + (v[i].sy + 1) * 3 + (v[i].sz + 1));
+            if (i > 0 && sk[i] <= sk[i - 1]) inc = false;
         }
-        if (ordered) return;
-        std::sort(key.begin(), key.end());
-        key.erase(std::unique(key.begin(), key.end()), key.end());
-        v.resize(key.size());
-        for (size_t i = 0; i < key.size(); ++i) {
-            int code = (int)(key[i] & 0xff);
-            v[i] = Entry{(int)(key[i] >> 8), (int8_t)(code / 9 - 1), (int8_t)((code / 3) % 3 - 1), (int8_t)(code % 3 - 1)};
+        if (inc) return n;
+        std::sort(sk.begin(), sk.end());
+        sk.erase(std::unique(sk.begin(), sk.end()), sk.end());
+        for (size_t i = 0; i < sk.size(); ++i) {
+            int code = (int)(sk[i] & 0xff);
+            v[i] = Entry{(int)(sk[i] >> 8), (int8_t)(code / 9 - 1), (int8_t)((code / 3) % 3 - 1), (int8_t)(code % 3 - 1)};
         }
+        return sk.size();
     };
-    std::vector<std::vector<Entry>> U(nb), V(nb), Wl(nb), X(nb);
+    auto sort_entries = [&](std::vector<Entry>& v) { v.resize(sort_span(v.data(), v.size())); };
+    std::vector<std::vector<Entry>> U(nb), V(nb), Wl(nb);
 #pragma omp parallel for schedule(dynamic, 8)
     for (int b = 0; b < nb; ++b) {
         if (t.level[b] >= 1) {
@@ -242,21 +267,43 @@ void build_lists_host(const HostTree& t, unsigned mask, HostLists& L) {
         sort_entries(U[b]);
         sort_entries(Wl[b]);
     }
-    for (int a = 0; a < nb; ++a)
-        for (const Entry& e : Wl[a]) X[e.src].push_back(Entry{a, (int8_t)-e.sx, (int8_t)-e.sy, (int8_t)-e.sz});
-    for (int b = 0; b < nb; ++b) sort_entries(X[b]);
-
     auto flatten = [nb](std::vector<std::vector<Entry>>& in, std::vector<int64_t>& off, std::vector<Entry>& out) {
         off.assign(nb + 1, 0);
         for (int b = 0; b < nb; ++b) off[b + 1] = off[b] + (int64_t)in[b].size();
-        out.clear();
-        out.reserve(off[nb]);
-        for (int b = 0; b < nb; ++b) out.insert(out.end(), in[b].begin(), in[b].end());
+        out.resize(off[nb]);
+#pragma omp parallel for schedule(static)
+        for (int b = 0; b < nb; ++b) std::copy(in[b].begin(), in[b].end(), out.begin() + off[b]);
     };
     flatten(U, L.u_off, L.u);
     flatten(V, L.v_off, L.v);
     flatten(Wl, L.w_off, L.w);
-    flatten(X, L.x_off, L.x);
+    // X lists: the W entries reversed, placed by counting (sources in increasing order), then
+    // each list put in (source, shift) order
+    L.x_off.assign(nb + 1, 0);
+    for (const Entry& e : L.w) ++L.x_off[e.src + 1];
+    for (int b = 0; b < nb; ++b) L.x_off[b + 1] += L.x_off[b];
+    L.x.resize(L.x_off[nb]);
+    {
+        std::vector<int64_t> at_x(L.x_off.begin(), L.x_off.end() - 1);
+        for (int a = 0; a < nb; ++a)
+            for (int64_t i = L.w_off[a]; i < L.w_off[a + 1]; ++i) {
+                const Entry& e = L.w[i];
+                L.x[at_x[e.src]++] = Entry{a, (int8_t)-e.sx, (int8_t)-e.sy, (int8_t)-e.sz};
+            }
+    }
+    std::vector<int64_t> xn(nb);   // entries kept per list (a W list has no duplicates, so all)
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int b = 0; b < nb; ++b)
+        xn[b] = (int64_t)sort_span(L.x.data() + L.x_off[b], (size_t)(L.x_off[b + 1] - L.x_off[b]));
+    int64_t kept = 0;
+    for (int b = 0; b < nb; ++b) {
+        const int64_t o = L.x_off[b];
+        L.x_off[b] = kept;
+        std::copy(L.x.begin() + o, L.x.begin() + o + xn[b], L.x.begin() + kept);   // moves left or stays
+        kept += xn[b];
+    }
+    L.x_off[nb] = kept;
+    L.x.resize(kept);
 }
 
 }  // namespace pk
