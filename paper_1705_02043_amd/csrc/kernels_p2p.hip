@@ -152,6 +152,11 @@ __device__ __forceinline__ double sep(double t, double s) { return t - s; }
 // cent of the pairs), measured slower.
 template <int KD, bool MIXED, int RB>
 constexpr bool kOneWaySlots = KD == 1 && MIXED && RB == 16;
+// The float32 Stokes form with 4 right-hand sides keeps its loop as it is (168 VGPRs, three
+// waves per SIMD) and adds only a one-target copy for waves without second targets, which the
+// registers allow.
+template <int KD, bool MIXED, int RB>
+constexpr bool kOneWayOne = KD == 3 && MIXED && RB == 4;
 
 template <int KD, bool MIXED, int RB>
 __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
@@ -422,6 +427,28 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
                 if (self_seg || (MIXED && a.guard_all)) by_slots(std::true_type{});
                 else by_slots(std::false_type{});
                 continue;
+            }
+            if constexpr (kOneWayOne<KD, MIXED, RB>) {
+                if (!two) {      // no second target slot in use: the one-target copy of the loop below
+                    for (int j0 = 0; j0 < cnt; j0 += 32) {
+                        const int j1 = min(cnt, j0 + 32);
+                        T part[ND];
+                        for (int c = 0; c < ND; ++c) part[c] = T(0);
+                        for (int q = j0; q < j1; ++q) {
+                            T d[ND];
+                            C sx, sy, sz;
+                            get(slot_of<RB>(q), sx, sy, sz, d);
+                            if (self_seg || a.guard_all)
+                                interact<KD, RB, true, T>(sep<MIXED>(ux[0], sx), sep<MIXED>(uy[0], sy),
+                                                          sep<MIXED>(uz[0], sz), d, part);
+                            else
+                                interact<KD, RB, false, T>(sep<MIXED>(ux[0], sx), sep<MIXED>(uy[0], sy),
+                                                           sep<MIXED>(uz[0], sz), d, part);
+                        }
+                        for (int c = 0; c < ND; ++c) acc[0][c] += (double)part[c] * inv_u;
+                    }
+                    continue;
+                }
             }
             if constexpr (MIXED) {
                 for (int j0 = 0; j0 < cnt; j0 += 32) {
