@@ -152,11 +152,12 @@ __device__ __forceinline__ double sep(double t, double s) { return t - s; }
 // cent of the pairs), measured slower.
 template <int KD, bool MIXED, int RB>
 constexpr bool kOneWaySlots = KD == 1 && MIXED && RB == 16;
-// The float32 Stokes form with 4 right-hand sides keeps its loop as it is (168 VGPRs, three
-// waves per SIMD) and adds only a one-target copy for waves without second targets, which the
-// registers allow.
+// The float32 Stokes form with 4 right-hand sides (168 VGPRs, three waves per SIMD) and the
+// float64 Stokes form with one (the leaf pass of W and L2T work; 124 VGPRs) keep their loops as
+// they are and add only a one-target copy for waves without second targets, which their
+// registers allow (the float64 4-RHS form would go from 156 to 190 VGPRs, three waves to two).
 template <int KD, bool MIXED, int RB>
-constexpr bool kOneWayOne = KD == 3 && MIXED && RB == 4;
+constexpr bool kOneWayOne = KD == 3 && ((MIXED && RB == 4) || (!MIXED && RB == 1));
 
 template <int KD, bool MIXED, int RB>
 __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
@@ -428,7 +429,21 @@ __global__ __launch_bounds__(kThreads) void k_p2p(P2PArgs a, int r0) {
                 else by_slots(std::false_type{});
                 continue;
             }
-            if constexpr (kOneWayOne<KD, MIXED, RB>) {
+            if constexpr (kOneWayOne<KD, MIXED, RB> && !MIXED) {
+                if (!two) {      // no second target slot in use: the one-target copy of the loop below
+                    for (int q = 0; q < cnt; ++q) {
+                        T d[ND];
+                        C sx, sy, sz;
+                        get(slot_of<RB>(q), sx, sy, sz, d);
+                        if (self_seg)
+                            interact<KD, RB, true, T>(ux[0] - sx, uy[0] - sy, uz[0] - sz, d, acc[0]);
+                        else
+                            interact<KD, RB, false, T>(ux[0] - sx, uy[0] - sy, uz[0] - sz, d, acc[0]);
+                    }
+                    continue;
+                }
+            }
+            if constexpr (kOneWayOne<KD, MIXED, RB> && MIXED) {
                 if (!two) {      // no second target slot in use: the one-target copy of the loop below
                     for (int j0 = 0; j0 < cnt; j0 += 32) {
                         const int j1 = min(cnt, j0 + 32);
