@@ -30,6 +30,8 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <future>
+#include <system_error>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -92,7 +94,7 @@ struct GemmRange {
 };
 
 struct SegRange {
-    int set = 0;            // 0: S2M and X items, 1: leaf items (near field, W + L2T)
+    int set = 0;            // 0: S2M items, 1: leaf items (near field, W + L2T), 2: X items
     int work0 = 0, nwork = 0;
 };
 
@@ -220,15 +222,16 @@ struct pkifmm_plan {
     PinnedBuf<uint64_t> keys_host;
     DBuf<int> tree_box, tree_out;       // per-level split boxes and their children (device tree build)
     PinnedBuf<int> tree_out_host;
-    DBuf<int64_t> v_off;
-    DBuf<int> v_targets;
-    int n_v_targets = 0;
+    // the host lists of the current points: built on a host thread that set_points starts for one
+    // large problem, so that an evaluation can enqueue its permutation, S2M and upward pass first;
+    // every reader of the lists or of their statistics waits for it (lists_wait)
+    std::shared_future<void> lists_ready;
 
     // work lists for the current R
     int R_built = -1;
     SegRange w_s2m, w_x, w_leaf_u, w_leaf_far;
-    DBuf<Seg> segs[2];                  // per SegRange set
-    DBuf<Work> work[2];
+    DBuf<Seg> segs[3];                  // per SegRange set
+    DBuf<Work> work[3];
     // U-list pairs evaluated once (one right-hand side): partial slots and, per leaf that is
     // the other side of such pairs, its slots in a fixed order
     Tuning tune;                        // the choices of the evaluation being enqueued
@@ -439,6 +442,38 @@ void build_tree_device(pkifmm_plan* P, const uint64_t* keys, int64_t n, int s_ma
         }
 }
 
+// The host lists and their statistics, once the thread that set_points started has built them;
+// rethrows what building them threw.
+void lists_wait(const pkifmm_plan* P) {
+    std::shared_future<void> f = P->lists_ready;
+    if (f.valid()) f.get();
+}
+
+// Before the points change or the plan goes: the lists thread has ended (its error, if any, is
+// dropped with the lists it was building).
+void lists_settle(pkifmm_plan* P) {
+    if (P->lists_ready.valid()) P->lists_ready.wait();
+    P->lists_ready = std::shared_future<void>();
+}
+
+// Sizes of the current lists and the number of near-field (U-list) point pairs.
+void list_stats(pkifmm_plan* P) {
+    const HostTree& t = P->tree;
+    const HostLists& L = P->lists;
+    auto& st = P->stats;
+    st.n_u = (int64_t)L.u.size();
+    st.n_v = (int64_t)L.v.size();
+    st.n_w = (int64_t)L.w.size();
+    st.n_x = (int64_t)L.x.size();
+    int64_t up = 0;
+    for (int b : t.leaves)
+        for (int64_t e = L.u_off[b]; e < L.u_off[b + 1]; ++e) {
+            const int a = L.u[e].src;
+            up += (int64_t)(t.end[b] - P->box_tbeg[b]) * (P->box_send[a] - t.begin[a]);
+        }
+    st.u_pairs = up;
+}
+
 // Work lists of one (tree, R) are built in three stages, each uploaded on the setup stream
 // into its own buffers, so that an evaluation can launch the kernels of a stage while the
 // host builds the next one.
@@ -456,16 +491,14 @@ bool far_step_d(const pkifmm_plan* P) {
 // same alone and in a batch.
 constexpr int kSplitLevels = 3;
 
-// Stage 1: S2M and X items, per-level and root GEMMs, workspace.
+// Stage 1: S2M items, per-level and root GEMMs, workspace (the tree alone: no host lists).
 void build_stage_tree(pkifmm_plan* P, int R) {
     const HostTree& t = P->tree;
-    const HostLists& L = P->lists;
     const int nb = t.nbox();
     const int ns = P->n_surf;
     std::vector<Seg> segs;
     std::vector<Work> work;
     const int kSelf = 13;
-    auto code = [](const Entry& e) { return (e.sx + 1) * 9 + (e.sy + 1) * 3 + (e.sz + 1); };
     // S2M: leaf points -> own upward check surface
     P->w_s2m = SegRange{0, (int)work.size(), 0};
     for (int b : t.leaves) {
@@ -475,20 +508,6 @@ void build_stage_tree(pkifmm_plan* P, int R) {
         for (int c0 = 0; c0 < ns; c0 += 64) work.push_back(Work{b, 2, c0, std::min(64, ns - c0), s0, s0 + 1});
     }
     P->w_s2m.nwork = (int)work.size() - P->w_s2m.work0;
-    // W/X lists take the cheaper form of the interaction: a W-list box that is a leaf with
-    // no more points than a surface acts through its points, and a leaf with no more points
-    // than a surface takes its X-list sources directly at its points
-    auto small_leaf = [&](int b) { return t.is_leaf(b) && t.end[b] - t.begin[b] <= ns; };
-    // X list: leaf points -> downward check surfaces
-    P->w_x = SegRange{0, (int)work.size(), 0};
-    for (int b = 0; b < nb; ++b) {
-        if (L.x_off[b + 1] == L.x_off[b] || small_leaf(b)) continue;
-        int s0 = (int)segs.size();
-        for (int64_t e = L.x_off[b]; e < L.x_off[b + 1]; ++e) segs.push_back(Seg{0, L.x[e].src, code(L.x[e])});
-        int s1 = (int)segs.size();
-        for (int c0 = 0; c0 < ns; c0 += 64) work.push_back(Work{b, 1, c0, std::min(64, ns - c0), s0, s1});
-    }
-    P->w_x.nwork = (int)work.size() - P->w_x.work0;
     hipStream_t s = P->setup_stream;
     P->segs[0].upload(segs, s);
     P->work[0].upload(work, s);
@@ -621,8 +640,36 @@ void build_stage_tree(pkifmm_plan* P, int R) {
     PK_HIP(hipStreamSynchronize(s));
 }
 
+// Stage 1b: X-list items (leaf points -> downward check surfaces), set 2.  W/X lists take the
+// cheaper form of the interaction: a W-list box that is a leaf with no more points than a
+// surface acts through its points, and a leaf with no more points than a surface takes its
+// X-list sources directly at its points (both in the near-field items).
+void build_stage_x(pkifmm_plan* P) {
+    lists_wait(P);
+    const HostTree& t = P->tree;
+    const HostLists& L = P->lists;
+    const int ns = P->n_surf;
+    std::vector<Seg> segs;
+    std::vector<Work> work;
+    auto code = [](const Entry& e) { return (e.sx + 1) * 9 + (e.sy + 1) * 3 + (e.sz + 1); };
+    auto small_leaf = [&](int b) { return t.is_leaf(b) && t.end[b] - t.begin[b] <= ns; };
+    for (int b = 0; b < t.nbox(); ++b) {
+        if (L.x_off[b + 1] == L.x_off[b] || small_leaf(b)) continue;
+        int s0 = (int)segs.size();
+        for (int64_t e = L.x_off[b]; e < L.x_off[b + 1]; ++e) segs.push_back(Seg{0, L.x[e].src, code(L.x[e])});
+        int s1 = (int)segs.size();
+        for (int c0 = 0; c0 < ns; c0 += 64) work.push_back(Work{b, 1, c0, std::min(64, ns - c0), s0, s1});
+    }
+    P->w_x = SegRange{2, 0, (int)work.size()};
+    hipStream_t s = P->setup_stream;
+    P->segs[2].upload(segs, s);
+    P->work[2].upload(work, s);
+    PK_HIP(hipStreamSynchronize(s));
+}
+
 // Stage 2: the leaf items (near field; W + L2T) and the two-way pair bookkeeping.
 void build_stage_near(pkifmm_plan* P, int R) {
+    lists_wait(P);
     const HostTree& t = P->tree;
     const HostLists& L = P->lists;
     const int nb = t.nbox();
@@ -820,6 +867,7 @@ void build_stage_near(pkifmm_plan* P, int R) {
 
 // Stage 3: M2L GEMMs grouped by offset.
 void build_stage_m2l(pkifmm_plan* P, int R) {
+    lists_wait(P);
     const HostTree& t = P->tree;
     const HostLists& L = P->lists;
     const int nb = t.nbox();
@@ -929,6 +977,7 @@ void build_stage_m2l(pkifmm_plan* P, int R) {
 
 void build_work(pkifmm_plan* P, int R) {
     build_stage_tree(P, R);
+    build_stage_x(P);
     build_stage_near(P, R);
     build_stage_m2l(P, R);
     P->R_built = R;
@@ -1237,7 +1286,9 @@ void enqueue_evaluate(pkifmm_plan* P, Workspace& w, int R, const double* density
         auto mark = [&]() { mark_on(s); };
         // first evaluation on new points: the M2L and near-field work lists are built on two
         // host threads (their own upload streams) while this thread builds the tree-pass lists
-        // and enqueues the upward pass; each is joined just before its kernels are enqueued
+        // and enqueues the upward pass; each is joined just before its kernels are enqueued.  The
+        // upward pass needs the tree alone, so it is enqueued before the host lists (still being
+        // built by the thread set_points started) are waited for.
         StageThread th_m2l, th_near;
         if (build) {
             th_m2l.start([P, R] { build_stage_m2l(P, R); });
@@ -1283,9 +1334,6 @@ void enqueue_evaluate(pkifmm_plan* P, Workspace& w, int R, const double* density
         run_p2p(P, w, P->w_s2m, nullptr, w.q_u, R, false, false, s, true);
         hipStream_t sx = P->x_stream, sn = P->near_stream;
         PK_HIP(hipEventRecord(P->ev_fork, s));
-        PK_HIP(hipStreamWaitEvent(sx, P->ev_fork, 0));
-        run_p2p(P, w, P->w_x, nullptr, w.q_x, R, false, false, sx, true);
-        PK_HIP(hipEventRecord(P->ev_xjoin, sx));
         for (int lv = t.depth; lv >= 0; --lv) {
             const bool split = lv <= kSplitLevels;
             run_gemm(P, w, P->g_m2m[lv], P->m2m.p, 0, kn, 8 * kn, w.phi_u, kn, w.q_u, kn, true, s, 8, split);
@@ -1293,6 +1341,10 @@ void enqueue_evaluate(pkifmm_plan* P, Workspace& w, int R, const double* density
             run_gemm(P, w, P->g_up2[lv], P->up_VS.p, 0, kn, P->r_up, w.tmp, kn, w.phi_u, kn, false, s, 1, split);
         }
         mark();
+        if (build) build_stage_x(P);
+        PK_HIP(hipStreamWaitEvent(sx, P->ev_fork, 0));
+        run_p2p(P, w, P->w_x, nullptr, w.q_x, R, false, false, sx, true);
+        PK_HIP(hipEventRecord(P->ev_xjoin, sx));
         // 3. root far field and V-list M2L into the downward check potentials
         th_m2l.join();                          // built while the upward pass was enqueued and ran
         bind_plan_workspace(P, w, kWsM2L);
@@ -1581,6 +1633,7 @@ int set_points_impl(pkifmm_plan* P, int n_problems, const int64_t* counts, const
     P->allocator.stream = stream;
     AllocScope scope(&P->allocator);
     try {
+        lists_settle(P);
         wait_idle(P);   // an evaluation in flight still reads the current points and lists
         P->have_points = false;
         P->R_built = -1;
@@ -1633,9 +1686,7 @@ int set_points_impl(pkifmm_plan* P, int n_problems, const int64_t* counts, const
         P->stats.close_points = P->guard_all ? 1 : 0;
         if (n_problems == 1) {
             build_tree_device(P, P->keys_b.p, n, P->cfg.max_pts_per_leaf, P->tree, s);
-            build_lists_host(P->tree, P->cfg.periodic_mask, P->lists);
-            add_root_ring(P->tree, P->cfg.periodic_mask, near_layers(P->cfg), P->lists);
-            P->box_prob.assign(P->tree.nbox(), 0);
+            P->box_prob.assign(P->tree.nbox(), 0);     // the lists follow below, on a host thread
         } else {
             std::vector<HostTree> trees(n_problems);
             std::vector<HostLists> lists(n_problems);
@@ -1671,6 +1722,22 @@ int set_points_impl(pkifmm_plan* P, int n_problems, const int64_t* counts, const
                 P->box_send[b] = P->box_tbeg[b] = t.begin[b] + P->leaf_nsrc_host.p[i];
             }
         }
+        // one problem: its interaction lists are built on a host thread from here on, beside the
+        // uploads below and the first evaluation's upward pass; every reader waits (lists_wait)
+        if (n_problems == 1) {
+            auto job = [P] {
+                build_lists_host(P->tree, P->cfg.periodic_mask, P->lists);
+                add_root_ring(P->tree, P->cfg.periodic_mask, near_layers(P->cfg), P->lists);
+                list_stats(P);
+            };
+            try {
+                P->lists_ready = std::async(std::launch::async, job).share();
+            } catch (const std::system_error&) {   // no thread to be had: build them here
+                job();
+            }
+        } else {
+            list_stats(P);
+        }
         P->b_send.upload(P->box_send, s);
         P->b_level.upload(t.level, s);
         P->b_ix.upload(t.ix, s);
@@ -1684,12 +1751,6 @@ int set_points_impl(pkifmm_plan* P, int n_problems, const int64_t* counts, const
             launch_leaf_offsets(P->xs.p, n, P->leaf_boxes.p, (int)t.leaves.size(), P->b_begin.p, P->b_end.p, P->b_level.p,
                                 P->b_ix.p, P->b_iy.p, P->b_iz.p, P->ioff.p, s);
         }
-        std::vector<int> vt;
-        for (int b = 0; b < t.nbox(); ++b)
-            if (P->lists.v_off[b + 1] > P->lists.v_off[b]) vt.push_back(b);
-        P->n_v_targets = (int)vt.size();
-        P->v_targets.upload(vt, s);
-        P->v_off.upload(P->lists.v_off, s);
         PK_HIP(hipStreamSynchronize(s));
         P->have_points = true;
         auto& st = P->stats;
@@ -1698,17 +1759,6 @@ int set_points_impl(pkifmm_plan* P, int n_problems, const int64_t* counts, const
         st.n_boxes = t.nbox();
         st.n_leaves = (int)t.leaves.size();
         st.depth = t.depth;
-        st.n_u = (int64_t)P->lists.u.size();
-        st.n_v = (int64_t)P->lists.v.size();
-        st.n_w = (int64_t)P->lists.w.size();
-        st.n_x = (int64_t)P->lists.x.size();
-        int64_t up = 0;
-        for (int b : t.leaves)
-            for (int64_t e = P->lists.u_off[b]; e < P->lists.u_off[b + 1]; ++e) {
-                int a = P->lists.u[e].src;
-                up += (int64_t)(t.end[b] - P->box_tbeg[b]) * (P->box_send[a] - t.begin[a]);
-            }
-        st.u_pairs = up;
     } catch (const Error& e) {
         return fail(P, e);
     } catch (const std::bad_alloc&) {
@@ -1928,6 +1978,13 @@ int pkifmm_autotune(pkifmm_plan* P, int R, const double* density, double* potent
 
 int pkifmm_get_stats(pkifmm_plan* P, pkifmm_stats* out) {
     if (!P || !out) return PKIFMM_ERR_INVALID_ARG;
+    try {
+        lists_wait(P);   // the list sizes
+    } catch (const Error& e) {
+        return fail(P, e);
+    } catch (const std::bad_alloc&) {
+        return fail(P, Error(PKIFMM_ERR_OOM, "host allocation"));
+    }
     if (!P->pending_events.empty()) {
         double sum[PKIFMM_NUM_PHASES] = {0};
         int cnt = 0;
@@ -1993,6 +2050,13 @@ int pkifmm_get_tree(const pkifmm_plan* P, int64_t* perm, int32_t* boxes) {
 int pkifmm_get_list(const pkifmm_plan* P, char which, int64_t* offsets, int32_t* entries) {
     if (!P || !offsets) return PKIFMM_ERR_INVALID_ARG;
     if (!P->have_points) return PKIFMM_ERR_NO_POINTS;
+    try {
+        lists_wait(P);
+    } catch (const Error& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        return PKIFMM_ERR_OOM;
+    }
     const HostLists& L = P->lists;
     const std::vector<int64_t>* off;
     const std::vector<Entry>* ent;
@@ -2017,6 +2081,7 @@ int pkifmm_get_list(const pkifmm_plan* P, char which, int64_t* offsets, int32_t*
 
 int pkifmm_plan_destroy(pkifmm_plan* P) {
     if (!P) return PKIFMM_OK;
+    lists_settle(P);
     if (P->ev_done) (void)hipEventSynchronize(P->ev_done);   // no evaluation may still read plan buffers
     for (auto& ev : P->pending_events)
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
