@@ -178,7 +178,8 @@ typedef struct {
     int64_t near_pairs;          /* point pairs of the near-field launch: U lists plus the W/X
                                     entries evaluated directly */
     int svd_rank_up, svd_rank_down;
-    double ms_set_points;        /* host wall time of the last pkifmm_set_points */
+    double ms_set_points;        /* host wall time of the last pkifmm_set_points (one problem:
+                                    without the list build it leaves running on a host thread) */
     double ms_evaluate;          /* host wall time of the last pkifmm_evaluate call (enqueue only
                                     unless a check synchronised) */
     int n_timed;                 /* evaluations averaged in ms_phase (PKIFMM_PHASE_TIMING) */
@@ -222,7 +223,11 @@ int pkifmm_plan_create(const pkifmm_config *cfg, pkifmm_plan **out);
  *            carries no density, and every leaf keeps its sources before its targets;
  *   both are copied and may be freed after the call returns.
  * Waits for the plan's last evaluation to finish (on whatever stream it ran) and
- * synchronises `stream` (the tree topology is built on the host).  In the mixed form it
+ * synchronises `stream` (the tree's box table is read back to the host).  For one problem
+ * the U/V/W/X lists are then completed on a host thread that the call starts and leaves
+ * running: pkifmm_evaluate, pkifmm_get_stats and pkifmm_get_list wait for it (and return
+ * an error raised while building them, OOM), and the next set_points and
+ * pkifmm_plan_destroy let it finish first.  A batch builds its lists in the call.  In the mixed form it
  * also looks for points of different leaves, or a point and another point's periodic
  * image, closer than 2^-27 L in every coordinate; if there are any, every near-field
  * segment guards zero separations (such points then meet as coincident points, at the
@@ -327,8 +332,10 @@ int pkifmm_autotune(pkifmm_plan *plan, int n_rhs, const double *density, double 
 
 /* Tree and list sizes of the current points and the last call timings.  With
  * PKIFMM_PHASE_TIMING this waits for the recorded events of every evaluation since
- * the previous call, reports their per-phase averages and starts a new window.
- * Errors: INVALID_ARG (NULL argument), HIP (waiting for the events). */
+ * the previous call, reports their per-phase averages and starts a new window.  Waits
+ * for the list build that pkifmm_set_points left running (the list sizes).
+ * Errors: INVALID_ARG (NULL argument), OOM (raised while building the lists), HIP
+ * (waiting for the events). */
 int pkifmm_get_stats(pkifmm_plan *plan, pkifmm_stats *out);
 
 /*
@@ -350,7 +357,9 @@ int pkifmm_get_tree(const pkifmm_plan *plan, int64_t *perm, int32_t *boxes);
  *   offsets [nbox + 1] int64 (CSR over boxes; boxes without such a list are empty)
  *   entries [offsets[nbox]][4] int32: source box, shift x, shift y, shift z
  * Call with entries = NULL to obtain offsets (and so the size) first.
- * Errors: INVALID_ARG (NULL plan or offsets, unknown `which`), NO_POINTS.
+ * Waits for the list build that pkifmm_set_points left running.
+ * Errors: INVALID_ARG (NULL plan or offsets, unknown `which`), NO_POINTS, OOM (raised
+ * while building the lists).
  */
 int pkifmm_get_list(const pkifmm_plan *plan, char which, int64_t *offsets, int32_t *entries);
 
