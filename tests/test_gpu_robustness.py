@@ -37,6 +37,7 @@ def _many_items():
         pb = W.laplace_sp_uniform(n=30000, seed=41, p=4, s=12, n_rhs=3, mask=7)
         f = okifmm.KIFMM(pb.kernel, pb.periodic_mask, pb.p, pb.s, pb.points)
         _many["pb"] = pb
+        _many["f"] = f
         _many["ref"] = np.stack([f.evaluate(d) for d in pb.density])
     return _many["pb"], _many["ref"]
 
@@ -149,3 +150,36 @@ def test_neutrality_check_is_scale_invariant(scale):
     with pytest.raises(pk.PkifmmError) as e:
         plan.evaluate(_dev(bad))
     assert e.value.status == pk.ERR_INCOMPATIBLE
+
+
+@pytest.mark.timeout(300)
+def test_list_thread_on_new_points_and_destroy():
+    """For one problem set_points leaves its U/V/W/X list build running on a host thread.
+    Points set twice in a row (the first build still running), list sizes and lists read right
+    after set_points, and plans destroyed right after set_points: the lists equal the oracle's
+    and the evaluation on the second points matches the oracle."""
+    pk = _pk()
+    pb, ref = _many_items()
+    f = _many["f"]
+    other = W.laplace_sp_uniform(n=30000, seed=44, p=4, s=12, n_rhs=1, mask=7)
+    for _ in range(3):   # destroyed while its lists may still be under construction
+        tmp = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=1)
+        tmp.set_points(_dev(other.points))
+        tmp.close()
+    plan = pk.Plan(pb.kernel, pb.periodic_mask, pb.p, pb.s, precision=1)
+    plan.set_points(_dev(other.points))
+    plan.set_points(_dev(pb.points))
+    st = plan.stats()
+    assert st["n_u"] == sum(len(v) for v in f.lists.U.values())
+    assert st["n_v"] == sum(len(v) for v in f.lists.V.values())
+    for which in "UX":
+        off, ent = plan.lists(which)
+        lref = getattr(f.lists, which)
+        for b in range(f.tree.nbox):
+            got = [(int(e[0]), (int(e[1]), int(e[2]), int(e[3]))) for e in ent[off[b]:off[b + 1]]]
+            assert got == list(lref.get(b, [])), (which, b)
+    plan.set_points(_dev(other.points))
+    plan.set_points(_dev(pb.points))   # straight into the evaluation this time
+    out = plan.evaluate(_dev(pb.density)).cpu().numpy()
+    for r in range(3):
+        assert _rel(out[r], ref[r]) < 1e-6, r
