@@ -1688,14 +1688,10 @@ int set_points_impl(pkifmm_plan* P, int n_problems, const int64_t* counts, const
             build_tree_device(P, P->keys_b.p, n, P->cfg.max_pts_per_leaf, P->tree, s);
             P->box_prob.assign(P->tree.nbox(), 0);     // the lists follow below, on a host thread
         } else {
-            std::vector<HostTree> trees(n_problems);
-            std::vector<HostLists> lists(n_problems);
-#pragma omp parallel for schedule(dynamic, 1)
-            for (int q = 0; q < n_problems; ++q) {
-                build_tree_host(keys + poff[q], poff[q + 1] - poff[q], P->cfg.max_pts_per_leaf, trees[q]);
-                build_lists_host(trees[q], P->cfg.periodic_mask, lists[q]);
-                add_root_ring(trees[q], P->cfg.periodic_mask, near_layers(P->cfg), lists[q]);
-            }
+            std::vector<HostTree> trees;
+            std::vector<HostLists> lists;
+            build_forest_host(keys, poff, P->cfg.max_pts_per_leaf, P->cfg.periodic_mask, near_layers(P->cfg), trees,
+                              lists);
             merge_forest(trees, lists, poff, P->tree, P->lists, P->box_prob);
         }
         const HostTree& t = P->tree;

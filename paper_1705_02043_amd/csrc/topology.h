@@ -49,6 +49,11 @@ struct HostLists {
 void build_tree_host(const uint64_t* sorted_keys, int64_t n, int s, HostTree& t);
 void build_lists_host(const HostTree& t, unsigned periodic_mask, HostLists& l);
 void add_root_ring(const HostTree& t, unsigned periodic_mask, int near_layers, HostLists& l);
+// The trees and lists of independent problems (problem q owns sorted_keys[poff[q], poff[q+1])),
+// several problems at a time on host threads, each as build_tree_host, build_lists_host and
+// add_root_ring make it alone.
+void build_forest_host(const uint64_t* sorted_keys, const std::vector<int64_t>& poff, int s, unsigned periodic_mask,
+                       int near_layers, std::vector<HostTree>& trees, std::vector<HostLists>& lists);
 void merge_forest(const std::vector<HostTree>& trees, const std::vector<HostLists>& lists,
                   const std::vector<int64_t>& poff, HostTree& t, HostLists& l, std::vector<int>& box_prob);
 int m2l_offset_index(int dx, int dy, int dz);   // -> 0..315

@@ -19,6 +19,7 @@
 //   X(B)  all (A, p) with (B, -p) in W(A)
 // The root has no V list; its far field is the periodic root operator.
 #include <algorithm>
+#include <exception>
 #include <cstdlib>
 #include <unordered_map>
 
@@ -374,6 +375,33 @@ void add_root_ring(const HostTree& t, unsigned mask, int layers, HostLists& L) {
     v.insert(v.end(), L.v.begin() + L.v_off[root + 1], L.v.end());
     for (size_t b = root + 1; b < L.v_off.size(); ++b) L.v_off[b] += (int64_t)ring.size();
     L.v.swap(v);
+}
+
+// One problem per host thread, the largest first (the OpenMP runtime runs the list builds'
+// own parallel loops inside this one with one thread).
+void build_forest_host(const uint64_t* sorted_keys, const std::vector<int64_t>& poff, int s, unsigned periodic_mask,
+                       int near_layers, std::vector<HostTree>& trees, std::vector<HostLists>& lists) {
+    const int np = (int)poff.size() - 1;
+    trees.assign(np, HostTree());
+    lists.assign(np, HostLists());
+    std::vector<int> order(np);
+    for (int q = 0; q < np; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return poff[a + 1] - poff[a] > poff[b + 1] - poff[b]; });
+    std::vector<std::exception_ptr> err(np);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < np; ++i) {
+        const int q = order[i];
+        try {
+            build_tree_host(sorted_keys + poff[q], poff[q + 1] - poff[q], s, trees[q]);
+            build_lists_host(trees[q], periodic_mask, lists[q]);
+            add_root_ring(trees[q], periodic_mask, near_layers, lists[q]);
+        } catch (...) {
+            err[q] = std::current_exception();
+        }
+    }
+    for (const std::exception_ptr& e : err)
+        if (e) std::rethrow_exception(e);
 }
 
 // Several independent trees as one forest: boxes renumbered level-major (all
