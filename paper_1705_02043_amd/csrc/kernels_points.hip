@@ -1,8 +1,9 @@
 // Point-wise kernels: wrap/validate/quantise/Morton keys, radix sort,
 // gathers and density permutations.  All are HBM-bound streaming kernels with
 // one point per thread and coalesced SoA accesses.
+#include <algorithm>
+
 #include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include "launch.h"
 
@@ -302,6 +303,33 @@ __global__ void k_tree_children(const uint64_t* __restrict__ keys, const int* __
     out[2 * g + 1] = lo;
 }
 
+// Segment of every key-sorted point (segment q holds the input positions [off[q], off[q+1]))
+// and the point's position in the key order.
+__global__ void k_segment_of(const uint32_t* __restrict__ idx, int64_t n, const int64_t* __restrict__ off, int n_seg,
+                             uint32_t* __restrict__ seg, uint32_t* __restrict__ pos) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int64_t v = idx[j];
+    int lo = 0, hi = n_seg;   // off[lo] <= v < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= v) lo = mid;
+        else hi = mid;
+    }
+    seg[j] = (uint32_t)lo;
+    pos[j] = (uint32_t)j;
+}
+
+__global__ void k_gather_pairs(const uint32_t* __restrict__ pos, int64_t n, const uint64_t* __restrict__ kin,
+                               const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+                               uint32_t* __restrict__ vout) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t p = pos[j];
+    kout[j] = kin[p];
+    vout[j] = vin[p];
+}
+
 __global__ void k_add_into(double* __restrict__ y, const double* __restrict__ x, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         y[i] += x[i];
@@ -343,11 +371,30 @@ void radix_sort_pairs(uint64_t* kin, uint64_t* kout, uint32_t* vin, uint32_t* vo
     if (n == 0) return;
     size_t bytes = 0;
     if (n_seg > 1) {
-        PK_HIP(rocprim::segmented_radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, (unsigned)n, (unsigned)n_seg,
-                                                   off, off + 1, 0, 63, s));
-        temp.ensure(bytes);
-        PK_HIP(rocprim::segmented_radix_sort_pairs(temp.p, bytes, kin, kout, vin, vout, (unsigned)n, (unsigned)n_seg,
-                                                   off, off + 1, 0, 63, s));
+        // one full-chip sort of every key, then a stable sort by segment: the input holds each
+        // segment contiguously, so this is each segment sorted on its own with ties in input
+        // order (a segmented sort runs one workgroup per segment, a few for the whole chip)
+        const int seg_bits = 32 - __builtin_clz((unsigned)(n_seg - 1));
+        uint32_t* nil = nullptr;
+        size_t b1 = 0, b2 = 0;
+        PK_HIP(rocprim::radix_sort_pairs(nullptr, b1, kin, kout, vin, vout, (size_t)n, 0, 63, s));
+        PK_HIP(rocprim::radix_sort_pairs(nullptr, b2, nil, nil, nil, nil, (size_t)n, 0, seg_bits, s));
+        auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+        const size_t rb = al(std::max(b1, b2)), n4 = al(sizeof(uint32_t) * n), n8 = al(sizeof(uint64_t) * n);
+        temp.ensure(rb + 5 * n4 + n8);
+        char* base = temp.p;
+        uint32_t* seg = reinterpret_cast<uint32_t*>(base + rb);
+        uint32_t* seg2 = reinterpret_cast<uint32_t*>(base + rb + n4);
+        uint32_t* pos = reinterpret_cast<uint32_t*>(base + rb + 2 * n4);
+        uint32_t* pos2 = reinterpret_cast<uint32_t*>(base + rb + 3 * n4);
+        uint32_t* vtmp = reinterpret_cast<uint32_t*>(base + rb + 4 * n4);
+        uint64_t* ktmp = reinterpret_cast<uint64_t*>(base + rb + 5 * n4);
+        PK_HIP(rocprim::radix_sort_pairs(base, b1, kin, ktmp, vin, vtmp, (size_t)n, 0, 63, s));
+        hipLaunchKernelGGL(k_segment_of, dim3(nblk(n, 256)), dim3(256), 0, s, vtmp, n, off, n_seg, seg, pos);
+        PK_HIP(hipGetLastError());
+        PK_HIP(rocprim::radix_sort_pairs(base, b2, seg, seg2, pos, pos2, (size_t)n, 0, seg_bits, s));
+        hipLaunchKernelGGL(k_gather_pairs, dim3(nblk(n, 256)), dim3(256), 0, s, pos2, n, ktmp, vtmp, kout, vout);
+        PK_HIP(hipGetLastError());
         return;
     }
     PK_HIP(rocprim::radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, (size_t)n, 0, end_bit, s));

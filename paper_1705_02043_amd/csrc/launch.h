@@ -14,7 +14,7 @@ void launch_keys(const double* xyz, int64_t n, double L, unsigned mask, uint64_t
                  uint32_t* vals, double* u, int* err, hipStream_t s);
 // Stable radix sort of (key, index) pairs on key bits [0, end_bit); temp storage is grown as
 // needed.  With n_seg > 1 each segment [off[i], off[i+1]) is sorted on its own (off: device,
-// n_seg+1; all 63 key bits).
+// n_seg+1, off[0] = 0, off[n_seg] = n; all 63 key bits), ties in input order.
 void radix_sort_pairs(uint64_t* keys_in, uint64_t* keys_out, uint32_t* vals_in, uint32_t* vals_out,
                       int64_t n, DBuf<char>& temp, hipStream_t s, int n_seg = 1, const int64_t* off = nullptr,
                       int end_bit = 63);

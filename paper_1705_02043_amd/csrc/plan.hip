@@ -364,14 +364,18 @@ void check_solve(const double* A_dev, int kn, int r, const std::vector<double>& 
 
 // in: nkb input columns per output column (K blocks), -1 for a zero block; ncols output columns
 void add_gemm(Gemm& g, int op, int M, const int* in, const int* out, const double* sc, size_t ncols, int nkb = 1) {
+    // eight input slots per column (K blocks; unused ones -1), then the column's output and
+    // scale; one tile per 64 columns and 64 rows
+    const size_t in0 = g.in.size(), col00 = g.out.size();
+    g.in.resize(in0 + 8 * ncols, -1);
+    int* gi = g.in.data() + in0;
+    for (size_t c = 0; c < ncols; ++c)
+        for (int kb = 0; kb < nkb; ++kb) gi[8 * c + kb] = in[c * nkb + kb];
+    g.out.insert(g.out.end(), out, out + ncols);
+    g.scale.insert(g.scale.end(), sc, sc + ncols);
     for (size_t c0 = 0; c0 < ncols; c0 += 64) {
-        int ncol = (int)std::min<size_t>(64, ncols - c0);
-        int col0 = (int)g.out.size();
-        for (int c = 0; c < ncol; ++c)
-            for (int kb = 0; kb < 8; ++kb) g.in.push_back(kb < nkb ? in[(c0 + c) * nkb + kb] : -1);
-        g.out.insert(g.out.end(), out + c0, out + c0 + ncol);
-        g.scale.insert(g.scale.end(), sc + c0, sc + c0 + ncol);
-        for (int r0 = 0; r0 < M; r0 += 64) g.tiles.push_back(Tile{op, col0, ncol, r0});
+        const int ncol = (int)std::min<size_t>(64, ncols - c0);
+        for (int r0 = 0; r0 < M; r0 += 64) g.tiles.push_back(Tile{op, (int)(col00 + c0), ncol, r0});
     }
 }
 
