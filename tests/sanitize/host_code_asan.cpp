@@ -1,7 +1,8 @@
 // Host code of the library under AddressSanitizer and UndefinedBehaviorSanitizer (built by
 // tests/test_sanitize_host.py with g++, no GPU code): the octree and U/V/W/X lists
 // (pkifmm_host_topology) on uniform, graded, clustered, one-point, empty and face-touching
-// inputs for every periodic mask, and the operator cache (write, read back, corrupt, truncate,
+// inputs for every periodic mask, the forest of a batch (one problem per host thread) against
+// each problem built alone, and the operator cache (write, read back, corrupt, truncate,
 // check).  Exits non-zero on any mismatch; the sanitizers abort on any memory or UB error.
 #include <algorithm>
 #include <cmath>
@@ -17,6 +18,7 @@
 
 #include "opcache.h"
 #include "pkifmm.h"
+#include "topology.h"
 
 namespace {
 
@@ -89,6 +91,46 @@ std::vector<uint64_t> sorted_keys(const std::vector<double>& xyz) {
     return k;
 }
 
+// A batch's forest (build_forest_host: several problems at a time on host threads, largest
+// first) against every problem built alone: the same boxes and the same lists.
+void forest(const std::vector<std::vector<uint64_t>>& probs, int s) {
+    std::vector<uint64_t> keys;
+    std::vector<int64_t> poff{0};
+    for (const auto& p : probs) {
+        keys.insert(keys.end(), p.begin(), p.end());
+        poff.push_back(poff.back() + (int64_t)p.size());
+    }
+    for (unsigned mask : {0u, 1u, 3u, 7u}) {
+        const int layers = mask == 7u ? 2 : 1;
+        std::vector<pk::HostTree> trees;
+        std::vector<pk::HostLists> lists;
+        pk::build_forest_host(keys.data(), poff, s, mask, layers, trees, lists);
+        if (trees.size() != probs.size() || lists.size() != probs.size()) {
+            std::printf("forest mask %u: %zu problems\n", mask, trees.size());
+            ++fails;
+            continue;
+        }
+        for (size_t q = 0; q < probs.size(); ++q) {
+            pk::HostTree t;
+            pk::HostLists L;
+            pk::build_tree_host(keys.data() + poff[q], poff[q + 1] - poff[q], s, t);
+            pk::build_lists_host(t, mask, L);
+            pk::add_root_ring(t, mask, layers, L);
+            const pk::HostTree& f = trees[q];
+            const pk::HostLists& g = lists[q];
+            const bool same = t.level == f.level && t.ix == f.ix && t.iy == f.iy && t.iz == f.iz &&
+                              t.begin == f.begin && t.end == f.end && t.parent == f.parent && t.child == f.child &&
+                              t.leaves == f.leaves && t.level_start == f.level_start && t.depth == f.depth &&
+                              L.u_off == g.u_off && L.v_off == g.v_off && L.w_off == g.w_off && L.x_off == g.x_off &&
+                              L.u == g.u && L.v == g.v && L.w == g.w && L.x == g.x;
+            if (!same) {
+                std::printf("forest mask %u: problem %zu differs from its own build\n", mask, q);
+                ++fails;
+            }
+        }
+    }
+}
+
 void cache() {
     const std::string dir = "asan_cache_dir";
     std::string cmd = "mkdir -p " + dir;
@@ -157,6 +199,17 @@ int main() {
     topology(same, 8, "coincident");
     topology(std::vector<uint64_t>{key_of(0.5, 0.5, 0.5)}, 1, "one point");
     topology(std::vector<uint64_t>{}, 10, "empty");
+    {   // a batch: uniform, graded, empty, one point, coincident, uniform again (sizes unordered)
+        std::vector<std::vector<uint64_t>> probs;
+        for (int n : {3000, 0, 1, 800}) {
+            std::vector<double> p;
+            for (int i = 0; i < 3 * n; ++i) p.push_back(n == 800 ? std::pow(u(rng), 3.0) : u(rng));
+            probs.push_back(sorted_keys(p));
+        }
+        probs.push_back(same);
+        probs.push_back(sorted_keys(xyz));      // the faces set
+        forest(probs, 24);
+    }
     int64_t nb = 0;
     if (pkifmm_host_topology(nullptr, 5, 10, 0, 'U', &nb, nullptr, nullptr, nullptr) != PKIFMM_ERR_INVALID_ARG) ++fails;
     std::vector<uint64_t> k1{1, 2, 3};
