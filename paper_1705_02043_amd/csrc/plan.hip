@@ -222,9 +222,9 @@ struct pkifmm_plan {
     PinnedBuf<uint64_t> keys_host;
     DBuf<int> tree_box, tree_out;       // per-level split boxes and their children (device tree build)
     PinnedBuf<int> tree_out_host;
-    // the host lists of the current points: built on a host thread that set_points starts for one
-    // large problem, so that an evaluation can enqueue its permutation, S2M and upward pass first;
-    // every reader of the lists or of their statistics waits for it (lists_wait)
+    // the host lists of the current points: for one problem built on a host thread that
+    // set_points starts, so that an evaluation can enqueue its permutation, S2M and upward pass
+    // first; every reader of the lists or of their statistics waits for it (lists_wait)
     std::shared_future<void> lists_ready;
 
     // work lists for the current R
